@@ -1,0 +1,152 @@
+"""CPU oracle for the frontier engine -- TEST INFRASTRUCTURE ONLY.
+
+Plain single-threaded C (``oracle.c``, built with gcc into ``liboracle.so``)
+behind a ctypes wrapper.  Only the test-suite, the smoke check and the
+benchmark's ``cpu_baseline`` leg may import this package; the product path
+(the ``paper_1501_05387_amd`` package and its HIP library) never does, and the
+two share no code.
+
+Every function follows a textbook definition named in the paper:
+
+* ``bfs``       hop distance from a source (Sec. 5.1), FIFO-queue BFS.
+* ``sssp``      non-negative-weight shortest paths (Sec. 4.1, Sec. 5.2), Dijkstra.
+* ``bc``        Brandes' two-pass betweenness (Sec. 5.3), FP64.
+* ``cc``        component labels (Sec. 5.4), union-find, label = min vertex id.
+* ``pagerank``  FP64 power iteration (Sec. 5.5), uniform dangling redistribution.
+
+All five are pinned against brute force, closed forms, library routines and
+invariants in ``tests/test_oracle_pins.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+SSSP_UNREACHED = np.uint32(0xFFFFFFFF)
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (single-threaded, -O2)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Oracle:
+    """The oracle bound to one compiled library (the default one, or a test build)."""
+
+    def __init__(self, libpath: str):
+        lib = ctypes.CDLL(libpath)
+        vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        lib.or_bfs.restype = i64
+        lib.or_bfs.argtypes = [i32, vp, vp, i32, vp]
+        lib.or_sssp.restype = i64
+        lib.or_sssp.argtypes = [i32, vp, vp, vp, i32, vp]
+        lib.or_bc.restype = i32
+        lib.or_bc.argtypes = [i32, vp, vp, vp, i32, vp]
+        lib.or_cc.restype = i32
+        lib.or_cc.argtypes = [i32, vp, vp, vp]
+        lib.or_pagerank.restype = i32
+        lib.or_pagerank.argtypes = [i32, vp, vp, f64, f64, i32, vp, vp, vp]
+        self.lib = lib
+        self.path = libpath
+
+    def bfs(self, row, col, src: int) -> np.ndarray:
+        """int32 hop depths from ``src``; unreached vertices get -1."""
+        row, col = _c(row, np.int32), _c(col, np.int32)
+        n = row.size - 1
+        depth = np.empty(n, np.int32)
+        if self.lib.or_bfs(n, _p(row), _p(col), int(src), _p(depth)) < 0:
+            raise ValueError("oracle.bfs: bad input")
+        return depth
+
+    def sssp(self, row, col, w, src: int) -> np.ndarray:
+        """uint32 shortest distances from ``src``; unreached vertices get 0xFFFFFFFF."""
+        row, col, w = _c(row, np.int32), _c(col, np.int32), _c(w, np.uint32)
+        n = row.size - 1
+        dist = np.empty(n, np.uint32)
+        rc = self.lib.or_sssp(n, _p(row), _p(col), _p(w), int(src), _p(dist))
+        if rc == -2:
+            raise OverflowError("oracle.sssp: a distance does not fit in uint32")
+        if rc < 0:
+            raise ValueError("oracle.sssp: bad input")
+        return dist
+
+    def bc(self, row, col, sources) -> np.ndarray:
+        """FP64 betweenness summed over ``sources`` (unnormalised, ordered pairs)."""
+        row, col = _c(row, np.int32), _c(col, np.int32)
+        src = _c(sources, np.int32)
+        n = row.size - 1
+        out = np.empty(n, np.float64)
+        if self.lib.or_bc(n, _p(row), _p(col), _p(src), src.size, _p(out)) != 0:
+            raise ValueError("oracle.bc: bad input (sources out of range or duplicated)")
+        return out
+
+    def cc(self, row, col):
+        """(int32 labels = min vertex id per component, number of components)."""
+        row, col = _c(row, np.int32), _c(col, np.int32)
+        n = row.size - 1
+        label = np.empty(n, np.int32)
+        k = self.lib.or_cc(n, _p(row), _p(col), _p(label))
+        if k < 0:
+            raise ValueError("oracle.cc: bad input")
+        return label, int(k)
+
+    def pagerank(self, row, col, damping: float = 0.85, tol: float = 1e-6, max_iter: int = 1000):
+        """(FP64 ranks, iterations run, last L1 change).  ``tol <= 0`` runs exactly max_iter."""
+        row, col = _c(row, np.int32), _c(col, np.int32)
+        n = row.size - 1
+        x = np.empty(n, np.float64)
+        it = ctypes.c_int32(0)
+        l1 = ctypes.c_double(0.0)
+        if self.lib.or_pagerank(n, _p(row), _p(col), float(damping), float(tol), int(max_iter),
+                                _p(x), ctypes.addressof(it), ctypes.addressof(l1)) != 0:
+            raise ValueError("oracle.pagerank: bad input")
+        return x, int(it.value), float(l1.value)
+
+
+_default = None
+
+
+def default() -> Oracle:
+    global _default
+    if _default is None:
+        _default = Oracle(build())
+    return _default
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _p(a: np.ndarray) -> int:
+    return a.ctypes.data if a.size else ctypes.addressof(ctypes.c_int64(0))
+
+
+def bfs(row, col, src: int) -> np.ndarray:
+    return default().bfs(row, col, src)
+
+
+def sssp(row, col, w, src: int) -> np.ndarray:
+    return default().sssp(row, col, w, src)
+
+
+def bc(row, col, sources) -> np.ndarray:
+    return default().bc(row, col, sources)
+
+
+def cc(row, col):
+    return default().cc(row, col)
+
+
+def pagerank(row, col, damping: float = 0.85, tol: float = 1e-6, max_iter: int = 1000):
+    return default().pagerank(row, col, damping, tol, max_iter)

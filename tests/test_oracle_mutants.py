@@ -1,0 +1,69 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case below copies ``oracle/oracle.c``, plants one mistake of the kind a
+reader might make (a dropped term, a wrong sign or index, a missing case),
+compiles the copy into a temporary library and runs the pins of
+``test_oracle_pins.py`` against it.  The test passes only if some pin fails.
+The real oracle is never modified.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+ORACLE_C = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+# (name, exact source text, replacement)
+MUTANTS = [
+    ("bfs_depth_from_parent_plus_two", "depth[v] = depth[u] + 1;\n                queue",
+     "depth[v] = depth[u] + 2;\n                queue"),
+    ("bfs_lifo_instead_of_fifo", "int32_t u = queue[head++];\n        for (int32_t e = R[u]; e < R[u + 1]; ++e) {\n            int32_t v = C[e];\n            if (depth[v] < 0)",
+     "int32_t u = queue[--tail];\n        for (int32_t e = R[u]; e < R[u + 1]; ++e) {\n            int32_t v = C[e];\n            if (depth[v] < 0)"),
+    ("sssp_ignores_weights", "uint64_t nd = d[u] + (uint64_t)W[e];", "uint64_t nd = d[u] + 1;"),
+    ("sssp_weight_of_wrong_edge", "uint64_t nd = d[u] + (uint64_t)W[e];",
+     "uint64_t nd = d[u] + (uint64_t)W[R[u]];"),
+    ("sssp_heap_sifts_wrong_way", "if (h[p].d <= x.d) break;", "if (h[p].d >= x.d) break;"),
+    ("sssp_relax_without_test", "if (nd < d[v]) {\n                d[v] = nd;", "if (1) {\n                d[v] = nd;"),
+    ("bc_drops_the_one", "(1.0 + delta[w])", "(delta[w])"),
+    ("bc_inverted_ratio", "sigma[v] / sigma[w] *", "sigma[w] / sigma[v] *"),
+    ("bc_counts_source", "if (w != s) bc[w] += delta[w];", "bc[w] += delta[w];"),
+    ("bc_sigma_from_any_neighbour", "if (depth[v] == depth[u] + 1) sigma[v] += sigma[u];",
+     "if (depth[v] != depth[u]) sigma[v] += sigma[u];"),
+    ("cc_larger_root_wins", "if (a < b) label[b] = a;\n            else if (b < a) label[a] = b;",
+     "if (a < b) label[a] = b;\n            else if (b < a) label[b] = a;"),
+    ("cc_no_final_find", "label[v] = uf_find(label, v);\n        if", "(void)0;\n        if"),
+    ("pr_drops_dangling", "damping * (s + dangling / N)", "damping * (s)"),
+    ("pr_teleport_not_divided", "(1.0 - damping) / N + damping", "(1.0 - damping) + damping"),
+    ("pr_divides_by_own_degree", "s += x[u] / (double)(R[u + 1] - R[u]);",
+     "s += x[u] / (double)(R[v + 1] - R[v]);"),
+    ("pr_stops_one_late", "if (tol > 0.0 && l1 < tol) break;", "if (tol > 0.0 && l1 < tol * 0.1) break;"),
+]
+
+
+def _build_mutant(tmp_path, name, old, new):
+    src = open(ORACLE_C).read()
+    assert src.count(old) == 1, "mutation anchor for %s not unique/absent" % name
+    mut = tmp_path / (name + ".c")
+    mut.write_text(src.replace(old, new))
+    lib = tmp_path / (name + ".so")
+    subprocess.check_call(["gcc", "-O1", "-fPIC", "-shared", "-std=c11", "-o", str(lib), str(mut), "-lm"])
+    return oracle.Oracle(str(lib))
+
+
+def _all_pins(O):
+    pins.pin_exhaustive(O, nmax=5)
+    pins.pin_closed_forms(O)
+    pins.pin_scipy(O)
+    pins.pin_invariants(O)
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_mutant(tmp_path, name, old, new):
+    O = _build_mutant(tmp_path, name, old, new)
+    with pytest.raises((AssertionError, ValueError, OverflowError)):
+        _all_pins(O)

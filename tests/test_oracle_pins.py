@@ -1,0 +1,230 @@
+"""Pins for the CPU oracle: every check here comes from somewhere other than the
+oracle itself -- brute force on tiny graphs, closed forms, scipy's graph
+routines, dense linear algebra and invariants that any correct answer obeys.
+
+The pins are written as functions of an oracle object so that
+``test_oracle_mutants.py`` can run them against deliberately broken builds of
+the oracle and show that each plausible mistake is caught.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.csgraph as csg
+
+import graphgen
+from tests import brute
+from tests import invariants as inv
+
+
+# --------------------------------------------------------------- helpers ----
+def _csr_matrix(row, col, data=None):
+    n = row.size - 1
+    if data is None:
+        data = np.ones(col.size)
+    return sp.csr_matrix((np.asarray(data, float), col, row), shape=(n, n))
+
+
+def _path(n):
+    return graphgen.from_edges(n, np.arange(n - 1), np.arange(1, n))
+
+
+def _star(n):
+    return graphgen.from_edges(n, np.zeros(n - 1, np.int32), np.arange(1, n))
+
+
+def _complete(n):
+    iu = np.triu_indices(n, 1)
+    return graphgen.from_edges(n, iu[0], iu[1])
+
+
+def _lattice(side):
+    """Undropped side x side lattice (no long edges), built from an explicit edge list."""
+    eu, ev = [], []
+    for r in range(side):
+        for c in range(side):
+            v = r * side + c
+            if c + 1 < side:
+                eu.append(v); ev.append(v + 1)
+            if r + 1 < side:
+                eu.append(v); ev.append(v + side)
+    return graphgen.from_edges(side * side, eu, ev)
+
+
+# ------------------------------------------------------ exhaustive pins ----
+def pin_exhaustive(O, nmax=5, seed=0):
+    """All labelled simple graphs on 1..nmax vertices vs Floyd-Warshall,
+    walk-count path numbers, Freeman BC and a dense PageRank solve."""
+    rng = np.random.default_rng(seed)
+    for n in range(1, nmax + 1):
+        for A in brute.all_simple_graphs(n):
+            row, col, _ = brute.csr_from_adj(A)
+            D = brute.floyd_warshall(A)
+            # BFS from every source = unit-weight shortest hop counts
+            for s in range(n):
+                want = np.where(np.isfinite(D[s]), D[s], -1).astype(np.int32)
+                got = O.bfs(row, col, s)
+                assert np.array_equal(got, want), (n, A.tolist(), s)
+            # SSSP with random symmetric weights
+            Wm = np.triu(rng.integers(1, 10, size=(n, n)), 1)
+            Wm = (Wm + Wm.T) * A
+            rowW, colW, wW = brute.csr_from_adj(Wm)
+            DW = brute.floyd_warshall(Wm)
+            for s in range(n):
+                want = np.where(np.isfinite(DW[s]), DW[s], 0xFFFFFFFF).astype(np.uint32)
+                assert np.array_equal(O.sssp(rowW, colW, wW, s), want), (n, Wm.tolist(), s)
+            # CC labels = smallest reachable id
+            lab, k = O.cc(row, col)
+            want = brute.component_min_labels(D)
+            assert np.array_equal(lab, want)
+            assert k == len(set(want.tolist()))
+            # BC over all sources and over a random subset
+            assert np.allclose(O.bc(row, col, np.arange(n)), brute.freeman_bc(A, range(n)),
+                               rtol=1e-12, atol=1e-12)
+            S = rng.permutation(n)[: max(1, n // 2)]
+            assert np.allclose(O.bc(row, col, S), brute.freeman_bc(A, S), rtol=1e-12, atol=1e-12)
+            # PageRank to a tight tolerance vs the fixed point
+            x, it, l1 = O.pagerank(row, col, 0.85, 1e-15, 10000)
+            assert np.allclose(x, brute.pagerank_solve(A, 0.85), rtol=0, atol=1e-13)
+
+
+def test_exhaustive_small_graphs(orc):
+    pin_exhaustive(orc)
+
+
+# -------------------------------------------------------- closed forms ----
+def pin_closed_forms(O):
+    n = 33
+    row, col = _path(n)
+    for s in (0, 7, n - 1):
+        assert np.array_equal(O.bfs(row, col, s), np.abs(np.arange(n) - s))
+    i = np.arange(n)
+    assert np.allclose(O.bc(row, col, np.arange(n)), 2.0 * i * (n - 1 - i))
+
+    row, col = _star(n)
+    d = O.bfs(row, col, 0)
+    assert d[0] == 0 and np.all(d[1:] == 1)
+    bcv = O.bc(row, col, np.arange(n))
+    assert bcv[0] == (n - 1) * (n - 2) and np.all(bcv[1:] == 0)
+    # star K_{1,k}: the centre c and each leaf l satisfy
+    #   c = (1-d)/N + d*k*l,   l = (1-d)/N + d*c/k
+    k = n - 1
+    dd = 0.85
+    A2 = np.array([[1.0, -dd * k], [-dd / k, 1.0]])
+    c_, l_ = np.linalg.solve(A2, [(1 - dd) / n, (1 - dd) / n])
+    x, _, _ = O.pagerank(row, col, dd, 1e-15, 10000)
+    assert abs(x[0] - c_) < 1e-14 and np.allclose(x[1:], l_, atol=1e-14)
+
+    row, col = _complete(9)
+    assert np.all(O.bc(row, col, np.arange(9)) == 0)
+    x, _, _ = O.pagerank(row, col, 0.85, 1e-15, 10000)
+    assert np.allclose(x, 1.0 / 9, atol=1e-15)          # regular graph
+
+    side = 17
+    row, col = _lattice(side)
+    rr, cc = np.divmod(np.arange(side * side), side)
+    for s in (0, 5 * side + 9):
+        man = np.abs(rr - rr[s]) + np.abs(cc - cc[s])
+        assert np.array_equal(O.bfs(row, col, s), man)
+        w1 = np.ones(col.size, np.uint32)
+        assert np.array_equal(O.sssp(row, col, w1, s), man.astype(np.uint32))
+        w3 = np.full(col.size, 3, np.uint32)
+        assert np.array_equal(O.sssp(row, col, w3, s), 3 * man.astype(np.uint32))
+    lab, k = O.cc(row, col)
+    assert k == 1 and np.all(lab == 0)
+
+
+def test_closed_forms(orc):
+    pin_closed_forms(orc)
+
+
+# ------------------------------------------------- scipy cross-checks ----
+def _random_graph(rng, n, p):
+    A = np.triu(rng.random((n, n)) < p, 1)
+    iu = np.nonzero(A)
+    return graphgen.from_edges(n, iu[0], iu[1])
+
+
+def pin_scipy(O, seed=1):
+    rng = np.random.default_rng(seed)
+    cases = [_random_graph(rng, n, p) for n, p in ((50, 0.05), (120, 0.02), (200, 0.01), (200, 0.04))]
+    cases.append(graphgen.rmat(10, 8, seed=5))
+    for row, col in cases:
+        n = row.size - 1
+        w = graphgen.weights(row, col, 64, seed=9)
+        M1 = _csr_matrix(row, col)
+        MW = _csr_matrix(row, col, w)
+        srcs = rng.choice(n, size=4, replace=False)
+        Dh = csg.shortest_path(M1, directed=False, unweighted=True, indices=srcs)
+        Dw = csg.dijkstra(MW, directed=False, indices=srcs)
+        for i, s in enumerate(srcs):
+            want = np.where(np.isfinite(Dh[i]), Dh[i], -1).astype(np.int32)
+            assert np.array_equal(O.bfs(row, col, s), want)
+            want = np.where(np.isfinite(Dw[i]), Dw[i], 0xFFFFFFFF).astype(np.uint32)
+            assert np.array_equal(O.sssp(row, col, w, s), want)
+        k_sp, lab_sp = csg.connected_components(M1, directed=False)
+        lab, k = O.cc(row, col)
+        assert k == k_sp
+        # same partition, and each label is the minimum id of its part
+        mins = np.full(k_sp, n, np.int64)
+        np.minimum.at(mins, lab_sp, np.arange(n))
+        assert np.array_equal(lab, mins[lab_sp])
+
+
+def test_scipy_crosscheck(orc):
+    pin_scipy(orc)
+
+
+# --------------------------------------------- invariants at mid size ----
+def pin_invariants(O):
+    row, col = graphgen.rmat(14)
+    n = row.size - 1
+    w = graphgen.weights(row, col, 64)
+    srcs = graphgen.sample_sources(row, col, 4)
+    depths = []
+    for s in srcs:
+        d = O.bfs(row, col, s)
+        inv.check_bfs(row, col, s, d)
+        depths.append(d)
+        dist = O.sssp(row, col, w, s)
+        inv.check_sssp(row, col, w, s, dist)
+        assert np.array_equal(dist != 0xFFFFFFFF, d >= 0)
+        # unit weights turn SSSP into BFS
+        assert np.array_equal(O.sssp(row, col, np.ones_like(w), s).astype(np.int64),
+                              np.where(d >= 0, d.astype(np.int64), 0xFFFFFFFF))
+    lab, k = O.cc(row, col)
+    assert inv.check_cc(row, col, lab) == k
+    bcv = O.bc(row, col, srcs)
+    assert np.all(bcv >= 0)
+    ident = inv.bc_pair_identity(depths)
+    assert abs(bcv.sum() - ident) <= 1e-9 * max(1.0, ident)
+    x, it, l1 = O.pagerank(row, col, 0.85, 1e-6, 1000)
+    assert abs(x.sum() - 1.0) < 1e-12 and np.all(x > 0)
+    assert l1 < 1e-6
+    # contraction: ||x_k - x*|| <= d/(1-d) ||x_k - x_{k-1}||
+    xs, _, _ = O.pagerank(row, col, 0.85, 1e-15, 10000)
+    assert np.abs(x - xs).sum() <= 0.85 / 0.15 * l1 * (1 + 1e-9)
+    # running exactly k-1 then k iterations reproduces the reported L1 change
+    xa, ka, l1a = O.pagerank(row, col, 0.85, 0.0, it - 1)
+    assert l1a >= 1e-6, "the stop rule must fire at the first iteration below tol"
+    xb, kb, l1b = O.pagerank(row, col, 0.85, 0.0, it)
+    assert ka == it - 1 and kb == it
+    assert np.array_equal(xb, x) and abs(np.abs(xb - xa).sum() - l1) < 1e-18
+
+
+def test_invariants_rmat(orc):
+    pin_invariants(orc)
+
+
+def test_input_validation(orc):
+    row, col = _path(5)
+    with pytest.raises(ValueError):
+        orc.bfs(row, col, 5)
+    with pytest.raises(ValueError):
+        orc.bc(row, col, [1, 1])
+    with pytest.raises(ValueError):
+        orc.pagerank(row, col, 1.0)
+    w = np.full(col.size, 0x7FFFFFFF, np.uint32)
+    with pytest.raises(OverflowError):
+        orc.sssp(row, col, w, 0)
