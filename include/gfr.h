@@ -1,0 +1,228 @@
+/*
+ * gfr.h -- C ABI of the MI355X frontier graph engine.
+ *
+ * The engine implements the data-centric frontier model of Gunrock
+ * (Wang et al., "Gunrock: A High-Performance Graph Processing Library on the
+ * GPU", PPoPP'16): an *advance* operator that expands every frontier vertex's
+ * CSR neighbour list under load balancing (Sec. 4.1, Sec. 4.4) and a *filter*
+ * operator that culls and deduplicates the result (Sec. 4.1, Sec. 4.5), driving
+ * BFS, SSSP, BC, CC and PageRank (Sec. 5).  All kernels are HIP for gfx950.
+ *
+ * General conventions
+ *   - Every call returns a gfr_status; nothing throws across the ABI.
+ *   - A failed call leaves its output buffers unspecified unless stated
+ *     otherwise and records a message readable with gfr_last_error().
+ *   - Output buffers are caller-owned and may be host memory or device memory
+ *     (for example a torch tensor's data_ptr on the context's device); the
+ *     library detects which.  Device outputs avoid the PCIe copy.
+ *   - Calls are synchronous: results are complete when the call returns and
+ *     the library keeps no reference to caller buffers (except the serving
+ *     calls, which lend `out` until the ticket completes).
+ *   - `stream` is a hipStream_t of the context's device, or NULL for the
+ *     context's own stream.  Work is enqueued on it and waited for.
+ *   - One context may be used from several host threads; calls on one context
+ *     are serialised internally.
+ */
+#ifndef GFR_H
+#define GFR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gfr_status;
+#define GFR_OK            0
+#define GFR_E_INVALID    -1 /* bad argument, bad graph, unusable input           */
+#define GFR_E_OOM        -2 /* device or host allocation failed                    */
+#define GFR_E_DEVICE     -3 /* HIP error or device-side watchdog                   */
+#define GFR_E_NOT_FOUND  -4 /* unknown graph handle or ticket                      */
+#define GFR_E_NOT_READY  -5 /* ticket not finished                                 */
+#define GFR_E_CAPACITY   -6 /* request larger than the admission budget            */
+
+typedef struct gfr_ctx gfr_ctx;   /* opaque, owned by the library                   */
+typedef int64_t gfr_graph;        /* handle of a resident graph; 0 is never valid   */
+typedef int64_t gfr_ticket;       /* handle of a served query; 0 is never valid     */
+typedef void *gfr_stream;         /* hipStream_t or NULL                            */
+
+/* flags of gfr_graph_load_csr / gfr_validate_csr */
+#define GFR_VALIDATE      1u  /* also reject asymmetric graphs, self loops, duplicate or unsorted columns */
+
+/* ---------------------------------------------------------------- context */
+/*
+ * Create a context on HIP device `device`.  `tuning_json` may be NULL or a
+ * JSON object of option overrides (see gfr_set_option for the keys).
+ * On success *out receives the context.  GFR_E_DEVICE if the device is
+ * missing or not gfx950.
+ */
+gfr_status gfr_ctx_create(int32_t device, const char *tuning_json, gfr_ctx **out);
+
+/* Destroy a context and free every graph and buffer it owns. NULL is a no-op. */
+gfr_status gfr_ctx_destroy(gfr_ctx *ctx);
+
+/* Message of the last failed call on this context (valid until the next call). */
+const char *gfr_last_error(const gfr_ctx *ctx);
+
+/*
+ * Set a numeric option of the context.  Keys:
+ *   "bfs.direction"   0 auto (per-level push/pull choice, Sec. 4.5), 1 push only, 2 pull only
+ *   "bfs.alpha"       push->pull when frontier edges > unvisited edges / alpha
+ *   "bfs.beta"        pull->push when frontier vertices < n / beta
+ *   "bfs.dedup"       0 atomic claim (each vertex enqueued once), 1 idempotent (Sec. 4.5)
+ *   "sssp.delta"      bucket width of the near/far priority queue (Sec. 4.5); 0 = automatic
+ *   "advance.chunk"   edges per work-group chunk of the load-balanced advance (Sec. 4.4),
+ *                     one of 256, 512, 1024, 2048, 4096
+ *   "lb.threshold"    frontier size below which the advance balances over vertices
+ *                     instead of edges (Sec. 4.4; the paper uses 4096)
+ * GFR_E_INVALID for an unknown key or an out-of-range value.
+ */
+gfr_status gfr_set_option(gfr_ctx *ctx, const char *key, double value);
+gfr_status gfr_get_option(gfr_ctx *ctx, const char *key, double *value);
+
+/*
+ * Statistics of the last solve on this context: "levels", "push_levels",
+ * "pull_levels", "edges_inspected", "iterations", "relaxations", "kernel_ms".
+ */
+gfr_status gfr_get_stat(gfr_ctx *ctx, const char *key, double *value);
+
+/*
+ * Host-only structural check of a CSR graph (no device work).  Checks what
+ * gfr_graph_load_csr checks; with GFR_VALIDATE also symmetry, self loops and
+ * sorted duplicate-free rows.  Writes a reason into msg (NUL terminated, at
+ * most msg_cap bytes) when the graph is rejected.  Returns GFR_OK or
+ * GFR_E_INVALID.
+ */
+gfr_status gfr_validate_csr(int32_t n, int64_t m, const int32_t *row_offsets,
+                            const int32_t *col_idx, const uint32_t *weights, uint32_t flags,
+                            char *msg, int32_t msg_cap);
+
+/* ------------------------------------------------------------------ graphs */
+/*
+ * Make a CSR graph resident on the device (Sec. 3: row offsets R[n+1] and
+ * column indices C[m]; per-edge weights W[m] for SSSP, Sec. 5.2).  The graph
+ * must be undirected, i.e. stored symmetrically, as every graph the paper
+ * evaluates is (Sec. 6).  The arrays are host memory and are copied; the
+ * caller may free them on return.  `weights` may be NULL (SSSP then fails).
+ * Rejected with GFR_E_INVALID: n <= 0, m < 0, m >= 2^31, R[0] != 0,
+ * R[n] != m, decreasing offsets, column ids outside [0,n); with GFR_VALIDATE
+ * also the symmetric/simple checks of gfr_validate_csr.
+ * On success *out receives a handle owned by the context.
+ */
+gfr_status gfr_graph_load_csr(gfr_ctx *ctx, int32_t n, int64_t m, const int32_t *row_offsets,
+                              const int32_t *col_idx, const uint32_t *weights, uint32_t flags,
+                              gfr_graph *out);
+
+/* Release a resident graph.  GFR_E_NOT_FOUND for an unknown handle. */
+gfr_status gfr_graph_free(gfr_ctx *ctx, gfr_graph g);
+
+/* Vertex count, entry count and device bytes held by the graph (any may be NULL). */
+gfr_status gfr_graph_info(gfr_ctx *ctx, gfr_graph g, int32_t *n, int64_t *m,
+                          uint64_t *device_bytes);
+
+/* -------------------------------------------------------------- primitives */
+/*
+ * Breadth-first search (Sec. 5.1): depth_out[v] = hop distance from `source`,
+ * depth_out[source] = 0, unreached vertices -1.  n int32 elements.
+ * Level-synchronous advance + filter with a per-level push/pull choice.
+ * GFR_E_INVALID if source is outside [0,n).
+ */
+gfr_status gfr_bfs(gfr_ctx *ctx, gfr_graph g, int32_t source, int32_t *depth_out,
+                   gfr_stream stream);
+
+/*
+ * Single-source shortest paths with non-negative integer weights
+ * (Sec. 4.1 Algorithm 1, Sec. 5.2): dist_out[v] = minimum path weight,
+ * dist_out[source] = 0, unreached 0xFFFFFFFF.  n uint32 elements.
+ * Near/far priority-queue split (Sec. 4.5).  GFR_E_INVALID if the graph has
+ * no weights, the source is out of range, or a distance would not fit below
+ * 0xFFFFFFFF.
+ */
+gfr_status gfr_sssp(gfr_ctx *ctx, gfr_graph g, int32_t source, uint32_t *dist_out,
+                    gfr_stream stream);
+
+/*
+ * Betweenness centrality restricted to k sources (Sec. 5.3, Brandes'
+ * two-pass formulation): bc_out[v] = sum over s in sources, s != v, of the
+ * dependency delta_s(v); unnormalised, summed over ordered pairs, not halved.
+ * Shortest-path counts are FP64, dependencies FP32.  `sources` is host
+ * memory (k distinct ids in range, else GFR_E_INVALID).  n float elements.
+ */
+gfr_status gfr_bc(gfr_ctx *ctx, gfr_graph g, const int32_t *sources, int32_t k, float *bc_out,
+                  gfr_stream stream);
+
+/*
+ * Connected components (Sec. 5.4): label_out[v] = smallest vertex id of v's
+ * component (n int32 elements); *num_components_out (host pointer, may be
+ * NULL) = number of components.  Hooking over an edge frontier that is
+ * filtered each round, then pointer jumping.
+ */
+gfr_status gfr_cc(gfr_ctx *ctx, gfr_graph g, int32_t *label_out, int32_t *num_components_out,
+                  gfr_stream stream);
+
+/*
+ * PageRank by power iteration (Sec. 5.5): x_0 = 1/N,
+ *   x_{k+1}(v) = (1-d)/N + d * (sum_{u in N(v)} x_k(u)/deg(u) + D_k/N),
+ * D_k the rank held by zero-degree vertices.  Stops after the first iteration
+ * whose L1 change is below l1_tol, or after max_iter iterations (GFR_OK in
+ * both cases; compare *iters_out with max_iter).  Ranks are FP32, global sums
+ * FP64.  rank_out: n floats; iters_out / final_l1_out: host pointers, may be
+ * NULL.  GFR_E_INVALID if damping is not in (0,1) or max_iter < 1.
+ */
+gfr_status gfr_pagerank(gfr_ctx *ctx, gfr_graph g, float damping, double l1_tol,
+                        int32_t max_iter, float *rank_out, int32_t *iters_out,
+                        double *final_l1_out, gfr_stream stream);
+
+/* ---------------------------------------------------------------- batching */
+/*
+ * k BFS (or SSSP) solves from `sources` (host memory, k >= 1) on one graph,
+ * run together: the sources share every read of the graph.  Row i of the
+ * output (n elements starting at out + i*n) equals the single-source result
+ * for sources[i].  Duplicated sources are allowed.
+ */
+gfr_status gfr_bfs_batch(gfr_ctx *ctx, gfr_graph g, const int32_t *sources, int32_t k,
+                         int32_t *depth_out, gfr_stream stream);
+gfr_status gfr_sssp_batch(gfr_ctx *ctx, gfr_graph g, const int32_t *sources, int32_t k,
+                          uint32_t *dist_out, gfr_stream stream);
+
+/* ----------------------------------------------------------------- serving */
+#define GFR_Q_BFS   1
+#define GFR_Q_SSSP  2
+
+typedef struct gfr_query {
+    int32_t kind;          /* GFR_Q_BFS or GFR_Q_SSSP                                 */
+    int32_t source;        /* source vertex                                           */
+    gfr_graph graph;       /* resident graph                                          */
+    void *out;             /* n elements (int32 depth / uint32 dist), lent until done */
+    int32_t out_on_device; /* nonzero: `out` is device memory of the context's device */
+    int32_t reserved;      /* must be 0                                               */
+    uint64_t user_tag;     /* returned untouched                                      */
+} gfr_query;
+
+/*
+ * Queue `count` queries for asynchronous execution; tickets_out[i] receives
+ * the ticket of queries[i].  Queries are admitted when their device footprint
+ * fits the context's budget ("serve.budget_bytes") and are batched with other
+ * admitted queries on the same graph as they arrive (continuous batching).
+ * A query that could never fit the budget -> GFR_E_CAPACITY for the whole
+ * call, nothing queued.  A query with a bad source or graph is queued and
+ * completes with that error status.
+ */
+gfr_status gfr_submit_queries(gfr_ctx *ctx, const gfr_query *queries, int32_t count,
+                              gfr_ticket *tickets_out);
+
+/*
+ * Collect up to `cap` finished tickets (and their statuses) into done/status,
+ * waiting up to timeout_us microseconds for at least one (0: do not wait).
+ * *ndone receives the count (0 on timeout, still GFR_OK).
+ */
+gfr_status gfr_poll(gfr_ctx *ctx, gfr_ticket *done, gfr_status *status, int32_t cap,
+                    int32_t *ndone, int32_t timeout_us);
+
+/* Cancel a queued query; GFR_E_NOT_FOUND if unknown or already finished. */
+gfr_status gfr_cancel(gfr_ctx *ctx, gfr_ticket t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GFR_H */

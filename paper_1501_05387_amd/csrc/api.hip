@@ -1,0 +1,585 @@
+// api.hip -- the C ABI (include/gfr.h): contexts, resident graphs, argument
+// checking, output placement (host or device), and dispatch to the solvers.
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+
+namespace gfr {
+
+void fail(gfr_status code, const std::string &msg) { throw Error{code, msg}; }
+
+Graph &get_graph(Ctx &c, gfr_graph h)
+{
+    auto it = c.graphs.find(h);
+    if (it == c.graphs.end()) fail(GFR_E_NOT_FOUND, "unknown graph handle " + std::to_string(h));
+    return *it->second;
+}
+
+bool is_device_ptr(const void *p)
+{
+    hipPointerAttribute_t attr;
+    memset(&attr, 0, sizeof attr);
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice;
+}
+
+int grid_blocks(const Ctx &c, int per_cu) { return c.num_cu * per_cu; }
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t count)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) p[i] = v;
+}
+
+void fill_u32(void *p, uint32_t value, size_t count, hipStream_t s)
+{
+    if (count == 0) return;
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t *)p, value, count);
+    GFR_LAUNCH_CHECK();
+}
+
+// Host check of a CSR graph; returns an empty string when it is acceptable.
+static std::string check_csr(int32_t n, int64_t m, const int32_t *R, const int32_t *C,
+                             const uint32_t *W, uint32_t flags)
+{
+    (void)W;
+    if (n <= 0) return "n must be positive";
+    if (m < 0) return "m must be non-negative";
+    if (m > (int64_t)INT32_MAX - 1) return "m must be below 2^31-1";
+    if (!R || (m > 0 && !C)) return "null CSR array";
+    if (R[0] != 0) return "row_offsets[0] must be 0";
+    if ((int64_t)R[n] != m) return "row_offsets[n] must equal m";
+    for (int32_t i = 0; i < n; ++i)
+        if (R[i + 1] < R[i]) return "row_offsets decrease at row " + std::to_string(i);
+    for (int64_t e = 0; e < m; ++e)
+        if (C[e] < 0 || C[e] >= n) return "column id out of range at entry " + std::to_string(e);
+    if (flags & GFR_VALIDATE) {
+        for (int32_t u = 0; u < n; ++u) {
+            for (int32_t e = R[u]; e < R[u + 1]; ++e) {
+                if (C[e] == u) return "self loop at vertex " + std::to_string(u);
+                if (e > R[u] && C[e] <= C[e - 1])
+                    return "row " + std::to_string(u) + " not strictly increasing (unsorted or duplicate)";
+            }
+        }
+        // symmetry: every (u,v) has (v,u) with the same weight
+        for (int32_t u = 0; u < n; ++u) {
+            for (int32_t e = R[u]; e < R[u + 1]; ++e) {
+                const int32_t v = C[e];
+                const int32_t *b = C + R[v], *en = C + R[v + 1];
+                const int32_t *f = std::lower_bound(b, en, u);
+                if (f == en || *f != u)
+                    return "asymmetric: edge " + std::to_string(u) + "->" + std::to_string(v) + " has no reverse";
+                if (W && W[f - C] != W[e])
+                    return "asymmetric weights on edge " + std::to_string(u) + "-" + std::to_string(v);
+            }
+        }
+    }
+    return std::string();
+}
+
+// The whole vertex set as a frontier queue, chunked for the gather kernels.
+static void build_full_queue(Ctx &c, Graph &g, const int32_t *R)
+{
+    const int32_t n = g.n;
+    std::vector<int32_t> v, row;
+    std::vector<uint32_t> off;
+    v.reserve(n);
+    for (int32_t i = 0; i < n; ++i)
+        if (R[i + 1] > R[i]) v.push_back(i);
+    const int32_t nf = (int32_t)v.size();
+    off.resize(nf);
+    row.resize(nf);
+    for (int32_t i = 0; i < nf; ++i) {
+        off[i] = (uint32_t)R[v[i]];
+        row[i] = R[v[i]];
+    }
+    const size_t nch = (size_t)(g.m + GATHER_CH - 1) / GATHER_CH;
+    std::vector<int32_t> part(nch + 1, 0);
+    {
+        size_t ci = 0;
+        for (int32_t i = 0; i < nf && ci < nch; ++i) {
+            const uint64_t end = (uint64_t)off[i] + (uint64_t)(R[v[i] + 1] - R[v[i]]);
+            while (ci < nch && (uint64_t)ci * GATHER_CH < end) part[ci++] = i;
+        }
+    }
+    const size_t b_v = al256(4ull * std::max(nf, 1)), b_p = al256(4ull * (nch + 1));
+    g.full_mem.alloc(3 * b_v + b_p + 256);
+    char *base = (char *)g.full_mem.p;
+    g.full.v = (int32_t *)base;
+    g.full.off = (uint32_t *)(base + b_v);
+    g.full.row = (int32_t *)(base + 2 * b_v);
+    g.full.part = (int32_t *)(base + 3 * b_v);
+    g.full_counts = (uint32_t *)(base + 3 * b_v + b_p);
+    uint32_t counts[4] = {(uint32_t)nf, (uint32_t)g.m, 0u, 0u};
+    if (nf) {
+        GFR_HIP(hipMemcpyAsync(g.full.v, v.data(), 4ull * nf, hipMemcpyHostToDevice, c.stream));
+        GFR_HIP(hipMemcpyAsync(g.full.off, off.data(), 4ull * nf, hipMemcpyHostToDevice, c.stream));
+        GFR_HIP(hipMemcpyAsync(g.full.row, row.data(), 4ull * nf, hipMemcpyHostToDevice, c.stream));
+    }
+    GFR_HIP(hipMemcpyAsync(g.full.part, part.data(), 4ull * (nch + 1), hipMemcpyHostToDevice, c.stream));
+    GFR_HIP(hipMemcpyAsync(g.full_counts, counts, sizeof counts, hipMemcpyHostToDevice, c.stream));
+    GFR_HIP(hipStreamSynchronize(c.stream));
+    g.full_nf = nf;
+    g.n_isolated = n - nf;
+    g.bytes += g.full_mem.bytes;
+}
+
+// An output buffer the solvers can write on the device: the caller's own
+// device buffer, or a staging buffer copied back to host memory afterwards.
+struct OutBuf {
+    void *user;
+    void *dev;
+    size_t bytes;
+    bool staged;
+    OutBuf(Ctx &c, void *p, size_t b) : user(p), dev(p), bytes(b), staged(false)
+    {
+        if (!p) fail(GFR_E_INVALID, "null output buffer");
+        if (!is_device_ptr(p)) {
+            if (c.stage.bytes < b) c.stage.alloc(b);
+            dev = c.stage.p;
+            staged = true;
+        }
+    }
+    void finish(hipStream_t s)
+    {
+        if (staged) GFR_HIP(hipMemcpyAsync(user, dev, bytes, hipMemcpyDeviceToHost, s));
+        GFR_HIP(hipStreamSynchronize(s));
+    }
+};
+
+static hipStream_t pick_stream(Ctx &c, gfr_stream s) { return s ? (hipStream_t)s : c.stream; }
+
+template <class F>
+static gfr_status guard(gfr_ctx *ctx, F f)
+{
+    if (!ctx) return GFR_E_INVALID;
+    Ctx &c = *(Ctx *)ctx;
+    std::lock_guard<std::recursive_mutex> lk(c.mu);
+    try {
+        c.err.clear();
+        GFR_HIP(hipSetDevice(c.device));
+        f(c);
+        return GFR_OK;
+    } catch (const Error &e) {
+        c.err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        c.err = "host allocation failed";
+        return GFR_E_OOM;
+    } catch (const std::exception &e) {
+        c.err = e.what();
+        return GFR_E_DEVICE;
+    }
+}
+
+static void timed_begin(Ctx &c, hipStream_t s)
+{
+    c.stats.clear();
+    c.ktimer.reset();
+    c.ktimer.on = c.opt.profile_kernels != 0;
+    GFR_HIP(hipEventRecord(c.ev0, s));
+}
+
+static void timed_end(Ctx &c, hipStream_t s)
+{
+    GFR_HIP(hipEventRecord(c.ev1, s));
+    GFR_HIP(hipEventSynchronize(c.ev1));
+    float ms = 0.f;
+    GFR_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+    c.stats.v["kernel_ms"] = ms;
+    c.ktimer.collect(c.stats.v);
+}
+
+struct OptKey {
+    const char *name;
+    double lo, hi;
+};
+
+static const OptKey kOptKeys[] = {
+    {"bfs.direction", 0, 2},  {"bfs.alpha", 1e-6, 1e9},       {"bfs.beta", 1e-6, 1e9},
+    {"bfs.dedup", 0, 1},      {"sssp.delta", 0, 4.0e9},       {"advance.chunk", 256, 4096},
+    {"lb.threshold", 0, 2e9}, {"serve.budget_bytes", 0, 1e15}, {"profile.kernels", 0, 1},
+};
+
+static double *opt_slot(Options &o, const std::string &k, double &tmp)
+{
+    (void)tmp;
+    static double dummy;
+    if (k == "bfs.alpha") return &o.bfs_alpha;
+    if (k == "bfs.beta") return &o.bfs_beta;
+    if (k == "sssp.delta") return &o.sssp_delta;
+    if (k == "serve.budget_bytes") return &o.serve_budget;
+    return &dummy;
+}
+
+static void set_option(Ctx &c, const std::string &key, double v)
+{
+    const OptKey *k = nullptr;
+    for (const auto &e : kOptKeys)
+        if (key == e.name) k = &e;
+    if (!k) fail(GFR_E_INVALID, "unknown option '" + key + "'");
+    if (!(v >= k->lo && v <= k->hi)) fail(GFR_E_INVALID, "option '" + key + "' out of range");
+    Options &o = c.opt;
+    if (key == "bfs.direction") o.bfs_direction = (int)v;
+    else if (key == "bfs.dedup") o.bfs_dedup = (int)v;
+    else if (key == "lb.threshold") o.lb_threshold = (int)v;
+    else if (key == "profile.kernels") o.profile_kernels = (int)v;
+    else if (key == "advance.chunk") {
+        const int iv = (int)v;
+        if (iv != 256 && iv != 512 && iv != 1024 && iv != 2048 && iv != 4096)
+            fail(GFR_E_INVALID, "advance.chunk must be 256, 512, 1024, 2048 or 4096");
+        o.advance_chunk = iv;
+    } else {
+        double tmp;
+        *opt_slot(o, key, tmp) = v;
+    }
+}
+
+static double get_option(Ctx &c, const std::string &key)
+{
+    const Options &o = c.opt;
+    if (key == "bfs.direction") return o.bfs_direction;
+    if (key == "bfs.alpha") return o.bfs_alpha;
+    if (key == "bfs.beta") return o.bfs_beta;
+    if (key == "bfs.dedup") return o.bfs_dedup;
+    if (key == "sssp.delta") return o.sssp_delta;
+    if (key == "advance.chunk") return o.advance_chunk;
+    if (key == "lb.threshold") return o.lb_threshold;
+    if (key == "serve.budget_bytes") return o.serve_budget;
+    if (key == "profile.kernels") return o.profile_kernels;
+    fail(GFR_E_INVALID, "unknown option '" + key + "'");
+}
+
+// Minimal parser for a flat JSON object of numeric options: {"key": number, ...}
+static void apply_tuning_json(Ctx &c, const char *js)
+{
+    std::string s(js);
+    size_t i = 0;
+    auto skip = [&]() {
+        while (i < s.size() && (s[i] == ' ' || s[i] == '\n' || s[i] == '\t' || s[i] == '\r' || s[i] == ','))
+            ++i;
+    };
+    skip();
+    if (i >= s.size() || s[i] != '{') fail(GFR_E_INVALID, "tuning_json: expected an object");
+    ++i;
+    for (;;) {
+        skip();
+        if (i < s.size() && s[i] == '}') break;
+        if (i >= s.size() || s[i] != '"') fail(GFR_E_INVALID, "tuning_json: expected a key");
+        size_t j = s.find('"', i + 1);
+        if (j == std::string::npos) fail(GFR_E_INVALID, "tuning_json: unterminated key");
+        std::string key = s.substr(i + 1, j - i - 1);
+        i = j + 1;
+        skip();
+        if (i >= s.size() || s[i] != ':') fail(GFR_E_INVALID, "tuning_json: expected ':'");
+        ++i;
+        skip();
+        char *endp = nullptr;
+        double v = strtod(s.c_str() + i, &endp);
+        if (endp == s.c_str() + i) fail(GFR_E_INVALID, "tuning_json: expected a number for " + key);
+        i = endp - s.c_str();
+        set_option(c, key, v);
+    }
+}
+
+}  // namespace gfr
+
+using namespace gfr;
+
+extern "C" {
+
+gfr_status gfr_ctx_create(int32_t device, const char *tuning_json, gfr_ctx **out)
+{
+    if (!out) return GFR_E_INVALID;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        (void)hipGetLastError();
+        return GFR_E_DEVICE;
+    }
+    Ctx *c = new (std::nothrow) Ctx();
+    if (!c) return GFR_E_OOM;
+    gfr_status st = guard((gfr_ctx *)c, [&](Ctx &cc) {
+        cc.device = device;
+        GFR_HIP(hipSetDevice(device));
+        hipDeviceProp_t p;
+        GFR_HIP(hipGetDeviceProperties(&p, device));
+        if (strncmp(p.gcnArchName, "gfx950", 6) != 0)
+            fail(GFR_E_DEVICE, std::string("device is ") + p.gcnArchName + ", this library is built for gfx950");
+        cc.num_cu = p.multiProcessorCount;
+        GFR_HIP(hipStreamCreateWithFlags(&cc.stream, hipStreamNonBlocking));
+        GFR_HIP(hipHostMalloc((void **)&cc.pinned, 4096, hipHostMallocDefault));
+        GFR_HIP(hipEventCreate(&cc.ev0));
+        GFR_HIP(hipEventCreate(&cc.ev1));
+        cc.zero_word.alloc(256);
+        GFR_HIP(hipMemsetAsync(cc.zero_word.p, 0, 256, cc.stream));
+        GFR_HIP(hipStreamSynchronize(cc.stream));
+        if (tuning_json) apply_tuning_json(cc, tuning_json);
+    });
+    if (st != GFR_OK) {
+        gfr_ctx_destroy((gfr_ctx *)c);
+        return st;
+    }
+    *out = (gfr_ctx *)c;
+    return GFR_OK;
+}
+
+gfr_status gfr_ctx_destroy(gfr_ctx *ctx)
+{
+    if (!ctx) return GFR_OK;
+    Ctx *c = (Ctx *)ctx;
+    (void)hipSetDevice(c->device);
+    serve_shutdown(*c);
+    c->graphs.clear();
+    c->arena.mem.release();
+    c->stage.release();
+    c->zero_word.release();
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return GFR_OK;
+}
+
+const char *gfr_last_error(const gfr_ctx *ctx)
+{
+    if (!ctx) return "null context";
+    return ((const Ctx *)ctx)->err.c_str();
+}
+
+gfr_status gfr_set_option(gfr_ctx *ctx, const char *key, double value)
+{
+    return guard(ctx, [&](Ctx &c) {
+        if (!key) fail(GFR_E_INVALID, "null key");
+        set_option(c, key, value);
+    });
+}
+
+gfr_status gfr_get_option(gfr_ctx *ctx, const char *key, double *value)
+{
+    return guard(ctx, [&](Ctx &c) {
+        if (!key || !value) fail(GFR_E_INVALID, "null argument");
+        *value = get_option(c, key);
+    });
+}
+
+gfr_status gfr_get_stat(gfr_ctx *ctx, const char *key, double *value)
+{
+    return guard(ctx, [&](Ctx &c) {
+        if (!key || !value) fail(GFR_E_INVALID, "null argument");
+        auto it = c.stats.v.find(key);
+        if (it == c.stats.v.end()) fail(GFR_E_NOT_FOUND, std::string("no statistic '") + key + "'");
+        *value = it->second;
+    });
+}
+
+gfr_status gfr_validate_csr(int32_t n, int64_t m, const int32_t *R, const int32_t *C,
+                            const uint32_t *W, uint32_t flags, char *msg, int32_t msg_cap)
+{
+    std::string why;
+    try {
+        why = check_csr(n, m, R, C, W, flags);
+    } catch (...) {
+        why = "validation failed";
+    }
+    if (msg && msg_cap > 0) {
+        size_t k = std::min((size_t)msg_cap - 1, why.size());
+        memcpy(msg, why.data(), k);
+        msg[k] = 0;
+    }
+    return why.empty() ? GFR_OK : GFR_E_INVALID;
+}
+
+gfr_status gfr_graph_load_csr(gfr_ctx *ctx, int32_t n, int64_t m, const int32_t *R, const int32_t *C,
+                              const uint32_t *W, uint32_t flags, gfr_graph *out)
+{
+    return guard(ctx, [&](Ctx &c) {
+        if (!out) fail(GFR_E_INVALID, "null output handle");
+        *out = 0;
+        std::string why = check_csr(n, m, R, C, W, flags);
+        if (!why.empty()) fail(GFR_E_INVALID, "graph_load_csr: " + why);
+        auto g = std::make_unique<Graph>();
+        g->n = n;
+        g->m = m;
+        g->R.alloc(4ull * (n + 1));
+        g->C.alloc(4ull * std::max<int64_t>(m, 1));
+        GFR_HIP(hipMemcpyAsync(g->R.p, R, 4ull * (n + 1), hipMemcpyHostToDevice, c.stream));
+        if (m) GFR_HIP(hipMemcpyAsync(g->C.p, C, 4ull * m, hipMemcpyHostToDevice, c.stream));
+        g->bytes = g->R.bytes + g->C.bytes;
+        if (W) {
+            g->W.alloc(4ull * std::max<int64_t>(m, 1));
+            if (m) GFR_HIP(hipMemcpyAsync(g->W.p, W, 4ull * m, hipMemcpyHostToDevice, c.stream));
+            g->weighted = true;
+            g->bytes += g->W.bytes;
+            double sw = 0;
+            for (int64_t e = 0; e < m; ++e) sw += W[e];
+            g->mean_w = m ? sw / (double)m : 1.0;
+        }
+        int32_t md = 0;
+        for (int32_t i = 0; i < n; ++i) md = std::max(md, R[i + 1] - R[i]);
+        g->max_deg = md;
+        build_full_queue(c, *g, R);
+        GFR_HIP(hipStreamSynchronize(c.stream));
+        const int64_t h = c.next_handle++;
+        c.graphs[h] = std::move(g);
+        *out = h;
+    });
+}
+
+gfr_status gfr_graph_free(gfr_ctx *ctx, gfr_graph g)
+{
+    return guard(ctx, [&](Ctx &c) {
+        get_graph(c, g);
+        GFR_HIP(hipStreamSynchronize(c.stream));
+        c.graphs.erase(g);
+    });
+}
+
+gfr_status gfr_graph_info(gfr_ctx *ctx, gfr_graph gh, int32_t *n, int64_t *m, uint64_t *bytes)
+{
+    return guard(ctx, [&](Ctx &c) {
+        Graph &g = get_graph(c, gh);
+        if (n) *n = g.n;
+        if (m) *m = g.m;
+        if (bytes) *bytes = g.bytes;
+    });
+}
+
+gfr_status gfr_bfs(gfr_ctx *ctx, gfr_graph gh, int32_t source, int32_t *depth_out, gfr_stream stream)
+{
+    return guard(ctx, [&](Ctx &c) {
+        Graph &g = get_graph(c, gh);
+        if (source < 0 || source >= g.n) fail(GFR_E_INVALID, "bfs: source out of range");
+        hipStream_t s = pick_stream(c, stream);
+        OutBuf o(c, depth_out, 4ull * g.n);
+        timed_begin(c, s);
+        run_bfs(c, g, source, (int32_t *)o.dev, s);
+        timed_end(c, s);
+        o.finish(s);
+    });
+}
+
+gfr_status gfr_sssp(gfr_ctx *ctx, gfr_graph gh, int32_t source, uint32_t *dist_out, gfr_stream stream)
+{
+    return guard(ctx, [&](Ctx &c) {
+        Graph &g = get_graph(c, gh);
+        if (source < 0 || source >= g.n) fail(GFR_E_INVALID, "sssp: source out of range");
+        if (!g.weighted) fail(GFR_E_INVALID, "sssp: graph was loaded without weights");
+        hipStream_t s = pick_stream(c, stream);
+        OutBuf o(c, dist_out, 4ull * g.n);
+        timed_begin(c, s);
+        run_sssp(c, g, source, (uint32_t *)o.dev, s);
+        timed_end(c, s);
+        o.finish(s);
+    });
+}
+
+gfr_status gfr_bc(gfr_ctx *ctx, gfr_graph gh, const int32_t *sources, int32_t k, float *bc_out,
+                  gfr_stream stream)
+{
+    return guard(ctx, [&](Ctx &c) {
+        Graph &g = get_graph(c, gh);
+        if (k < 0 || (k > 0 && !sources)) fail(GFR_E_INVALID, "bc: bad source list");
+        std::vector<int32_t> src(sources, sources + k);
+        for (int32_t i = 0; i < k; ++i)
+            if (src[i] < 0 || src[i] >= g.n) fail(GFR_E_INVALID, "bc: source out of range");
+        std::vector<int32_t> sorted(src);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            fail(GFR_E_INVALID, "bc: duplicate source");
+        hipStream_t s = pick_stream(c, stream);
+        OutBuf o(c, bc_out, 4ull * g.n);
+        timed_begin(c, s);
+        run_bc(c, g, src.data(), k, (float *)o.dev, s);
+        timed_end(c, s);
+        o.finish(s);
+    });
+}
+
+gfr_status gfr_cc(gfr_ctx *ctx, gfr_graph gh, int32_t *label_out, int32_t *num_components_out,
+                  gfr_stream stream)
+{
+    return guard(ctx, [&](Ctx &c) {
+        Graph &g = get_graph(c, gh);
+        hipStream_t s = pick_stream(c, stream);
+        OutBuf o(c, label_out, 4ull * g.n);
+        int32_t nc = 0;
+        timed_begin(c, s);
+        run_cc(c, g, (int32_t *)o.dev, &nc, s);
+        timed_end(c, s);
+        o.finish(s);
+        if (num_components_out) *num_components_out = nc;
+    });
+}
+
+gfr_status gfr_pagerank(gfr_ctx *ctx, gfr_graph gh, float damping, double l1_tol, int32_t max_iter,
+                        float *rank_out, int32_t *iters_out, double *final_l1_out, gfr_stream stream)
+{
+    return guard(ctx, [&](Ctx &c) {
+        Graph &g = get_graph(c, gh);
+        if (!(damping > 0.f && damping < 1.f)) fail(GFR_E_INVALID, "pagerank: damping must be in (0,1)");
+        if (max_iter < 1) fail(GFR_E_INVALID, "pagerank: max_iter must be >= 1");
+        if (!(l1_tol >= 0.0)) fail(GFR_E_INVALID, "pagerank: l1_tol must be >= 0");
+        hipStream_t s = pick_stream(c, stream);
+        OutBuf o(c, rank_out, 4ull * g.n);
+        int32_t it = 0;
+        double l1 = 0.0;
+        timed_begin(c, s);
+        run_pagerank(c, g, damping, l1_tol, max_iter, (float *)o.dev, &it, &l1, s);
+        timed_end(c, s);
+        o.finish(s);
+        if (iters_out) *iters_out = it;
+        if (final_l1_out) *final_l1_out = l1;
+    });
+}
+
+gfr_status gfr_bfs_batch(gfr_ctx *ctx, gfr_graph gh, const int32_t *sources, int32_t k,
+                         int32_t *depth_out, gfr_stream stream)
+{
+    return guard(ctx, [&](Ctx &c) {
+        Graph &g = get_graph(c, gh);
+        if (k < 1 || !sources) fail(GFR_E_INVALID, "bfs_batch: need k >= 1 sources");
+        for (int32_t i = 0; i < k; ++i)
+            if (sources[i] < 0 || sources[i] >= g.n) fail(GFR_E_INVALID, "bfs_batch: source out of range");
+        hipStream_t s = pick_stream(c, stream);
+        OutBuf o(c, depth_out, 4ull * g.n * (size_t)k);
+        timed_begin(c, s);
+        run_bfs_batch(c, g, sources, k, (int32_t *)o.dev, s);
+        timed_end(c, s);
+        o.finish(s);
+    });
+}
+
+gfr_status gfr_sssp_batch(gfr_ctx *ctx, gfr_graph gh, const int32_t *sources, int32_t k,
+                          uint32_t *dist_out, gfr_stream stream)
+{
+    return guard(ctx, [&](Ctx &c) {
+        Graph &g = get_graph(c, gh);
+        if (k < 1 || !sources) fail(GFR_E_INVALID, "sssp_batch: need k >= 1 sources");
+        if (!g.weighted) fail(GFR_E_INVALID, "sssp_batch: graph was loaded without weights");
+        for (int32_t i = 0; i < k; ++i)
+            if (sources[i] < 0 || sources[i] >= g.n) fail(GFR_E_INVALID, "sssp_batch: source out of range");
+        hipStream_t s = pick_stream(c, stream);
+        OutBuf o(c, dist_out, 4ull * g.n * (size_t)k);
+        timed_begin(c, s);
+        run_sssp_batch(c, g, sources, k, (uint32_t *)o.dev, s);
+        timed_end(c, s);
+        o.finish(s);
+    });
+}
+
+}  // extern "C"

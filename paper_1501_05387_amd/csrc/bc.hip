@@ -1,0 +1,225 @@
+// bc.hip -- betweenness centrality from a set of sources, Brandes'
+// two-pass formulation as the paper maps it (Sec. 5.3):
+//   forward   an advance identical to BFS discovers level L+1 from level L,
+//             then a compute step gathers sigma(v) = sum of sigma(u) over the
+//             neighbours u one level up (shortest-path counts, FP64);
+//   backward  walks the levels in reverse and gathers
+//             delta(v) = sigma(v) * sum over neighbours w one level down of
+//                        (1 + delta(w)) / sigma(w),
+//             stored in FP32; bc(v) accumulates delta(v) over sources.
+// Both gathers are pull-style: no floating-point atomics, fixed order per
+// list (see gather.h).  Every level is kept as a contiguous slice of one BFS
+// order array so the backward pass can revisit it.
+#include <vector>
+
+#include "engine.h"
+#include "gather.h"
+
+namespace gfr {
+
+struct BcArgs {
+    const int32_t *R;
+    const int32_t *C;
+    int32_t *depth;
+    uint32_t *vis;
+};
+
+// push advance of one level (load-balanced edge chunks), claims via the
+// visited bitmap, appends the new level to the next slice of the order array
+template <int CH>
+__global__ __launch_bounds__(GFR_BLOCK) void bc_discover(BcArgs a, FrontierQ qin, uint32_t nf, uint32_t mf,
+                                                         int32_t L, FrontierQ qout, unsigned long long *ctr)
+{
+    __shared__ uint32_t s_off[CH + 1];
+    __shared__ int32_t s_row[CH + 1];
+    const uint32_t nchunks = (mf + CH - 1) / CH;
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const uint32_t e0 = c * CH;
+        const uint32_t e1 = min(e0 + (uint32_t)CH, mf);
+        const int s = qin.part[c];
+        const int t = (c + 1 < nchunks) ? qin.part[c + 1] : (int)nf - 1;
+        const int cnt = t - s + 1;
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += GFR_BLOCK) {
+            s_off[i] = qin.off[s + i];
+            s_row[i] = qin.row[s + i];
+        }
+        __syncthreads();
+        for (uint32_t k = 0; k < (uint32_t)CH; k += GFR_BLOCK) {
+            const uint32_t e = e0 + k + threadIdx.x;
+            int32_t v = 0, rv = 0;
+            uint32_t dv = 0;
+            bool won = false;
+            if (e < e1) {
+                const int i = upper_index(s_off, 0, cnt - 1, e);
+                v = a.C[s_row[i] + (int32_t)(e - s_off[i])];
+                const uint32_t bit = 1u << (v & 31);
+                uint32_t *w = a.vis + (v >> 5);
+                if (!(*w & bit)) won = !(atomicOr(w, bit) & bit);
+                if (won) {
+                    a.depth[v] = L + 1;
+                    rv = a.R[v];
+                    dv = (uint32_t)(a.R[v + 1] - rv);
+                }
+            }
+            wave_enqueue(won, v, dv, rv, ctr, qout, CH);
+        }
+    }
+}
+
+__global__ void bc_source_init(BcArgs a, int32_t src, FrontierQ q0, double *sigma, unsigned long long *ctr0)
+{
+    const int32_t rs = a.R[src], deg = a.R[src + 1] - rs;
+    if (threadIdx.x == 0) {
+        a.depth[src] = 0;
+        a.vis[src >> 5] |= 1u << (src & 31);
+        sigma[src] = 1.0;
+        q0.v[0] = src;
+        q0.off[0] = 0;
+        q0.row[0] = rs;
+        *ctr0 = (1ull << 32) | (unsigned long long)(uint32_t)deg;
+    }
+    for (uint32_t c = threadIdx.x; (uint64_t)c * GATHER_CH < (uint64_t)deg; c += blockDim.x) q0.part[c] = 0;
+}
+
+struct SigmaOp {
+    const int32_t *depth;
+    const double *sigma;
+    int32_t L;   // level of the predecessors
+    __device__ double operator()(int32_t u, int32_t) const { return depth[u] == L ? sigma[u] : 0.0; }
+};
+
+struct SigmaFin {
+    double *sigma;
+    __device__ void operator()(int32_t v, double s) const { sigma[v] = s; }
+};
+
+struct DeltaOp {
+    const int32_t *depth;
+    const double *coef;
+    int32_t L;   // level of the successors
+    __device__ double operator()(int32_t w, int32_t) const { return depth[w] == L ? coef[w] : 0.0; }
+};
+
+struct DeltaFin {
+    const double *sigma;
+    double *coef;
+    double *bc;
+    __device__ void operator()(int32_t v, double s) const
+    {
+        const float dl = (float)(sigma[v] * s);
+        coef[v] = (1.0 + (double)dl) / sigma[v];
+        bc[v] += (double)dl;
+    }
+};
+
+__global__ void bc_leaf_coef(const FrontierQ q, uint32_t nf, const double *sigma, double *coef)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += gridDim.x * blockDim.x) {
+        const int32_t v = q.v[i];
+        coef[v] = 1.0 / sigma[v];
+    }
+}
+
+__global__ void bc_to_f32(const double *acc, float *out, int32_t n)
+{
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        out[v] = (float)acc[v];
+}
+
+struct Level {
+    uint32_t start, nf, mf, pbase;
+};
+
+void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipStream_t s)
+{
+    const int32_t n = g.n;
+    const uint32_t nwords = (uint32_t)(((int64_t)n + 63) / 64) * 2u;
+    const size_t nparts = (size_t)(g.m / GATHER_CH) + 2ull * n + 4;
+    const size_t nch = (size_t)(g.m / GATHER_CH) + 2;
+    const size_t nlev = (size_t)n + 2;
+    c.arena.reserve(al256(4ull * n) + al256(4ull * nwords) + 3 * al256(8ull * n) + 3 * al256(4ull * n) +
+                    al256(4 * nparts) + 2 * al256(8 * nch) + al256(8 * nlev));
+    BcArgs a;
+    a.R = g.R.as<int32_t>();
+    a.C = g.C.as<int32_t>();
+    a.depth = c.arena.take<int32_t>(n);
+    a.vis = c.arena.take<uint32_t>(nwords);
+    double *sigma = c.arena.take<double>(n);
+    double *coef = c.arena.take<double>(n);
+    double *acc = c.arena.take<double>(n);
+    int32_t *order = c.arena.take<int32_t>(n);
+    uint32_t *off = c.arena.take<uint32_t>(n);
+    int32_t *row = c.arena.take<int32_t>(n);
+    int32_t *part = c.arena.take<int32_t>(nparts);
+    GatherScratch gs{c.arena.take<double>(nch), c.arena.take<double>(nch)};
+    unsigned long long *ctr = c.arena.take<unsigned long long>(nlev);
+    const int G = grid_blocks(c, 4);
+
+    fill_u32(acc, 0u, 2ull * n, s);
+    auto qat = [&](const Level &l) {
+        return FrontierQ{order + l.start, off + l.start, row + l.start, part + l.pbase};
+    };
+    std::vector<Level> lv;
+    double levels_total = 0;
+    for (int32_t si = 0; si < k; ++si) {
+        const int32_t src = sources[si];
+        fill_u32(a.depth, 0xFFFFFFFFu, n, s);
+        fill_u32(a.vis, 0u, nwords, s);
+        lv.clear();
+        lv.push_back(Level{0, 1, 0, 0});
+        hipLaunchKernelGGL(bc_source_init, dim3(1), dim3(GFR_BLOCK), 0, s, a, src, qat(lv[0]), sigma, ctr);
+        GFR_LAUNCH_CHECK();
+        GFR_HIP(hipMemcpyAsync(c.pinned, ctr, 8, hipMemcpyDeviceToHost, s));
+        GFR_HIP(hipStreamSynchronize(s));
+        lv[0].mf = c.pinned[0];
+        // forward
+        for (;;) {
+            const Level cur = lv.back();
+            const int32_t L = (int32_t)lv.size() - 1;
+            if (cur.mf == 0) break;
+            Level nx{cur.start + cur.nf, 0, 0, cur.pbase + (cur.mf + GATHER_CH - 1) / GATHER_CH + 1};
+            unsigned long long *cn = ctr + lv.size();
+            fill_u32(cn, 0u, 2, s);
+            hipLaunchKernelGGL(bc_discover<GATHER_CH>, dim3(G), dim3(GFR_BLOCK), 0, s, a, qat(cur), cur.nf, cur.mf,
+                               L, qat(nx), cn);
+            GFR_LAUNCH_CHECK();
+            GFR_HIP(hipMemcpyAsync(c.pinned, cn, 8, hipMemcpyDeviceToHost, s));
+            GFR_HIP(hipStreamSynchronize(s));
+            nx.mf = c.pinned[0];
+            nx.nf = c.pinned[1];
+            if (nx.nf == 0) break;
+            lv.push_back(nx);
+            const uint32_t *cw = (const uint32_t *)cn;
+            hipLaunchKernelGGL((gather_chunks<GATHER_CH, SigmaOp, SigmaFin>), dim3(G), dim3(GFR_BLOCK), 0, s,
+                               qat(nx), cw + 1, cw, a.C, SigmaOp{a.depth, sigma, L}, SigmaFin{sigma}, gs,
+                               c.zero_word.as<uint32_t>());
+            hipLaunchKernelGGL((gather_fixup<GATHER_CH, SigmaFin>), dim3(G), dim3(GFR_BLOCK), 0, s, qat(nx), cw + 1,
+                               cw, SigmaFin{sigma}, gs, c.zero_word.as<uint32_t>());
+            GFR_LAUNCH_CHECK();
+        }
+        levels_total += (double)lv.size();
+        // backward: deepest level has no successors
+        const int32_t Lmax = (int32_t)lv.size() - 1;
+        if (Lmax >= 1) {
+            const Level &d = lv[Lmax];
+            hipLaunchKernelGGL(bc_leaf_coef, dim3(G), dim3(GFR_BLOCK), 0, s, qat(d), d.nf, sigma, coef);
+            GFR_LAUNCH_CHECK();
+        }
+        for (int32_t L = Lmax - 1; L >= 1; --L) {
+            const Level &l = lv[L];
+            const uint32_t *cw = (const uint32_t *)(ctr + L);
+            hipLaunchKernelGGL((gather_chunks<GATHER_CH, DeltaOp, DeltaFin>), dim3(G), dim3(GFR_BLOCK), 0, s, qat(l),
+                               cw + 1, cw, a.C, DeltaOp{a.depth, coef, L + 1}, DeltaFin{sigma, coef, acc}, gs,
+                               c.zero_word.as<uint32_t>());
+            hipLaunchKernelGGL((gather_fixup<GATHER_CH, DeltaFin>), dim3(G), dim3(GFR_BLOCK), 0, s, qat(l), cw + 1, cw,
+                               DeltaFin{sigma, coef, acc}, gs, c.zero_word.as<uint32_t>());
+            GFR_LAUNCH_CHECK();
+        }
+    }
+    hipLaunchKernelGGL(bc_to_f32, dim3(G), dim3(GFR_BLOCK), 0, s, acc, bc, n);
+    GFR_LAUNCH_CHECK();
+    c.stats.v["levels"] = levels_total;
+}
+
+}  // namespace gfr

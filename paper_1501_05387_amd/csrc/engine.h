@@ -1,0 +1,238 @@
+// engine.h -- host-side internals of the frontier engine (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gfr.h"
+#include "device.h"
+
+namespace gfr {
+
+struct Error {
+    gfr_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(gfr_status code, const std::string &msg);
+
+#define GFR_HIP(x)                                                                          \
+    do {                                                                                    \
+        hipError_t e_ = (x);                                                                \
+        if (e_ != hipSuccess)                                                               \
+            ::gfr::fail(e_ == hipErrorOutOfMemory ? GFR_E_OOM : GFR_E_DEVICE,               \
+                        std::string(#x) + ": " + hipGetErrorString(e_));                    \
+    } while (0)
+
+#define GFR_LAUNCH_CHECK() GFR_HIP(hipGetLastError())
+
+// Device allocation owned by RAII.
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
+    ~DevMem() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t b)
+    {
+        release();
+        if (b == 0) b = 256;
+        GFR_HIP(hipMalloc(&p, b));
+        bytes = b;
+    }
+    template <class T> T *as() const { return (T *)p; }
+};
+
+// Growable scratch arena, carved per solve.  Grows only.
+struct Arena {
+    DevMem mem;
+    size_t used = 0;
+    void reserve(size_t b)
+    {
+        used = 0;
+        if (b > mem.bytes) mem.alloc(b + (b >> 3));
+    }
+    template <class T> T *take(size_t count)
+    {
+        size_t b = (count * sizeof(T) + 255) & ~(size_t)255;
+        if (used + b > mem.bytes) fail(GFR_E_DEVICE, "internal: arena overflow");
+        T *p = (T *)((char *)mem.p + used);
+        used += b;
+        return p;
+    }
+};
+
+static inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Graph {
+    int32_t n = 0;
+    int64_t m = 0;
+    DevMem R, C, W;
+    bool weighted = false;
+    int32_t max_deg = 0;
+    double mean_w = 0.0;
+    uint64_t bytes = 0;
+    // the whole vertex set as a frontier queue (non-isolated vertices in id
+    // order, offsets = row offsets), chunked for the gather kernels
+    FrontierQ full{};
+    DevMem full_mem;
+    uint32_t *full_counts = nullptr;   // device [nf, mf, 0, 0]
+    int32_t full_nf = 0;
+    int32_t n_isolated = 0;
+    // hints for the speculative level loop
+    int32_t bfs_levels_hint = 8;
+    int32_t sssp_iter_hint = 16;
+};
+
+struct Options {
+    int bfs_direction = 0;      // 0 auto, 1 push, 2 pull
+    double bfs_alpha = 15.0;
+    double bfs_beta = 18.0;
+    int bfs_dedup = 0;          // 0 atomic, 1 idempotent
+    double sssp_delta = 0.0;    // 0 -> automatic
+    int advance_chunk = 1024;
+    int lb_threshold = 4096;
+    double serve_budget = 8.0e9;
+    int profile_kernels = 0;
+};
+
+struct Stats {
+    std::map<std::string, double> v;
+    void clear() { v.clear(); }
+};
+
+struct Server;
+
+// Optional per-launch timing of named kernels with HIP events on the launch
+// stream ("profile.kernels" option).  Results land in the context statistics
+// as "t.<kernel>.ms" (summed device time) and "t.<kernel>.n" (launches).
+struct KernelTimer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<const char *, std::pair<hipEvent_t, hipEvent_t>>> marks;
+    size_t used = 0;
+    hipEvent_t take()
+    {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            GFR_HIP(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void reset()
+    {
+        used = 0;
+        marks.clear();
+    }
+    template <class F> void run(const char *name, hipStream_t s, F launch)
+    {
+        if (!on) {
+            launch();
+            return;
+        }
+        hipEvent_t a = take(), b = take();
+        GFR_HIP(hipEventRecord(a, s));
+        launch();
+        GFR_HIP(hipEventRecord(b, s));
+        marks.push_back({name, {a, b}});
+    }
+    void collect(std::map<std::string, double> &out)
+    {
+        for (auto &m : marks) {
+            GFR_HIP(hipEventSynchronize(m.second.second));
+            float ms = 0.f;
+            GFR_HIP(hipEventElapsedTime(&ms, m.second.first, m.second.second));
+            out[std::string("t.") + m.first + ".ms"] += ms;
+            out[std::string("t.") + m.first + ".n"] += 1.0;
+        }
+        reset();
+    }
+    ~KernelTimer()
+    {
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 256;
+    std::recursive_mutex mu;
+    std::string err;
+    std::map<int64_t, std::unique_ptr<Graph>> graphs;
+    int64_t next_handle = 1;
+    Arena arena;
+    DevMem stage;                 // device staging for host output buffers
+    DevMem zero_word;             // a device word that always holds 0
+    uint32_t *pinned = nullptr;   // small pinned host buffer for control readbacks
+    Options opt;
+    Stats stats;
+    Server *server = nullptr;     // owned; destroyed by serve_shutdown
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    KernelTimer ktimer;
+};
+
+Graph &get_graph(Ctx &c, gfr_graph h);
+bool is_device_ptr(const void *p);
+int grid_blocks(const Ctx &c, int per_cu = 4);
+
+// Solvers (outputs are device pointers on the context's device).
+void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s);
+void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s);
+void run_cc(Ctx &c, Graph &g, int32_t *label, int32_t *ncomp, hipStream_t s);
+void run_pagerank(Ctx &c, Graph &g, float damping, double tol, int32_t max_iter, float *rank,
+                  int32_t *iters, double *l1, hipStream_t s);
+void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipStream_t s);
+void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t *depth,
+                   hipStream_t s);
+void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_t *dist,
+                    hipStream_t s);
+
+// Edges per chunk of the gather / for-each-edge kernels and of the full queue.
+constexpr uint32_t GATHER_CH = 1024;
+
+// Stops the serving runtime of a context (no-op if none).
+void serve_shutdown(Ctx &c);
+
+// Fill helpers.
+void fill_u32(void *p, uint32_t value, size_t count, hipStream_t s);
+
+// Spin on a device word until the speculative level loop reports completion.
+// Launches `launch(k)` batches and reads *flag (device) back after each batch.
+template <class LaunchFn>
+int32_t run_until_done(Ctx &c, const uint32_t *flag_dev, uint32_t done_value, int32_t first_batch,
+                       int64_t max_launches, hipStream_t s, LaunchFn launch)
+{
+    int64_t launched = 0;
+    int32_t batch = first_batch < 1 ? 1 : first_batch;
+    for (;;) {
+        for (int32_t i = 0; i < batch; ++i) launch();
+        GFR_LAUNCH_CHECK();
+        launched += batch;
+        GFR_HIP(hipMemcpyAsync(c.pinned, flag_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        GFR_HIP(hipStreamSynchronize(s));
+        if (*(volatile uint32_t *)c.pinned == done_value) break;
+        if (launched > max_launches) fail(GFR_E_DEVICE, "iteration watchdog: solve did not converge");
+        batch = batch < 128 ? batch * 2 : 256;
+    }
+    return (int32_t)launched;
+}
+
+}  // namespace gfr

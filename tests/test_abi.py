@@ -1,0 +1,90 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function the
+header declares, the binding knows each of them, and the host-only CSR
+validation accepts and rejects the right graphs.  No device work here."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import graphgen
+import paper_1501_05387_amd as gfr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gfr.h")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gfr_\w+)\s*\(", txt)))
+
+
+def test_header_declares_the_abi():
+    names = header_functions()
+    for required in ("gfr_graph_load_csr", "gfr_bfs", "gfr_sssp", "gfr_bc", "gfr_cc", "gfr_pagerank",
+                     "gfr_submit_queries", "gfr_poll"):
+        assert required in names
+
+
+def test_library_exports_every_header_symbol():
+    L = gfr.lib()
+    for name in header_functions():
+        assert hasattr(L, name), "libgfr.so does not export %s" % name
+        assert isinstance(getattr(L, name), ctypes._CFuncPtr)
+
+
+def test_binding_covers_every_header_symbol():
+    assert sorted(gfr.SIGNATURES) == header_functions()
+
+
+def test_library_has_no_oracle_dependency():
+    # the product library must not link or embed the oracle
+    data = open(gfr.LIB_PATH, "rb").read()
+    assert b"or_bfs" not in data and b"liboracle" not in data
+
+
+def test_validate_accepts_generated_graphs():
+    row, col = graphgen.rmat(10)
+    w = graphgen.weights(row, col)
+    ok, why = gfr.validate_csr(row, col, w)
+    assert ok, why
+    row, col = graphgen.grid(32)
+    assert gfr.validate_csr(row, col)[0]
+
+
+@pytest.mark.parametrize("case", ["asym", "loop", "dup", "unsorted", "range", "offsets", "wasym"])
+def test_validate_rejects(case):
+    row = np.array([0, 2, 3, 4], np.int32)
+    col = np.array([1, 2, 0, 0], np.int32)
+    w = np.array([5, 6, 5, 6], np.uint32)
+    assert gfr.validate_csr(row, col, w)[0]
+    if case == "asym":
+        row, col = np.array([0, 1, 1, 1], np.int32), np.array([1], np.int32)
+        w = None
+    elif case == "loop":
+        row, col, w = np.array([0, 1, 1], np.int32), np.array([0], np.int32), None
+    elif case == "dup":
+        row, col, w = np.array([0, 2, 4], np.int32), np.array([1, 1, 0, 0], np.int32), None
+    elif case == "unsorted":
+        row = np.array([0, 2, 3, 4], np.int32)
+        col = np.array([2, 1, 0, 0], np.int32)
+        w = None
+    elif case == "range":
+        col = np.array([1, 7, 0, 0], np.int32)
+    elif case == "offsets":
+        row = np.array([0, 3, 2, 4], np.int32)
+    elif case == "wasym":
+        w = np.array([5, 6, 5, 7], np.uint32)
+    ok, why = gfr.validate_csr(row, col, w)
+    assert not ok and why
+
+
+def test_structural_checks_without_validate_flag():
+    row = np.array([0, 1, 1, 1], np.int32)
+    col = np.array([1], np.int32)
+    assert gfr.validate_csr(row, col, validate=False)[0]          # asymmetric passes the basic check
+    assert not gfr.validate_csr(np.array([1, 1], np.int32), np.zeros(0, np.int32), validate=False)[0]

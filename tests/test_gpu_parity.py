@@ -1,0 +1,310 @@
+"""GPU parity: the HIP engine (through the C ABI) against the CPU oracle on the
+same seeded inputs.  BFS depths, SSSP distances and CC labels must match bit
+for bit; BC within 1e-5 relative; FP32 PageRank within 1e-6 L1 of the FP64
+oracle run for the same number of iterations.
+
+Sizes span several load-balancing chunks and ragged tails; the edge cases
+cover isolated and degree-zero sources, hubs larger than one chunk, graphs
+without edges, many components and long thin frontiers.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1501_05387_amd as gfr
+    c = gfr.Context(0)
+    yield c
+    c.close()
+
+
+def _host(t):
+    import torch
+    if isinstance(t, torch.Tensor):
+        return t.cpu().numpy()
+    return t
+
+
+def _load(ctx, row, col, w=None):
+    return ctx.graph_load_csr(row, col, w)
+
+
+def _star(k):
+    return graphgen.from_edges(k + 1, np.zeros(k, np.int32), np.arange(1, k + 1))
+
+
+def _path(n):
+    return graphgen.from_edges(n, np.arange(n - 1), np.arange(1, n))
+
+
+GRAPHS = {
+    "rmat12": lambda: graphgen.rmat(12),
+    "rmat16": lambda: graphgen.rmat(16),
+    "grid96": lambda: graphgen.grid(96),
+    "star5000": lambda: _star(5000),
+    "path3000": lambda: _path(3000),
+    "forest": lambda: graphgen.from_edges(2000, np.arange(0, 1998, 2), np.arange(1, 1999, 2)),
+}
+
+_cache = {}
+
+
+def graph(name):
+    if name not in _cache:
+        row, col = GRAPHS[name]()
+        w = graphgen.weights(row, col, 1000 if name.startswith("grid") else 64)
+        _cache[name] = (row, col, w)
+    return _cache[name]
+
+
+def _sources(row, col, k, seed=3):
+    n = row.size - 1
+    try:
+        s = list(graphgen.sample_sources(row, col, min(k, 4), seed=seed))
+    except ValueError:
+        s = []
+    s += [0, n - 1]
+    deg = np.diff(row)
+    iso = np.nonzero(deg == 0)[0]
+    if iso.size:
+        s.append(int(iso[0]))
+    return sorted(set(int(x) for x in s))
+
+
+# -------------------------------------------------------------------- BFS
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("direction", [0, 1, 2])
+def test_bfs_matches_oracle(ctx, name, direction):
+    row, col, w = graph(name)
+    g = _load(ctx, row, col)
+    ctx.set_option("bfs.direction", direction)
+    try:
+        for s in _sources(row, col, 4):
+            _say("bfs", name, "dir", direction, "src", s)
+            got = _host(ctx.bfs(g, s))
+            want = oracle.bfs(row, col, s)
+            assert np.array_equal(got, want), (name, direction, s, int(np.sum(got != want)))
+    finally:
+        ctx.set_option("bfs.direction", 0)
+        g.free()
+
+
+def test_bfs_rmat16_from_vertex0_all_chunks(ctx):
+    row, col, _ = graph("rmat16")
+    g = _load(ctx, row, col)
+    want = oracle.bfs(row, col, 0)
+    try:
+        for ch in (256, 512, 1024, 2048, 4096):
+            ctx.set_option("advance.chunk", ch)
+            _say("bfs rmat16 src0 chunk", ch)
+            assert np.array_equal(_host(ctx.bfs(g, 0)), want)
+    finally:
+        ctx.set_option("advance.chunk", 1024)
+        g.free()
+
+
+def test_bfs_host_output_and_stats(ctx):
+    row, col, _ = graph("rmat12")
+    g = _load(ctx, row, col)
+    out = np.empty(row.size - 1, np.int32)
+    ctx.bfs(g, 0, out=out)
+    assert np.array_equal(out, oracle.bfs(row, col, 0))
+    assert ctx.stat("levels") >= 2
+    assert ctx.stat("kernel_ms") > 0
+    g.free()
+
+
+# ------------------------------------------------------------------- SSSP
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("delta", [0, 1, 7, 100000])
+def test_sssp_matches_oracle(ctx, name, delta):
+    row, col, w = graph(name)
+    g = _load(ctx, row, col, w)
+    ctx.set_option("sssp.delta", delta)
+    try:
+        for s in _sources(row, col, 4):
+            _say("sssp", name, "delta", delta, "src", s)
+            got = _host(ctx.sssp(g, s)).view(np.uint32)
+            want = oracle.sssp(row, col, w, s)
+            assert np.array_equal(got, want), (name, delta, s, int(np.sum(got != want)))
+    finally:
+        ctx.set_option("sssp.delta", 0)
+        g.free()
+
+
+def test_sssp_chunks(ctx):
+    row, col, w = graph("rmat16")
+    g = _load(ctx, row, col, w)
+    want = oracle.sssp(row, col, w, 0)
+    try:
+        for ch in (256, 4096):
+            ctx.set_option("advance.chunk", ch)
+            _say("sssp rmat16 chunk", ch)
+            assert np.array_equal(_host(ctx.sssp(g, 0)).view(np.uint32), want)
+    finally:
+        ctx.set_option("advance.chunk", 1024)
+        g.free()
+
+
+def test_sssp_rejects_unweighted_and_overflow(ctx):
+    import paper_1501_05387_amd as gfr
+    row, col = _path(10)
+    g = _load(ctx, row, col)
+    with pytest.raises(gfr.GfrError):
+        ctx.sssp(g, 0)
+    g.free()
+    w = np.full(col.size, 0x7FFFFFFF, np.uint32)
+    g = _load(ctx, row, col, w)
+    with pytest.raises(gfr.GfrError) as ei:
+        ctx.sssp(g, 0)
+    assert ei.value.status == gfr.GFR_E_INVALID
+    g.free()
+
+
+# --------------------------------------------------------------------- CC
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_cc_matches_oracle(ctx, name):
+    row, col, _ = graph(name)
+    g = _load(ctx, row, col)
+    _say("cc", name)
+    lab, k = ctx.cc(g)
+    want, kw = oracle.cc(row, col)
+    assert np.array_equal(_host(lab), want)
+    assert k == kw
+    g.free()
+
+
+# --------------------------------------------------------------------- PR
+@pytest.mark.parametrize("name", ["rmat12", "rmat16", "grid96", "star5000", "forest"])
+def test_pagerank_matches_oracle(ctx, name):
+    row, col, _ = graph(name)
+    g = _load(ctx, row, col)
+    _say("pagerank", name)
+    x, it, l1 = ctx.pagerank(g, 0.85, 1e-6, 1000)
+    x = _host(x).astype(np.float64)
+    xo, ito, _ = oracle.pagerank(row, col, 0.85, 0.0, it)      # the oracle at the GPU's iteration count
+    err = np.abs(x - xo).sum()
+    _say("pagerank", name, "iters", it, "L1 err", err)
+    assert err <= 1e-6, err
+    assert abs(x.sum() - 1.0) < 1e-5
+    assert l1 < 1e-6 and it < 1000
+    _, it_ref, _ = oracle.pagerank(row, col, 0.85, 1e-6, 1000)
+    assert abs(it - it_ref) <= 1
+    g.free()
+
+
+def test_pagerank_max_iter(ctx):
+    row, col, _ = graph("rmat12")
+    g = _load(ctx, row, col)
+    x, it, l1 = ctx.pagerank(g, 0.85, 0.0, 5)
+    assert it == 5
+    xo, _, _ = oracle.pagerank(row, col, 0.85, 0.0, 5)
+    assert np.abs(_host(x) - xo).sum() <= 1e-6
+    g.free()
+
+
+# --------------------------------------------------------------------- BC
+@pytest.mark.parametrize("name", ["rmat12", "grid96", "star5000", "path3000", "forest"])
+def test_bc_matches_oracle(ctx, name):
+    row, col, _ = graph(name)
+    n = row.size - 1
+    src = np.array(_sources(row, col, 4)[:6], np.int32)
+    g = _load(ctx, row, col)
+    _say("bc", name, "sources", src.tolist())
+    got = _host(ctx.bc(g, src)).astype(np.float64)
+    want = oracle.bc(row, col, src)
+    nz = want != 0
+    rel = np.abs(got[nz] - want[nz]) / np.abs(want[nz])
+    assert np.all(got[~nz] == 0)
+    assert rel.size == 0 or rel.max() <= 1e-5, rel.max()
+    g.free()
+
+
+def test_bc_rejects_duplicates(ctx):
+    import paper_1501_05387_amd as gfr
+    row, col, _ = graph("rmat12")
+    g = _load(ctx, row, col)
+    with pytest.raises(gfr.GfrError):
+        ctx.bc(g, [1, 1])
+    g.free()
+
+
+# ------------------------------------------------------------ edge cases
+def test_graph_without_edges(ctx):
+    row = np.zeros(6, np.int32)
+    col = np.zeros(0, np.int32)
+    g = ctx.graph_load_csr(row, col, np.zeros(0, np.uint32))
+    d = _host(ctx.bfs(g, 2))
+    assert d.tolist() == [-1, -1, 0, -1, -1]
+    s = _host(ctx.sssp(g, 4)).view(np.uint32)
+    assert s[4] == 0 and np.all(s[:4] == 0xFFFFFFFF)
+    lab, k = ctx.cc(g)
+    assert _host(lab).tolist() == list(range(5)) and k == 5
+    x, it, _ = ctx.pagerank(g)
+    assert np.allclose(_host(x), 0.2)
+    g.free()
+
+
+def test_single_vertex(ctx):
+    g = ctx.graph_load_csr(np.zeros(2, np.int32), np.zeros(0, np.int32))
+    assert _host(ctx.bfs(g, 0)).tolist() == [0]
+    assert _host(ctx.bc(g, [0])).tolist() == [0.0]
+    g.free()
+
+
+def test_bad_arguments(ctx):
+    import paper_1501_05387_amd as gfr
+    row, col, _ = graph("rmat12")
+    g = _load(ctx, row, col)
+    for call in (lambda: ctx.bfs(g, -1), lambda: ctx.bfs(g, row.size - 1),
+                 lambda: ctx.pagerank(g, 1.5), lambda: ctx.set_option("nope", 1),
+                 lambda: ctx.set_option("advance.chunk", 300)):
+        with pytest.raises(gfr.GfrError) as ei:
+            call()
+        assert ei.value.status == gfr.GFR_E_INVALID
+    g.free()
+    with pytest.raises(gfr.GfrError) as ei:
+        ctx.bfs(g, 0)
+    assert ei.value.status == gfr.GFR_E_NOT_FOUND
+
+
+def test_determinism(ctx):
+    row, col, w = graph("rmat16")
+    g = _load(ctx, row, col, w)
+    a = [_host(ctx.sssp(g, 5)).copy() for _ in range(2)]
+    assert np.array_equal(a[0], a[1])
+    p = [_host(ctx.pagerank(g)[0]).copy() for _ in range(2)]
+    assert np.array_equal(p[0], p[1])
+    l = [_host(ctx.cc(g)[0]).copy() for _ in range(2)]
+    assert np.array_equal(l[0], l[1])
+    g.free()
+
+
+# ---------------------------------------------------------------- batching
+def test_batch_equals_single(ctx):
+    row, col, w = graph("rmat12")
+    n = row.size - 1
+    g = _load(ctx, row, col, w)
+    src = np.array([0, 5, 5, 17, n - 1], np.int32)
+    _say("bfs_batch / sssp_batch")
+    d = _host(ctx.bfs_batch(g, src)).reshape(len(src), n)
+    s = _host(ctx.sssp_batch(g, src)).view(np.uint32).reshape(len(src), n)
+    for i, x in enumerate(src):
+        assert np.array_equal(d[i], oracle.bfs(row, col, x))
+        assert np.array_equal(s[i], oracle.sssp(row, col, w, x))
+    g.free()
