@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark: BFS + SSSP from 64 sources on an R-MAT scale-22 graph.
+
+Workload (one "step"): a BFS and an SSSP from each of 64 sources drawn
+uniformly from the largest component of a seeded R-MAT graph (scale 22, edge
+factor 16, (a,b,c,d) = (0.57,0.19,0.19,0.05), symmetrised, simple, int32 CSR,
+uint32 weights uniform in [1,64]).  Inputs are synthetic and resident in HBM
+before timing; outputs (64 x n depths and 64 x n distances) are written to
+device buffers.
+
+value = GTEPS over the step: for every solve, the sum of the degrees of the
+vertices it reaches (the paper's directed-edge convention), summed over all
+128 solves and divided by the step time.
+
+The JSON line also carries:
+  roofline      the dominant kernel's algorithmic bytes per launch / its
+                average launch time (HIP events on the launch stream, in a
+                second pass over the same steps), against 8 TB/s HBM peak
+  cpu_baseline  the CPU oracle (1 thread) on a bounded sample of the work
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_digest() -> str:
+    d = os.path.join(ROOT, "paper_1501_05387_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def bfs_bytes(st: dict, solves: int, n: int) -> float:
+    """Algorithmic bytes of bfs_level over `solves` BFS (traffic model of the design notes)."""
+    push = 12 * st["push_entries"] + 8 * st["push_edges"] + 16 * st["push_new"]
+    pull = (n / 4.0) * st["pull_levels"] + 8 * st["pull_unvisited"] + 8 * st["pull_inspected"] \
+        + 16 * st["pull_new"]
+    return push + pull
+
+
+def sssp_bytes(st: dict) -> float:
+    """Algorithmic bytes of sssp_relax: per near entry its queue slot and distance (16 B),
+    per relaxed edge column, weight and target distance (12 B), per improvement one
+    atomic read-modify-write of the distance and one mark (8 B)."""
+    return 16 * st["near_entries"] + 12 * st["relaxations"] + 8 * st["improvements"]
+
+
+STAT_KEYS = ["push_entries", "push_edges", "push_new", "pull_levels", "pull_unvisited",
+             "pull_inspected", "pull_new", "near_entries", "relaxations", "improvements",
+             "far_entries", "iterations", "levels", "launches", "solves"]
+
+
+def read_stats(ctx, keys):
+    out = {}
+    for k in keys:
+        try:
+            out[k] = ctx.stat(k)
+        except Exception:
+            pass
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--edge-factor", type=int, default=16)
+    ap.add_argument("--sources", type=int, default=64)
+    ap.add_argument("--cpu-sources", type=int, default=1, help="oracle sample size (sources)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the engine is single-device); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import graphgen
+    import paper_1501_05387_amd as gfr
+
+    def log(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    t0 = time.time()
+    row, col = graphgen.rmat(args.scale, args.edge_factor)
+    w = graphgen.weights(row, col, 64)
+    srcs = graphgen.sample_sources(row, col, args.sources)
+    n, m = row.size - 1, col.size
+    log("graph scale %d: n=%d m=%d (%.1fs)" % (args.scale, n, m, time.time() - t0))
+
+    ctx = gfr.Context(0)
+    g = ctx.graph_load_csr(row, col, w)
+    dev = torch.device("cuda:0")
+    dep = torch.empty(args.sources * n, dtype=torch.int32, device=dev)
+    dist = torch.empty(args.sources * n, dtype=torch.int32, device=dev)
+
+    def step():
+        ctx.bfs_batch(g, srcs, out=dep)
+        ctx.sssp_batch(g, srcs, out=dist)
+
+    for i in range(args.warmup):
+        step()
+        log("warmup step %d done" % i)
+    torch.cuda.synchronize()
+
+    # edges traversed per step: each solve counts the degrees of the vertices it reaches
+    deg = torch.from_numpy(np.diff(row).astype(np.int64)).to(dev)
+    d2 = dep.view(args.sources, n)
+    te_bfs = sum(int(deg[d2[i] >= 0].sum().item()) for i in range(args.sources))
+    s2 = dist.view(args.sources, n)
+    te_sssp = sum(int(deg[s2[i] != -1].sum().item()) for i in range(args.sources))
+
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t1) / args.steps
+    value = (te_bfs + te_sssp) / t_step / 1e9
+    log("timed %d steps: %.2f ms/step, %.1f GTEPS" % (args.steps, t_step * 1e3, value))
+
+    # per-primitive split of one step (library event timing of each whole call)
+    torch.cuda.synchronize()
+    ctx.bfs_batch(g, srcs, out=dep)
+    ms_bfs = ctx.stat("kernel_ms")
+    ctx.sssp_batch(g, srcs, out=dist)
+    ms_sssp = ctx.stat("kernel_ms")
+
+    # roofline pass: per-launch HIP events around the level kernels
+    ctx.set_option("profile.kernels", 1)
+    ctx.bfs_batch(g, srcs, out=dep)
+    sb = read_stats(ctx, STAT_KEYS)
+    kb_ms, kb_n = ctx.stat("t.bfs_level.ms"), ctx.stat("t.bfs_level.n")
+    kbc_ms, kbc_n = ctx.stat("t.bfs_compact.ms"), ctx.stat("t.bfs_compact.n")
+    ctx.sssp_batch(g, srcs, out=dist)
+    ss = read_stats(ctx, STAT_KEYS)
+    ks_ms, ks_n = ctx.stat("t.sssp_relax.ms"), ctx.stat("t.sssp_relax.n")
+    ksc_ms, ksc_n = ctx.stat("t.sssp_compact.ms"), ctx.stat("t.sssp_compact.n")
+    ctx.set_option("profile.kernels", 0)
+    b_bytes = bfs_bytes(sb, args.sources, n)
+    s_bytes = sssp_bytes(ss)
+    kernels = {
+        "bfs_level": {"ms": kb_ms, "launches": kb_n, "bytes": b_bytes,
+                      "GBs": b_bytes / (kb_ms * 1e-3) / 1e9},
+        "sssp_relax": {"ms": ks_ms, "launches": ks_n, "bytes": s_bytes,
+                       "GBs": s_bytes / (ks_ms * 1e-3) / 1e9},
+        "bfs_compact": {"ms": kbc_ms, "launches": kbc_n},
+        "sssp_compact": {"ms": ksc_ms, "launches": ksc_n},
+    }
+    dom = max(("bfs_level", "sssp_relax"), key=lambda k: kernels[k]["ms"])
+    kd = kernels[dom]
+    achieved = kd["bytes"] / kd["launches"] / (kd["ms"] / kd["launches"] * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        tj = json.load(open(tfile))
+        ent = tj.get("%s/rmat%d" % (dom, args.scale))
+        if ent and ent.get("source_digest") == kernel_source_digest():
+            traffic = ent.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "bytes_per_launch": kd["bytes"] / kd["launches"],
+                "avg_launch_us": kd["ms"] / kd["launches"] * 1e3}
+    log("kernels:", json.dumps(kernels))
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        k = max(1, min(args.cpu_sources, args.sources))
+        te = 0
+        tc = 0.0
+        ok = True
+        for i in range(k):
+            s = int(srcs[i])
+            ta = time.perf_counter()
+            db = oracle.bfs(row, col, s)
+            ds = oracle.sssp(row, col, w, s)
+            tc += time.perf_counter() - ta
+            reached = db >= 0
+            te += 2 * int(np.diff(row)[reached].sum())
+            ok = ok and np.array_equal(d2[i].cpu().numpy(), db)
+            ok = ok and np.array_equal(s2[i].cpu().numpy().view(np.uint32), ds)
+        cpu = {"value": round(te / tc / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+               "sample": "queue BFS + binary-heap Dijkstra from %d of the %d sources, 1 thread, "
+                         "%.1f s" % (k, args.sources, tc)}
+        parity = ok
+        log("cpu oracle: %.3f GTEPS on %d source(s), parity %s" % (te / tc / 1e9, k, ok))
+
+    line = {
+        "metric": "BFS/SSSP GTEPS on R-MAT s22 ef16 (HBM GB/s); batched queries/s + p99 latency",
+        "value": round(value, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_step * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "rmat%d_ef%d_bfs_sssp_%dsrc" % (args.scale, args.edge_factor, args.sources),
+                   "scale": args.scale, "edge_factor": args.edge_factor, "n": n, "m": m,
+                   "sources": args.sources, "weights": "uniform[1,64]", "parallelism": "single-gpu"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": {"gteps_bfs": round(te_bfs / (ms_bfs * 1e-3) / 1e9, 3),
+                   "gteps_sssp": round(te_sssp / (ms_sssp * 1e-3) / 1e9, 3),
+                   "ms_bfs_64": round(ms_bfs, 3), "ms_sssp_64": round(ms_sssp, 3),
+                   "edges_traversed_per_step": te_bfs + te_sssp, "kernels": kernels,
+                   "parity_sample_ok": parity, "source_digest": kernel_source_digest()},
+    }
+    print(json.dumps(line), flush=True)
+    g.free()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -12,6 +12,7 @@
 // order array so the backward pass can revisit it.
 #include <vector>
 
+#include "compact.h"
 #include "engine.h"
 #include "gather.h"
 
@@ -24,11 +25,11 @@ struct BcArgs {
     uint32_t *vis;
 };
 
-// push advance of one level (load-balanced edge chunks), claims via the
-// visited bitmap, appends the new level to the next slice of the order array
+// push advance of one level (load-balanced edge chunks): claims via the
+// visited bitmap, marks the new level in the frontier bitmap `fb`
 template <int CH>
 __global__ __launch_bounds__(GFR_BLOCK) void bc_discover(BcArgs a, FrontierQ qin, uint32_t nf, uint32_t mf,
-                                                         int32_t L, FrontierQ qout, unsigned long long *ctr)
+                                                         int32_t L, uint32_t *fb)
 {
     __shared__ uint32_t s_off[CH + 1];
     __shared__ int32_t s_row[CH + 1];
@@ -47,25 +48,41 @@ __global__ __launch_bounds__(GFR_BLOCK) void bc_discover(BcArgs a, FrontierQ qin
         __syncthreads();
         for (uint32_t k = 0; k < (uint32_t)CH; k += GFR_BLOCK) {
             const uint32_t e = e0 + k + threadIdx.x;
-            int32_t v = 0, rv = 0;
-            uint32_t dv = 0;
-            bool won = false;
             if (e < e1) {
                 const int i = upper_index(s_off, 0, cnt - 1, e);
-                v = a.C[s_row[i] + (int32_t)(e - s_off[i])];
+                const int32_t v = a.C[s_row[i] + (int32_t)(e - s_off[i])];
                 const uint32_t bit = 1u << (v & 31);
                 uint32_t *w = a.vis + (v >> 5);
-                if (!(*w & bit)) won = !(atomicOr(w, bit) & bit);
-                if (won) {
+                if (!(*w & bit) && !(atomicOr(w, bit) & bit)) {
                     a.depth[v] = L + 1;
-                    rv = a.R[v];
-                    dv = (uint32_t)(a.R[v + 1] - rv);
+                    atomicOr(fb + (v >> 5), bit);
                 }
             }
-            wave_enqueue(won, v, dv, rv, ctr, qout, CH);
         }
     }
 }
+
+// compaction of one BFS level into its slice of the BFS order (vertex order)
+struct BcWords {
+    uint32_t *fb;
+    unsigned long long *out;   // packed (entries << 32 | edges) of the new level
+    uint32_t *parity;
+    __device__ bool skip() const { return false; }
+    __device__ uint32_t get(uint32_t w) const
+    {
+        const uint32_t bits = fb[w];
+        if (bits) fb[w] = 0u;
+        return bits;
+    }
+    __device__ void partial(uint32_t) {}
+    __device__ void control(uint32_t nf, uint32_t mf) const
+    {
+        if (threadIdx.x == 0) {
+            *out = ((unsigned long long)nf << 32) | mf;
+            *parity ^= 1u;
+        }
+    }
+};
 
 __global__ void bc_source_init(BcArgs a, int32_t src, FrontierQ q0, double *sigma, unsigned long long *ctr0)
 {
@@ -138,8 +155,9 @@ void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipS
     const size_t nparts = (size_t)(g.m / GATHER_CH) + 2ull * n + 4;
     const size_t nch = (size_t)(g.m / GATHER_CH) + 2;
     const size_t nlev = (size_t)n + 2;
-    c.arena.reserve(al256(4ull * n) + al256(4ull * nwords) + 3 * al256(8ull * n) + 3 * al256(4ull * n) +
-                    al256(4 * nparts) + 2 * al256(8 * nch) + al256(8 * nlev));
+    c.arena.reserve(al256(4ull * n) + 2 * al256(4ull * nwords) + 3 * al256(8ull * n) + 3 * al256(4ull * n) +
+                    al256(4 * nparts) + 2 * al256(8 * nch) + al256(8 * nlev) +
+                    al256(16ull * (uint64_t)compact_geom(nwords, c.num_cu).blocks) + al256(256));
     BcArgs a;
     a.R = g.R.as<int32_t>();
     a.C = g.C.as<int32_t>();
@@ -155,6 +173,13 @@ void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipS
     GatherScratch gs{c.arena.take<double>(nch), c.arena.take<double>(nch)};
     unsigned long long *ctr = c.arena.take<unsigned long long>(nlev);
     const int G = grid_blocks(c, 4);
+    const CompactGeom cg = compact_geom(nwords, c.num_cu);
+    uint32_t *fb = c.arena.take<uint32_t>(nwords);
+    unsigned long long *status = c.arena.take<unsigned long long>(2ull * cg.blocks);
+    uint32_t *cw = c.arena.take<uint32_t>(64);   // [0] compaction parity, [1] look-back error
+    fill_u32(fb, 0u, nwords, s);
+    fill_u32(status, 0u, 4ull * cg.blocks, s);
+    fill_u32(cw, 0u, 64, s);
 
     fill_u32(acc, 0u, 2ull * n, s);
     auto qat = [&](const Level &l) {
@@ -180,9 +205,10 @@ void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipS
             if (cur.mf == 0) break;
             Level nx{cur.start + cur.nf, 0, 0, cur.pbase + (cur.mf + GATHER_CH - 1) / GATHER_CH + 1};
             unsigned long long *cn = ctr + lv.size();
-            fill_u32(cn, 0u, 2, s);
             hipLaunchKernelGGL(bc_discover<GATHER_CH>, dim3(G), dim3(GFR_BLOCK), 0, s, a, qat(cur), cur.nf, cur.mf,
-                               L, qat(nx), cn);
+                               L, fb);
+            hipLaunchKernelGGL(compact_kernel<BcWords>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R, n, nwords, cg.wpt,
+                               BcWords{fb, cn, cw}, qat(nx), GATHER_CH, status, cw, cw + 1);
             GFR_LAUNCH_CHECK();
             GFR_HIP(hipMemcpyAsync(c.pinned, cn, 8, hipMemcpyDeviceToHost, s));
             GFR_HIP(hipStreamSynchronize(s));
@@ -219,6 +245,9 @@ void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipS
     }
     hipLaunchKernelGGL(bc_to_f32, dim3(G), dim3(GFR_BLOCK), 0, s, acc, bc, n);
     GFR_LAUNCH_CHECK();
+    GFR_HIP(hipMemcpyAsync(c.pinned, cw + 1, 4, hipMemcpyDeviceToHost, s));
+    GFR_HIP(hipStreamSynchronize(s));
+    if (c.pinned[0]) fail(GFR_E_DEVICE, "bc: frontier compaction look-back timed out");
     c.stats.v["levels"] = levels_total;
 }
 

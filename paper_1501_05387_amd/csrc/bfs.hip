@@ -1,22 +1,28 @@
 // bfs.hip -- single-source BFS: level-synchronous advance + filter with a
 // per-level push/pull choice (Sec. 4.5 "Push vs. pull traversal", Sec. 5.1).
 //
-// One kernel launch per level.  The level's direction, frontier size and edge
-// count live in a device control block that the last work-group of each level
-// rewrites, so the host can enqueue levels speculatively and only reads a
-// single word back every few launches.
-//
-// Push level (advance + filter fused): the frontier queue carries the exclusive
-// scan of its degrees and a chunk index, so every work-group takes an equal
-// slice of the frontier's edges (load-balanced partitioning, Sec. 4.4); each
-// edge tests the visited bitmap and claims the neighbour with one atomicOr
-// (the non-idempotent advance of Sec. 4.5), the winner writes depth and
-// appends the vertex to the next queue with one 64-bit atomic per wave.
-//
-// Pull level: every unvisited vertex scans its neighbour list until it finds
-// one in the current frontier bitmap (Sec. 4.5).  A wave owns 64 consecutive
-// vertices, i.e. two whole bitmap words, so visited / next-frontier words are
-// written with plain stores.
+// Every level is two launches:
+//   bfs_level   the advance.  Push: the frontier queue carries the exclusive
+//               scan of its degrees and a chunk index, so every work-group
+//               takes an equal slice of the frontier's edges (load-balanced
+//               partitioning, Sec. 4.4); each edge tests the visited bitmap
+//               and claims the neighbour (one atomicOr, the non-idempotent
+//               advance of Sec. 4.5; or, in idempotent mode, a plain test and
+//               an atomicOr whose result is ignored: duplicates write the
+//               same depth and collapse in the bitmap).  Pull: every
+//               unvisited vertex scans its list until it meets a vertex of
+//               the current frontier bitmap; a wave owns 64 consecutive
+//               vertices, i.e. two whole bitmap words, so visited and
+//               next-frontier words are written with plain stores.
+//               Either way the new frontier is a bitmap.
+//   compact     the filter: the bitmap becomes the next queue in vertex order
+//               (compact.h), and the last work-group runs the level control:
+//               stop on an empty frontier, otherwise choose push or pull from
+//               the frontier's edge count against the unvisited vertices'
+//               (the rule of Sec. 4.5, with tunable ratios alpha and beta).
+// The control state lives in device memory, so the host enqueues levels
+// speculatively and only reads one word back every few levels.
+#include "compact.h"
 #include "device.h"
 #include "engine.h"
 
@@ -25,19 +31,20 @@ namespace gfr {
 enum : uint32_t { DIR_PUSH = 0, DIR_PULL = 1, DIR_DONE = 2 };
 
 struct BfsCtl {
-    unsigned long long next;       // packed counter of the queue being built (entries<<32 | edges)
-    unsigned long long mu;         // edges incident to unvisited vertices
-    unsigned long long inspected;  // edges inspected so far
-    uint32_t dir;                  // DIR_* of the current level (first word read back by the host)
-    uint32_t nf;                   // entries of the current queue
-    uint32_t mf;                   // edges of the current queue
-    int32_t level;                 // depth of the current frontier
-    uint32_t cur;                  // parity of the current queue
-    uint32_t arrive;               // last-work-group counter
-    uint32_t nu;                   // unvisited vertices
-    uint32_t force;                // 0 auto, 1 push only, 2 pull only
+    uint32_t dir;       // DIR_* of the current level (first word: read back by the host)
+    int32_t level;      // depth of the current frontier
+    uint32_t nf, mf;    // entries / edges of the current queue
+    unsigned long long mu;  // edges incident to unvisited vertices
+    uint32_t nu;        // unvisited vertices
+    uint32_t force;     // 0 auto, 1 push only, 2 pull only
+    uint32_t dedup;     // 0 atomic claim, 1 idempotent
     float alpha, beta;
+    uint32_t parity;    // status-buffer parity of the compaction
+    uint32_t err;       // compaction look-back gave up (never expected)
     uint32_t push_levels, pull_levels;
+    // traffic model counters (summed over levels)
+    unsigned long long push_entries, push_edges, push_new;
+    unsigned long long pull_unvisited, pull_inspected, pull_new;
 };
 
 struct BfsArgs {
@@ -48,13 +55,14 @@ struct BfsArgs {
     int32_t *depth;
     uint32_t *vis;
     uint32_t *fb[3];
-    FrontierQ q[2];
+    FrontierQ q;
+    uint32_t *part_insp;   // per work-group edges inspected by a pull level
     BfsCtl *ctl;
 };
 
-__device__ __forceinline__ uint32_t *pick3(const BfsArgs &a, int i)
+__device__ __forceinline__ uint32_t *pick3(uint32_t *const *fb, int i)
 {
-    return i == 0 ? a.fb[0] : (i == 1 ? a.fb[1] : a.fb[2]);
+    return i == 0 ? fb[0] : (i == 1 ? fb[1] : fb[2]);
 }
 
 template <int CH>
@@ -64,11 +72,9 @@ __global__ __launch_bounds__(GFR_BLOCK) void bfs_level(BfsArgs a)
     const uint32_t dir = ctl->dir;
     if (dir == DIR_DONE) return;
     const int32_t L = ctl->level;
-    const uint32_t cur = ctl->cur;
-    const FrontierQ qin = a.q[cur], qout = a.q[cur ^ 1];
-    uint32_t *fb_cur = pick3(a, L % 3), *fb_next = pick3(a, (L + 1) % 3), *fb_clr = pick3(a, (L + 2) % 3);
+    uint32_t *fb_cur = pick3(a.fb, L % 3), *fb_next = pick3(a.fb, (L + 1) % 3), *fb_clr = pick3(a.fb, (L + 2) % 3);
 
-    // the bitmap of level L+2 must be empty before level L+1 starts writing it
+    // the bitmap of level L+2 must be empty before level L+1 writes it
     for (uint32_t i = blockIdx.x * GFR_BLOCK + threadIdx.x; i < a.nwords; i += gridDim.x * GFR_BLOCK)
         fb_clr[i] = 0u;
 
@@ -76,40 +82,43 @@ __global__ __launch_bounds__(GFR_BLOCK) void bfs_level(BfsArgs a)
         __shared__ uint32_t s_off[CH + 1];
         __shared__ int32_t s_row[CH + 1];
         const uint32_t mf = ctl->mf, nf = ctl->nf;
+        const bool idem = ctl->dedup != 0;
+        const FrontierQ q = a.q;
         const uint32_t nchunks = (mf + CH - 1) / CH;
         for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
             const uint32_t e0 = c * CH;
             const uint32_t e1 = min(e0 + (uint32_t)CH, mf);
-            const int s = qin.part[c];
-            const int t = (c + 1 < nchunks) ? qin.part[c + 1] : (int)nf - 1;
+            const int s = q.part[c];
+            const int t = (c + 1 < nchunks) ? q.part[c + 1] : (int)nf - 1;
             const int cnt = t - s + 1;
             __syncthreads();
             for (int i = threadIdx.x; i < cnt; i += GFR_BLOCK) {
-                s_off[i] = qin.off[s + i];
-                s_row[i] = qin.row[s + i];
+                s_off[i] = q.off[s + i];
+                s_row[i] = q.row[s + i];
             }
             __syncthreads();
-#pragma unroll 1
+#pragma unroll 2
             for (uint32_t k = 0; k < (uint32_t)CH; k += GFR_BLOCK) {
                 const uint32_t e = e0 + k + threadIdx.x;
-                const bool valid = e < e1;
-                int32_t v = 0, rv = 0;
-                uint32_t dv = 0;
-                bool won = false;
-                if (valid) {
+                if (e < e1) {
                     const int i = upper_index(s_off, 0, cnt - 1, e);
-                    v = a.C[s_row[i] + (int32_t)(e - s_off[i])];
+                    const int32_t v = a.C[s_row[i] + (int32_t)(e - s_off[i])];
                     const uint32_t bit = 1u << (v & 31);
                     uint32_t *w = a.vis + (v >> 5);
-                    if (!(*w & bit)) won = !(atomicOr(w, bit) & bit);
-                    if (won) {
-                        a.depth[v] = L + 1;
-                        atomicOr(fb_next + (v >> 5), bit);
-                        rv = a.R[v];
-                        dv = (uint32_t)(a.R[v + 1] - rv);
+                    if (!(*w & bit)) {
+                        bool won;
+                        if (idem) {
+                            atomicOr(w, bit);
+                            won = true;
+                        } else {
+                            won = !(atomicOr(w, bit) & bit);
+                        }
+                        if (won) {
+                            a.depth[v] = L + 1;
+                            atomicOr(fb_next + (v >> 5), bit);
+                        }
                     }
                 }
-                wave_enqueue(won, v, dv, rv, &ctl->next, qout, CH);
             }
         }
     } else {
@@ -120,21 +129,26 @@ __global__ __launch_bounds__(GFR_BLOCK) void bfs_level(BfsArgs a)
              grp += waves) {
             const int32_t v = (int32_t)(grp * 64u) + lane;
             const uint32_t word = grp * 2u + (uint32_t)(lane >> 5);
-            const bool inr = v < a.n;
             const uint32_t visw = a.vis[word];
-            const bool todo = inr && !(visw & (1u << (v & 31)));
             bool found = false;
-            int32_t rv = 0, re = 0;
-            if (todo) {
-                rv = a.R[v];
-                re = a.R[v + 1];
-                for (int32_t e = rv; e < re; ++e) {
-                    const int32_t u = a.C[e];
-                    ++insp;
-                    if (fb_cur[u >> 5] & (1u << (u & 31))) {
+            if (v < a.n && !(visw & (1u << (v & 31)))) {
+                int32_t e = a.R[v];
+                const int32_t re = a.R[v + 1];
+                // four independent neighbour probes per step
+                while (e < re) {
+                    const int32_t k = min(4, re - e);
+                    int32_t u[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) u[j] = a.C[j < k ? e + j : e];
+                    uint32_t hit = 0;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) hit |= (j < k) ? (fb_cur[u[j] >> 5] >> (u[j] & 31)) & 1u : 0u;
+                    insp += (uint32_t)k;
+                    if (hit) {
                         found = true;
                         break;
                     }
+                    e += 4;
                 }
             }
             const uint64_t fm = ballot(found);
@@ -144,20 +158,53 @@ __global__ __launch_bounds__(GFR_BLOCK) void bfs_level(BfsArgs a)
                 fb_next[word] = bits;
                 if (bits) a.vis[word] = visw | bits;
             }
-            wave_enqueue(found, v, (uint32_t)(re - rv), rv, &ctl->next, qout, CH);
         }
+        // per-group partial (plain store, summed by the level control)
+        __shared__ uint32_t s_insp[GFR_WAVES];
         const uint32_t tot = wave_sum_u32(insp);
-        if (lane == 0 && tot) atomicAdd(&ctl->inspected, (unsigned long long)tot);
+        if (lane == 0) s_insp[threadIdx.x / 64] = tot;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int i = 0; i < GFR_WAVES; ++i) t += s_insp[i];
+            a.part_insp[blockIdx.x] = t;
+        }
     }
+}
 
-    if (last_block_arrives(&ctl->arrive) && threadIdx.x == 0) {
-        const unsigned long long nx = atomicAdd(&ctl->next, 0ull);
-        const uint32_t nf2 = (uint32_t)(nx >> 32), mf2 = (uint32_t)nx;
+// Filter + level control for the compaction kernel.
+struct BfsWords {
+    BfsArgs a;
+    uint32_t nparts;   // work-groups of bfs_level (entries of part_insp)
+
+    __device__ bool skip() const { return a.ctl->dir == DIR_DONE; }
+    __device__ uint32_t get(uint32_t w) const { return pick3(a.fb, (a.ctl->level + 1) % 3)[w]; }
+    __device__ void partial(uint32_t) {}
+    __device__ void control(uint32_t nf2, uint32_t mf2) const
+    {
+        BfsCtl *ctl = a.ctl;
+        const uint32_t dir = ctl->dir;
+        uint32_t insp = 0;
+        if (dir == DIR_PULL) {
+            for (uint32_t i = threadIdx.x; i < nparts; i += GFR_BLOCK) insp += a.part_insp[i];
+            __shared__ uint32_t s[GFR_WAVES];
+            insp = wave_sum_u32(insp);
+            if (lane_id() == 0) s[threadIdx.x / 64] = insp;
+            __syncthreads();
+            insp = 0;
+            for (int i = 0; i < GFR_WAVES; ++i) insp += s[i];
+        }
+        if (threadIdx.x != 0) return;
         if (dir == DIR_PUSH) {
             ctl->push_levels += 1;
-            ctl->inspected += ctl->mf;
+            ctl->push_entries += ctl->nf;
+            ctl->push_edges += ctl->mf;
+            ctl->push_new += nf2;
         } else {
             ctl->pull_levels += 1;
+            ctl->pull_unvisited += ctl->nu;
+            ctl->pull_inspected += insp;
+            ctl->pull_new += nf2;
         }
         ctl->nu -= nf2;
         ctl->mu -= mf2;
@@ -171,14 +218,13 @@ __global__ __launch_bounds__(GFR_BLOCK) void bfs_level(BfsArgs a)
             nd = ((double)nf2 < (double)a.n / ctl->beta && nf2 < ctl->nf) ? DIR_PUSH : DIR_PULL;
         ctl->nf = nf2;
         ctl->mf = mf2;
-        ctl->next = 0ull;
-        ctl->level = L + 1;
-        ctl->cur = cur ^ 1u;
+        ctl->level += 1;
+        ctl->parity ^= 1u;
         ctl->dir = nd;
     }
-}
+};
 
-__global__ void bfs_init(BfsArgs a, int32_t src, uint32_t chunk, uint32_t force, float alpha,
+__global__ void bfs_init(BfsArgs a, int32_t src, uint32_t chunk, uint32_t force, uint32_t dedup, float alpha,
                          float beta, unsigned long long m)
 {
     const int32_t rs = a.R[src], deg = a.R[src + 1] - rs;
@@ -187,25 +233,26 @@ __global__ void bfs_init(BfsArgs a, int32_t src, uint32_t chunk, uint32_t force,
         a.depth[src] = 0;
         a.vis[src >> 5] = 1u << (src & 31);
         a.fb[0][src >> 5] = 1u << (src & 31);
-        a.q[0].v[0] = src;
-        a.q[0].off[0] = 0;
-        a.q[0].row[0] = rs;
-        ctl->next = 0ull;
+        a.q.v[0] = src;
+        a.q.off[0] = 0;
+        a.q.row[0] = rs;
         ctl->mu = m - (unsigned long long)deg;
-        ctl->inspected = 0ull;
         ctl->nf = 1;
         ctl->mf = (uint32_t)deg;
         ctl->level = 0;
-        ctl->cur = 0;
-        ctl->arrive = 0;
         ctl->nu = (uint32_t)a.n - 1u;
         ctl->force = force;
+        ctl->dedup = dedup;
         ctl->alpha = alpha;
         ctl->beta = beta;
+        ctl->parity = 0;
+        ctl->err = 0;
         ctl->push_levels = ctl->pull_levels = 0;
+        ctl->push_entries = ctl->push_edges = ctl->push_new = 0ull;
+        ctl->pull_unvisited = ctl->pull_inspected = ctl->pull_new = 0ull;
         ctl->dir = deg == 0 ? DIR_DONE : (force == 2 ? DIR_PULL : DIR_PUSH);
     }
-    for (uint32_t c = threadIdx.x; (uint64_t)c * chunk < (uint64_t)deg; c += blockDim.x) a.q[0].part[c] = 0;
+    for (uint32_t c = threadIdx.x; (uint64_t)c * chunk < (uint64_t)deg; c += blockDim.x) a.q.part[c] = 0;
 }
 
 void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s)
@@ -214,7 +261,10 @@ void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s)
     const uint32_t chunk = (uint32_t)c.opt.advance_chunk;
     const uint32_t nwords = (uint32_t)(((int64_t)n + 63) / 64) * 2u;
     const size_t nparts = (size_t)(g.m / chunk) + 2;
-    size_t need = 4 * al256(nwords * 4ull) + 2 * (3 * al256(4ull * n) + al256(4 * nparts)) + al256(sizeof(BfsCtl));
+    const int G = grid_blocks(c, 4);
+    const CompactGeom cg = compact_geom(nwords, c.num_cu);
+    size_t need = 4 * al256(nwords * 4ull) + 3 * al256(4ull * n) + al256(4 * nparts) + al256(4ull * G) +
+                  al256(16ull * cg.blocks) + al256(sizeof(BfsCtl));
     c.arena.reserve(need);
     BfsArgs a;
     a.R = g.R.as<int32_t>();
@@ -224,44 +274,59 @@ void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s)
     a.depth = depth;
     a.vis = c.arena.take<uint32_t>(nwords);
     for (int i = 0; i < 3; ++i) a.fb[i] = c.arena.take<uint32_t>(nwords);
-    for (int i = 0; i < 2; ++i) {
-        a.q[i].v = c.arena.take<int32_t>(n);
-        a.q[i].off = c.arena.take<uint32_t>(n);
-        a.q[i].row = c.arena.take<int32_t>(n);
-        a.q[i].part = c.arena.take<int32_t>(nparts);
-    }
+    a.q.v = c.arena.take<int32_t>(n);
+    a.q.off = c.arena.take<uint32_t>(n);
+    a.q.row = c.arena.take<int32_t>(n);
+    a.q.part = c.arena.take<int32_t>(nparts);
+    a.part_insp = c.arena.take<uint32_t>(G);
+    unsigned long long *status = c.arena.take<unsigned long long>(2ull * cg.blocks);
     a.ctl = c.arena.take<BfsCtl>(1);
 
     fill_u32(depth, 0xFFFFFFFFu, (size_t)n, s);
     fill_u32(a.vis, 0u, nwords, s);
     fill_u32(a.fb[0], 0u, nwords, s);
     fill_u32(a.fb[1], 0u, nwords, s);
-    hipLaunchKernelGGL(bfs_init, dim3(1), dim3(GFR_BLOCK), 0, s, a, src, chunk,
-                       (uint32_t)c.opt.bfs_direction, (float)c.opt.bfs_alpha, (float)c.opt.bfs_beta,
+    fill_u32(status, 0u, 4ull * cg.blocks, s);
+    hipLaunchKernelGGL(bfs_init, dim3(1), dim3(GFR_BLOCK), 0, s, a, src, chunk, (uint32_t)c.opt.bfs_direction,
+                       (uint32_t)c.opt.bfs_dedup, (float)c.opt.bfs_alpha, (float)c.opt.bfs_beta,
                        (unsigned long long)g.m);
     GFR_LAUNCH_CHECK();
 
-    const int G = grid_blocks(c, 4);
-    auto launch = [&]() { c.ktimer.run("bfs_level", s, [&]() {
-        switch (chunk) {
-        case 256: hipLaunchKernelGGL(bfs_level<256>, dim3(G), dim3(GFR_BLOCK), 0, s, a); break;
-        case 512: hipLaunchKernelGGL(bfs_level<512>, dim3(G), dim3(GFR_BLOCK), 0, s, a); break;
-        case 1024: hipLaunchKernelGGL(bfs_level<1024>, dim3(G), dim3(GFR_BLOCK), 0, s, a); break;
-        case 2048: hipLaunchKernelGGL(bfs_level<2048>, dim3(G), dim3(GFR_BLOCK), 0, s, a); break;
-        default: hipLaunchKernelGGL(bfs_level<4096>, dim3(G), dim3(GFR_BLOCK), 0, s, a); break;
-        }
-    }); };
+    BfsWords words{a, (uint32_t)G};
+    auto launch = [&]() {
+        c.ktimer.run("bfs_level", s, [&]() {
+            switch (chunk) {
+            case 256: hipLaunchKernelGGL(bfs_level<256>, dim3(G), dim3(GFR_BLOCK), 0, s, a); break;
+            case 512: hipLaunchKernelGGL(bfs_level<512>, dim3(G), dim3(GFR_BLOCK), 0, s, a); break;
+            case 1024: hipLaunchKernelGGL(bfs_level<1024>, dim3(G), dim3(GFR_BLOCK), 0, s, a); break;
+            case 2048: hipLaunchKernelGGL(bfs_level<2048>, dim3(G), dim3(GFR_BLOCK), 0, s, a); break;
+            default: hipLaunchKernelGGL(bfs_level<4096>, dim3(G), dim3(GFR_BLOCK), 0, s, a); break;
+            }
+        });
+        c.ktimer.run("bfs_compact", s, [&]() {
+            hipLaunchKernelGGL(compact_kernel<BfsWords>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R, n, nwords,
+                               cg.wpt, words, a.q, chunk, status, &a.ctl->parity, &a.ctl->err);
+        });
+    };
     const int32_t launched = run_until_done(c, &a.ctl->dir, DIR_DONE, g.bfs_levels_hint + 1,
                                             (int64_t)n + 4, s, launch);
     BfsCtl h;
     GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
     GFR_HIP(hipStreamSynchronize(s));
     memcpy(&h, c.pinned, sizeof(BfsCtl));
-    c.stats.v["levels"] = h.level;
-    c.stats.v["push_levels"] = h.push_levels;
-    c.stats.v["pull_levels"] = h.pull_levels;
-    c.stats.v["edges_inspected"] = (double)h.inspected;
-    c.stats.v["launches"] = launched;
+    if (h.err) fail(GFR_E_DEVICE, "bfs: frontier compaction look-back timed out");
+    c.stats.v["levels"] += h.level;
+    c.stats.v["push_levels"] += h.push_levels;
+    c.stats.v["pull_levels"] += h.pull_levels;
+    c.stats.v["edges_inspected"] += (double)(h.push_edges + h.pull_inspected);
+    c.stats.v["push_entries"] += (double)h.push_entries;
+    c.stats.v["push_edges"] += (double)h.push_edges;
+    c.stats.v["push_new"] += (double)h.push_new;
+    c.stats.v["pull_unvisited"] += (double)h.pull_unvisited;
+    c.stats.v["pull_inspected"] += (double)h.pull_inspected;
+    c.stats.v["pull_new"] += (double)h.pull_new;
+    c.stats.v["launches"] += launched;
+    c.stats.v["solves"] += 1.0;
     g.bfs_levels_hint = h.level;
 }
 

@@ -97,24 +97,48 @@ __global__ __launch_bounds__(GFR_BLOCK) void cc_hook_list(int32_t *label, const 
     }
 }
 
-__global__ __launch_bounds__(GFR_BLOCK) void cc_count_roots(const int32_t *label, int32_t n, uint32_t *roots)
+// per-group root counts (plain stores), summed by cc_sum
+__global__ __launch_bounds__(GFR_BLOCK) void cc_count_roots(const int32_t *label, int32_t n, uint32_t *part)
 {
     uint32_t r = 0;
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
         r += (label[v] == v);
+    __shared__ uint32_t s[GFR_WAVES];
     r = wave_sum_u32(r);
-    if (lane_id() == 0 && r) atomicAdd(roots, r);
+    if (lane_id() == 0) s[threadIdx.x / 64] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int i = 0; i < GFR_WAVES; ++i) t += s[i];
+        part[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(GFR_BLOCK) void cc_sum(const uint32_t *part, uint32_t nparts, uint32_t *out)
+{
+    uint32_t r = 0;
+    for (uint32_t i = threadIdx.x; i < nparts; i += GFR_BLOCK) r += part[i];
+    __shared__ uint32_t s[GFR_WAVES];
+    r = wave_sum_u32(r);
+    if (lane_id() == 0) s[threadIdx.x / 64] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int i = 0; i < GFR_WAVES; ++i) t += s[i];
+        *out = t;
+    }
 }
 
 void run_cc(Ctx &c, Graph &g, int32_t *label, int32_t *ncomp, hipStream_t s)
 {
     const int32_t n = g.n;
     const size_t cap = (size_t)(g.m / 2) + 1;
-    c.arena.reserve(2 * al256(8 * cap) + al256(4 * 64));
+    const int G = grid_blocks(c, 4);
+    c.arena.reserve(2 * al256(8 * cap) + al256(4 * 64) + al256(4ull * G));
     int2 *list[2] = {c.arena.take<int2>(cap), c.arena.take<int2>(cap)};
     uint32_t *ctr = c.arena.take<uint32_t>(64);   // [round] kept counters, [63] roots
+    uint32_t *rpart = c.arena.take<uint32_t>(G);
     fill_u32(ctr, 0u, 64, s);
-    const int G = grid_blocks(c, 4);
     hipLaunchKernelGGL(cc_init, dim3(G), dim3(GFR_BLOCK), 0, s, label, n);
     const int32_t *C = g.C.as<int32_t>();
     // round 1: hook over the full CSR, no compaction
@@ -142,7 +166,8 @@ void run_cc(Ctx &c, Graph &g, int32_t *label, int32_t *ncomp, hipStream_t s)
         GFR_LAUNCH_CHECK();
         ++rounds;
     }
-    hipLaunchKernelGGL(cc_count_roots, dim3(G), dim3(GFR_BLOCK), 0, s, label, n, ctr + 63);
+    hipLaunchKernelGGL(cc_count_roots, dim3(G), dim3(GFR_BLOCK), 0, s, label, n, rpart);
+    hipLaunchKernelGGL(cc_sum, dim3(1), dim3(GFR_BLOCK), 0, s, rpart, (uint32_t)G, ctr + 63);
     GFR_LAUNCH_CHECK();
     GFR_HIP(hipMemcpyAsync(c.pinned, ctr + 63, 4, hipMemcpyDeviceToHost, s));
     GFR_HIP(hipStreamSynchronize(s));

@@ -98,68 +98,6 @@ struct FrontierQ {
     int32_t *part;
 };
 
-// Append (v, degree, row start) for every lane with `valid`, wave-aggregated.
-// `packed` is the queue's counter: high 32 bits = entries, low 32 bits = edges.
-// One 64-bit atomic per wave reserves consecutive slots AND the matching edge
-// range, so the offsets are an exact exclusive scan in slot order.
-__device__ __forceinline__ void wave_enqueue(bool valid, int32_t v, uint32_t deg, int32_t rowstart,
-                                             unsigned long long *packed, FrontierQ q, uint32_t chunk)
-{
-    const uint64_t mask = ballot(valid && deg > 0);
-    if (mask == 0) return;
-    const bool mine = valid && deg > 0;
-    const uint32_t e = mine ? deg : 0u;
-    const uint32_t incl = wave_incl_scan(e);
-    const uint32_t total = shfl_u32(incl, 63);
-    const int leader = __ffsll((unsigned long long)mask) - 1;
-    unsigned long long base = 0;
-    if (lane_id() == leader)
-        base = atomicAdd(packed, ((unsigned long long)__popcll(mask) << 32) | (unsigned long long)total);
-    base = shfl_u64(base, leader);
-    if (mine) {
-        const uint32_t slot = (uint32_t)(base >> 32) + lanes_below(mask);
-        const uint32_t o = (uint32_t)base + incl - e;
-        q.v[slot] = v;
-        q.off[slot] = o;
-        q.row[slot] = rowstart;
-        // chunk starts inside [o, o+deg)
-        for (uint32_t c = (o + chunk - 1) / chunk; c * (uint64_t)chunk < (uint64_t)o + deg; ++c)
-            q.part[c] = (int32_t)slot;
-    }
-}
-
-// Plain wave-aggregated append of ids (no offsets); returns nothing.
-__device__ __forceinline__ void wave_append(bool valid, int32_t v, uint32_t *count, int32_t *out)
-{
-    const uint64_t mask = ballot(valid);
-    if (mask == 0) return;
-    const int leader = __ffsll((unsigned long long)mask) - 1;
-    uint32_t base = 0;
-    if (lane_id() == leader) base = atomicAdd(count, (uint32_t)__popcll(mask));
-    base = shfl_u32(base, leader);
-    if (valid) out[base + lanes_below(mask)] = v;
-}
-
-// Last-work-group detection: every work-group calls this once at its end;
-// exactly one (the last to arrive) gets true, after a device-scope fence, and
-// may then read what all other groups produced.  Resets the counter.
-__device__ __forceinline__ bool last_block_arrives(uint32_t *counter)
-{
-    __shared__ bool is_last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t t = atomicAdd(counter, 1u);
-        is_last = (t == gridDim.x - 1);
-        if (is_last) {
-            *counter = 0;
-            __threadfence();
-        }
-    }
-    __syncthreads();
-    return is_last;
-}
-
 // Largest i in [lo, hi] with a[i] <= key (a sorted ascending, a[lo] <= key).
 __device__ __forceinline__ int upper_index(const uint32_t *a, int lo, int hi, uint32_t key)
 {

@@ -19,7 +19,7 @@ struct PrCtl {
     uint32_t done;      // first word: read back by the host
     uint32_t iters;
     uint32_t max_iter;
-    uint32_t arrive;
+    uint32_t pad;
     double D;           // rank held by zero-degree vertices, current iterate
     double l1;          // L1 change of the last iteration
     double tol;
@@ -74,14 +74,36 @@ __global__ __launch_bounds__(GFR_BLOCK) void pr_init(const int32_t *R, int32_t n
         else dang += (double)xv;
     }
     block_sum2(dang, zero);
-    if (threadIdx.x == 0) part[2 * blockIdx.x] = dang;
-    if (last_block_arrives(&ctl->arrive) && threadIdx.x == 0) {
-        double D = 0.0;
-        for (uint32_t b = 0; b < gridDim.x; ++b) D += part[2 * b];
-        ctl->D = D;
-        ctl->iters = 0;
-        ctl->l1 = 0.0;
-        ctl->done = 0;
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = 0.0;
+        part[2 * blockIdx.x + 1] = dang;
+    }
+}
+
+// One work-group: reduce the per-group partials of pr_init / pr_finalize in a
+// fixed order and run the iteration control.  first != 0: after pr_init.
+__global__ __launch_bounds__(GFR_BLOCK) void pr_reduce(const double *part, uint32_t nparts, PrCtl *ctl,
+                                                       uint32_t first)
+{
+    if (!first && ctl->done) return;
+    double l1 = 0.0, dang = 0.0;
+    for (uint32_t b = threadIdx.x; b < nparts; b += GFR_BLOCK) {
+        l1 += part[2 * b];
+        dang += part[2 * b + 1];
+    }
+    block_sum2(l1, dang);
+    if (threadIdx.x == 0) {
+        ctl->D = dang;
+        if (first) {
+            ctl->iters = 0;
+            ctl->l1 = 0.0;
+            ctl->done = 0;
+        } else {
+            const uint32_t k = ctl->iters + 1;
+            ctl->iters = k;
+            ctl->l1 = l1;
+            if ((ctl->tol > 0.0 && l1 < ctl->tol) || k >= ctl->max_iter) ctl->done = 1;
+        }
     }
 }
 
@@ -110,17 +132,6 @@ __global__ __launch_bounds__(GFR_BLOCK) void pr_finalize(const int32_t *R, int32
         part[2 * blockIdx.x] = l1;
         part[2 * blockIdx.x + 1] = dang;
     }
-    if (last_block_arrives(&ctl->arrive) && threadIdx.x == 0) {
-        double L = 0.0, D = 0.0;
-        for (uint32_t b = 0; b < gridDim.x; ++b) {
-            L += part[2 * b];
-            D += part[2 * b + 1];
-        }
-        ctl->l1 = L;
-        ctl->D = D;
-        ctl->iters = k + 1;
-        if ((ctl->tol > 0.0 && L < ctl->tol) || k + 1 >= ctl->max_iter) ctl->done = 1;
-    }
 }
 
 void run_pagerank(Ctx &c, Graph &g, float damping, double tol, int32_t max_iter, float *rank,
@@ -145,6 +156,7 @@ void run_pagerank(Ctx &c, Graph &g, float damping, double tol, int32_t max_iter,
     h.damping = damping;
     GFR_HIP(hipMemcpyAsync(ctl, &h, sizeof h, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(pr_init, dim3(G), dim3(GFR_BLOCK), 0, s, g.R.as<int32_t>(), n, xa, contrib, part, ctl);
+    hipLaunchKernelGGL(pr_reduce, dim3(1), dim3(GFR_BLOCK), 0, s, part, (uint32_t)G, ctl, 1u);
     GFR_LAUNCH_CHECK();
 
     PrOp op{contrib};
@@ -157,6 +169,7 @@ void run_pagerank(Ctx &c, Graph &g, float damping, double tol, int32_t max_iter,
                            g.full_counts, g.full_counts + 1, fin, gs, &ctl->done);
         hipLaunchKernelGGL(pr_finalize, dim3(G), dim3(GFR_BLOCK), 0, s, g.R.as<int32_t>(), n, xa, xb, contrib,
                            sum, part, ctl);
+        hipLaunchKernelGGL(pr_reduce, dim3(1), dim3(GFR_BLOCK), 0, s, part, (uint32_t)G, ctl, 0u);
     };
     const int32_t first = max_iter < 8 ? max_iter : 8;
     run_until_done(c, &ctl->done, 1u, first, (int64_t)max_iter + 8, s, launch);
