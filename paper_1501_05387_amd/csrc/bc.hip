@@ -25,11 +25,12 @@ struct BcArgs {
     uint32_t *vis;
 };
 
-// push advance of one level (load-balanced edge chunks): claims via the
-// visited bitmap, marks the new level in the frontier bitmap `fb`
+// push advance of one level (load-balanced edge chunks): an unvisited
+// neighbour gets its depth and a mark byte (plain stores; duplicates write
+// the same values and collapse in the compaction)
 template <int CH>
 __global__ __launch_bounds__(GFR_BLOCK) void bc_discover(BcArgs a, FrontierQ qin, uint32_t nf, uint32_t mf,
-                                                         int32_t L, uint32_t *fb)
+                                                         int32_t L, uint8_t *mark)
 {
     __shared__ uint32_t s_off[CH + 1];
     __shared__ int32_t s_row[CH + 1];
@@ -51,11 +52,9 @@ __global__ __launch_bounds__(GFR_BLOCK) void bc_discover(BcArgs a, FrontierQ qin
             if (e < e1) {
                 const int i = upper_index(s_off, 0, cnt - 1, e);
                 const int32_t v = a.C[s_row[i] + (int32_t)(e - s_off[i])];
-                const uint32_t bit = 1u << (v & 31);
-                uint32_t *w = a.vis + (v >> 5);
-                if (!(*w & bit) && !(atomicOr(w, bit) & bit)) {
+                if (!((a.vis[v >> 5] >> (v & 31)) & 1u) && !mark[v]) {
                     a.depth[v] = L + 1;
-                    atomicOr(fb + (v >> 5), bit);
+                    mark[v] = 1;
                 }
             }
         }
@@ -63,16 +62,20 @@ __global__ __launch_bounds__(GFR_BLOCK) void bc_discover(BcArgs a, FrontierQ qin
 }
 
 // compaction of one BFS level into its slice of the BFS order (vertex order)
-struct BcWords {
-    uint32_t *fb;
+struct BcMarks {
+    uint8_t *mark;
+    uint32_t *vis;
     unsigned long long *out;   // packed (entries << 32 | edges) of the new level
     uint32_t *parity;
     __device__ bool skip() const { return false; }
-    __device__ uint32_t get(uint32_t w) const
+    __device__ uint32_t mask(uint32_t w) const
     {
-        const uint32_t bits = fb[w];
-        if (bits) fb[w] = 0u;
-        return bits;
+        const uint32_t m = marks_to_mask(mark + 32ull * w);
+        if (m) {
+            clear_marks(mark + 32ull * w);
+            vis[w] |= m;
+        }
+        return m;
     }
     __device__ void partial(uint32_t) {}
     __device__ void control(uint32_t nf, uint32_t mf) const
@@ -155,7 +158,7 @@ void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipS
     const size_t nparts = (size_t)(g.m / GATHER_CH) + 2ull * n + 4;
     const size_t nch = (size_t)(g.m / GATHER_CH) + 2;
     const size_t nlev = (size_t)n + 2;
-    c.arena.reserve(al256(4ull * n) + 2 * al256(4ull * nwords) + 3 * al256(8ull * n) + 3 * al256(4ull * n) +
+    c.arena.reserve(al256(4ull * n) + al256(4ull * nwords) + al256(32ull * nwords) + 3 * al256(8ull * n) + 3 * al256(4ull * n) +
                     al256(4 * nparts) + 2 * al256(8 * nch) + al256(8 * nlev) +
                     al256(16ull * (uint64_t)compact_geom(nwords, c.num_cu).blocks) + al256(256));
     BcArgs a;
@@ -174,10 +177,10 @@ void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipS
     unsigned long long *ctr = c.arena.take<unsigned long long>(nlev);
     const int G = grid_blocks(c, 4);
     const CompactGeom cg = compact_geom(nwords, c.num_cu);
-    uint32_t *fb = c.arena.take<uint32_t>(nwords);
+    uint8_t *mark = c.arena.take<uint8_t>(32ull * nwords);
     unsigned long long *status = c.arena.take<unsigned long long>(2ull * cg.blocks);
     uint32_t *cw = c.arena.take<uint32_t>(64);   // [0] compaction parity, [1] look-back error
-    fill_u32(fb, 0u, nwords, s);
+    fill_u32(mark, 0u, 8ull * nwords, s);
     fill_u32(status, 0u, 4ull * cg.blocks, s);
     fill_u32(cw, 0u, 64, s);
 
@@ -206,9 +209,9 @@ void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipS
             Level nx{cur.start + cur.nf, 0, 0, cur.pbase + (cur.mf + GATHER_CH - 1) / GATHER_CH + 1};
             unsigned long long *cn = ctr + lv.size();
             hipLaunchKernelGGL(bc_discover<GATHER_CH>, dim3(G), dim3(GFR_BLOCK), 0, s, a, qat(cur), cur.nf, cur.mf,
-                               L, fb);
-            hipLaunchKernelGGL(compact_kernel<BcWords>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R, n, nwords, cg.wpt,
-                               BcWords{fb, cn, cw}, qat(nx), GATHER_CH, status, cw, cw + 1);
+                               L, mark);
+            hipLaunchKernelGGL(compact_kernel<BcMarks>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R, n, nwords, cg.wpt,
+                               BcMarks{mark, a.vis, cn, cw}, qat(nx), GATHER_CH, status, cw, cw + 1);
             GFR_LAUNCH_CHECK();
             GFR_HIP(hipMemcpyAsync(c.pinned, cn, 8, hipMemcpyDeviceToHost, s));
             GFR_HIP(hipStreamSynchronize(s));

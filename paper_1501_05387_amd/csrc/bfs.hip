@@ -6,17 +6,18 @@
 //               scan of its degrees and a chunk index, so every work-group
 //               takes an equal slice of the frontier's edges (load-balanced
 //               partitioning, Sec. 4.4); each edge tests the visited bitmap
-//               and claims the neighbour (one atomicOr, the non-idempotent
-//               advance of Sec. 4.5; or, in idempotent mode, a plain test and
-//               an atomicOr whose result is ignored: duplicates write the
-//               same depth and collapse in the bitmap).  Pull: every
-//               unvisited vertex scans its list until it meets a vertex of
-//               the current frontier bitmap; a wave owns 64 consecutive
-//               vertices, i.e. two whole bitmap words, so visited and
-//               next-frontier words are written with plain stores.
-//               Either way the new frontier is a bitmap.
-//   compact     the filter: the bitmap becomes the next queue in vertex order
-//               (compact.h), and the last work-group runs the level control:
+//               and, for an unvisited neighbour not yet marked, writes its
+//               depth and a mark byte with plain stores.  This is the
+//               idempotent advance of Sec. 4.5: concurrent discoverers write
+//               the same values, and the compaction removes the duplicates.
+//               (With bfs.dedup = 0 the neighbour is first claimed with an
+//               atomicOr on the visited bitmap, the non-idempotent form.)
+//               Pull: every unvisited vertex scans its list until it meets a
+//               vertex of the current frontier bitmap.
+//               Either way the new frontier is a byte array of marks.
+//   compact     the filter: the marks become the next queue in vertex order
+//               and the next frontier bitmap, visited is updated (compact.h),
+//               and the last work-group runs the level control:
 //               stop on an empty frontier, otherwise choose push or pull from
 //               the frontier's edge count against the unvisited vertices'
 //               (the rule of Sec. 4.5, with tunable ratios alpha and beta).
@@ -53,17 +54,13 @@ struct BfsArgs {
     int32_t n;
     uint32_t nwords;
     int32_t *depth;
-    uint32_t *vis;
-    uint32_t *fb[3];
+    uint32_t *vis;        // visited bitmap (updated by the compaction)
+    uint32_t *fb;         // current frontier bitmap (written by the compaction)
+    uint8_t *mark;        // next-frontier marks, one byte per vertex
     FrontierQ q;
     uint32_t *part_insp;   // per work-group edges inspected by a pull level
     BfsCtl *ctl;
 };
-
-__device__ __forceinline__ uint32_t *pick3(uint32_t *const *fb, int i)
-{
-    return i == 0 ? fb[0] : (i == 1 ? fb[1] : fb[2]);
-}
 
 template <int CH>
 __global__ __launch_bounds__(GFR_BLOCK) void bfs_level(BfsArgs a)
@@ -72,11 +69,6 @@ __global__ __launch_bounds__(GFR_BLOCK) void bfs_level(BfsArgs a)
     const uint32_t dir = ctl->dir;
     if (dir == DIR_DONE) return;
     const int32_t L = ctl->level;
-    uint32_t *fb_cur = pick3(a.fb, L % 3), *fb_next = pick3(a.fb, (L + 1) % 3), *fb_clr = pick3(a.fb, (L + 2) % 3);
-
-    // the bitmap of level L+2 must be empty before level L+1 writes it
-    for (uint32_t i = blockIdx.x * GFR_BLOCK + threadIdx.x; i < a.nwords; i += gridDim.x * GFR_BLOCK)
-        fb_clr[i] = 0u;
 
     if (dir == DIR_PUSH) {
         __shared__ uint32_t s_off[CH + 1];
@@ -105,17 +97,10 @@ __global__ __launch_bounds__(GFR_BLOCK) void bfs_level(BfsArgs a)
                     const int32_t v = a.C[s_row[i] + (int32_t)(e - s_off[i])];
                     const uint32_t bit = 1u << (v & 31);
                     uint32_t *w = a.vis + (v >> 5);
-                    if (!(*w & bit)) {
-                        bool won;
-                        if (idem) {
-                            atomicOr(w, bit);
-                            won = true;
-                        } else {
-                            won = !(atomicOr(w, bit) & bit);
-                        }
-                        if (won) {
+                    if (!(*w & bit) && !a.mark[v]) {
+                        if (idem || !(atomicOr(w, bit) & bit)) {
                             a.depth[v] = L + 1;
-                            atomicOr(fb_next + (v >> 5), bit);
+                            a.mark[v] = 1;
                         }
                     }
                 }
@@ -142,7 +127,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bfs_level(BfsArgs a)
                     for (int j = 0; j < 4; ++j) u[j] = a.C[j < k ? e + j : e];
                     uint32_t hit = 0;
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) hit |= (j < k) ? (fb_cur[u[j] >> 5] >> (u[j] & 31)) & 1u : 0u;
+                    for (int j = 0; j < 4; ++j) hit |= (j < k) ? (a.fb[u[j] >> 5] >> (u[j] & 31)) & 1u : 0u;
                     insp += (uint32_t)k;
                     if (hit) {
                         found = true;
@@ -151,12 +136,9 @@ __global__ __launch_bounds__(GFR_BLOCK) void bfs_level(BfsArgs a)
                     e += 4;
                 }
             }
-            const uint64_t fm = ballot(found);
-            if (found) a.depth[v] = L + 1;
-            if ((lane & 31) == 0) {
-                const uint32_t bits = (uint32_t)(fm >> lane);
-                fb_next[word] = bits;
-                if (bits) a.vis[word] = visw | bits;
+            if (found) {
+                a.depth[v] = L + 1;
+                a.mark[v] = 1;
             }
         }
         // per-group partial (plain store, summed by the level control)
@@ -173,12 +155,21 @@ __global__ __launch_bounds__(GFR_BLOCK) void bfs_level(BfsArgs a)
 }
 
 // Filter + level control for the compaction kernel.
-struct BfsWords {
+struct BfsMarks {
     BfsArgs a;
     uint32_t nparts;   // work-groups of bfs_level (entries of part_insp)
 
     __device__ bool skip() const { return a.ctl->dir == DIR_DONE; }
-    __device__ uint32_t get(uint32_t w) const { return pick3(a.fb, (a.ctl->level + 1) % 3)[w]; }
+    __device__ uint32_t mask(uint32_t w) const
+    {
+        const uint32_t m = marks_to_mask(a.mark + 32ull * w);
+        if (m) {
+            clear_marks(a.mark + 32ull * w);
+            a.vis[w] |= m;
+        }
+        a.fb[w] = m;
+        return m;
+    }
     __device__ void partial(uint32_t) {}
     __device__ void control(uint32_t nf2, uint32_t mf2) const
     {
@@ -232,7 +223,7 @@ __global__ void bfs_init(BfsArgs a, int32_t src, uint32_t chunk, uint32_t force,
         BfsCtl *ctl = a.ctl;
         a.depth[src] = 0;
         a.vis[src >> 5] = 1u << (src & 31);
-        a.fb[0][src >> 5] = 1u << (src & 31);
+        a.fb[src >> 5] = 1u << (src & 31);
         a.q.v[0] = src;
         a.q.off[0] = 0;
         a.q.row[0] = rs;
@@ -263,8 +254,8 @@ void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s)
     const size_t nparts = (size_t)(g.m / chunk) + 2;
     const int G = grid_blocks(c, 4);
     const CompactGeom cg = compact_geom(nwords, c.num_cu);
-    size_t need = 4 * al256(nwords * 4ull) + 3 * al256(4ull * n) + al256(4 * nparts) + al256(4ull * G) +
-                  al256(16ull * cg.blocks) + al256(sizeof(BfsCtl));
+    size_t need = 2 * al256(nwords * 4ull) + al256(nwords * 32ull) + 3 * al256(4ull * n) + al256(4 * nparts) +
+                  al256(4ull * G) + al256(16ull * cg.blocks) + al256(sizeof(BfsCtl));
     c.arena.reserve(need);
     BfsArgs a;
     a.R = g.R.as<int32_t>();
@@ -273,7 +264,8 @@ void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s)
     a.nwords = nwords;
     a.depth = depth;
     a.vis = c.arena.take<uint32_t>(nwords);
-    for (int i = 0; i < 3; ++i) a.fb[i] = c.arena.take<uint32_t>(nwords);
+    a.fb = c.arena.take<uint32_t>(nwords);
+    a.mark = c.arena.take<uint8_t>(32ull * nwords);
     a.q.v = c.arena.take<int32_t>(n);
     a.q.off = c.arena.take<uint32_t>(n);
     a.q.row = c.arena.take<int32_t>(n);
@@ -284,15 +276,15 @@ void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s)
 
     fill_u32(depth, 0xFFFFFFFFu, (size_t)n, s);
     fill_u32(a.vis, 0u, nwords, s);
-    fill_u32(a.fb[0], 0u, nwords, s);
-    fill_u32(a.fb[1], 0u, nwords, s);
+    fill_u32(a.fb, 0u, nwords, s);
+    fill_u32(a.mark, 0u, 8ull * nwords, s);
     fill_u32(status, 0u, 4ull * cg.blocks, s);
     hipLaunchKernelGGL(bfs_init, dim3(1), dim3(GFR_BLOCK), 0, s, a, src, chunk, (uint32_t)c.opt.bfs_direction,
                        (uint32_t)c.opt.bfs_dedup, (float)c.opt.bfs_alpha, (float)c.opt.bfs_beta,
                        (unsigned long long)g.m);
     GFR_LAUNCH_CHECK();
 
-    BfsWords words{a, (uint32_t)G};
+    BfsMarks marks{a, (uint32_t)G};
     auto launch = [&]() {
         c.ktimer.run("bfs_level", s, [&]() {
             switch (chunk) {
@@ -304,8 +296,8 @@ void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s)
             }
         });
         c.ktimer.run("bfs_compact", s, [&]() {
-            hipLaunchKernelGGL(compact_kernel<BfsWords>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R, n, nwords,
-                               cg.wpt, words, a.q, chunk, status, &a.ctl->parity, &a.ctl->err);
+            hipLaunchKernelGGL(compact_kernel<BfsMarks>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R, n, nwords,
+                               cg.wpt, marks, a.q, chunk, status, &a.ctl->parity, &a.ctl->err);
         });
     };
     const int32_t launched = run_until_done(c, &a.ctl->dir, DIR_DONE, g.bfs_levels_hint + 1,

@@ -1,23 +1,30 @@
-// compact.h -- ordered bitmap -> frontier-queue compaction (the filter's
-// compaction step, Sec. 4.1 "Filter": scan-based culling of the frontier).
+// compact.h -- ordered frontier compaction (the filter's compaction step,
+// Sec. 4.1 "Filter": scan-based culling and deduplication of the frontier).
 //
-// Advance kernels only set bits in a frontier bitmap (many threads, distinct
-// words).  This kernel turns the bitmap into the next frontier queue in vertex
-// order: every thread owns a run of consecutive bitmap words, counts its
-// vertices and their degrees, a block scan and a decoupled look-back across
-// work-groups give every run its global slot and edge offset, and a second
-// pass over the same words writes (vertex, edge offset, row start) plus the
-// chunk index of the load-balanced advance.
+// Advance kernels mark the next frontier in a byte array with plain stores
+// (idempotent: several threads may store the same mark).  On MI355X scattered
+// atomics are capped near 27 G ops/s at any table size while plain stores and
+// loads run several times faster, so marking needs no atomics at all.
 //
-// No counter is shared by all work-groups: on MI355X same-address atomics from
-// hundreds of work-groups serialise at the memory side, so the only
-// cross-group traffic is one 64-bit status word per work-group.  The last
-// work-group knows the grand totals and runs the caller's per-level control.
+// This kernel turns the marks into the next frontier queue in vertex order.
+// Every thread owns `wpt` consecutive groups of 32 vertices ("words"); the
+// caller's functor reads (and consumes) the marks of a word and returns them
+// as a 32-bit mask.  Pass 1 counts vertices and their degrees; a block scan
+// and a decoupled look-back across work-groups give every thread its global
+// slot and edge offset; pass 2 stages the group's entries in LDS and writes
+// (vertex, edge offset, row start) contiguously, plus the chunk index used by
+// the load-balanced advance.  No counter is shared by all work-groups (on
+// MI355X same-address atomics serialise at ~11 ns each): the only
+// cross-group traffic is one 64-bit status word per work-group, and the last
+// work-group, which learns the grand totals, runs the caller's control.
 //
 // Status words (one per work-group, two parity buffers): flag in bits 62-63
 // (1 = aggregate of this group, 2 = inclusive prefix), entry count in bits
 // 31-61, edge count in bits 0-30.  Sums of packed values stay packed because
 // entries < 2^31 and edges < 2^31.
+//
+// Every marked vertex must have at least one edge (marks come from edges of a
+// symmetric graph), so each entry carries work for the next advance.
 #pragma once
 
 #include "device.h"
@@ -27,16 +34,43 @@ namespace gfr {
 constexpr unsigned long long ST_AGG = 1ull << 62;
 constexpr unsigned long long ST_INC = 2ull << 62;
 constexpr unsigned long long ST_FLAGS = 3ull << 62;
-constexpr int COMPACT_MAX_WPT = 32;   // bitmap words per thread held in registers
+constexpr int COMPACT_MAX_WPT = 32;   // words per thread held in registers
+constexpr int COMPACT_STAGE = 2048;   // entries staged in LDS per output round
+constexpr int COMPACT_EPT = COMPACT_STAGE / GFR_BLOCK;
 
+// Status words carry their whole payload, and no other data written by a
+// predecessor group is read by its successors, so relaxed device-coherent
+// atomics suffice.  (Acquire/release at device scope would write back or
+// invalidate the caches on every access, which a spinning look-back repeats.)
 __device__ __forceinline__ unsigned long long st_load(const unsigned long long *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void st_store(unsigned long long *p, unsigned long long v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// 32 mark bytes (each 0 or 1) at p -> 32-bit mask; p is 32-byte aligned
+__device__ __forceinline__ uint32_t marks_to_mask(const uint8_t *p)
+{
+    const uint4 a = *(const uint4 *)p, b = *(const uint4 *)(p + 16);
+    const uint32_t x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        // bytes of value 0/1 at bit positions 0,8,16,24 -> bits 21..24 of the product
+        const uint32_t y = x[i] & 0x01010101u;
+        m |= ((y * 0x00204081u) >> 21 & 0xFu) << (4 * i);
+    }
+    return m;
+}
+
+__device__ __forceinline__ void clear_marks(uint8_t *p)
+{
+    *(uint4 *)p = make_uint4(0, 0, 0, 0);
+    *(uint4 *)(p + 16) = make_uint4(0, 0, 0, 0);
 }
 
 __device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long x)
@@ -51,12 +85,13 @@ __device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long l
     return x;
 }
 
-// exclusive block scan of packed values; *total receives the block sum
+// exclusive block scan; *total receives the block sum
 __device__ __forceinline__ unsigned long long block_excl_scan_u64(unsigned long long x, unsigned long long *total)
 {
     __shared__ unsigned long long s_w[GFR_WAVES];
     const int w = threadIdx.x / 64;
     const unsigned long long inc = wave_incl_scan_u64(x);
+    __syncthreads();
     if (lane_id() == 63) s_w[w] = inc;
     __syncthreads();
     unsigned long long base = 0, tot = 0;
@@ -65,14 +100,13 @@ __device__ __forceinline__ unsigned long long block_excl_scan_u64(unsigned long 
         if (i < w) base += s_w[i];
         tot += s_w[i];
     }
-    __syncthreads();
     *total = tot;
     return base + inc - x;
 }
 
-// Work-group exclusive prefix by decoupled look-back (wave 0 only; the other
-// waves receive it through LDS).  `spin_budget` bounds every wait so the
-// kernel always terminates; on exhaustion *err is set and 0 is used.
+// Work-group exclusive prefix by decoupled look-back (wave 0; the other waves
+// receive it through LDS).  Every wait is bounded, so the kernel always ends;
+// if a bound is ever exhausted *err is set and the results are flagged bad.
 __device__ __forceinline__ unsigned long long lookback_prefix(unsigned long long *status, unsigned long long agg,
                                                               uint32_t *err)
 {
@@ -93,7 +127,6 @@ __device__ __forceinline__ unsigned long long lookback_prefix(unsigned long long
             for (;;) {
                 const int j = top - lane;
                 unsigned long long st = j >= 0 ? st_load(status + j) : ST_INC;
-                // wait until every lane of the window sees a published value
                 while (ballot((st & ST_FLAGS) == 0) != 0) {
                     if ((st & ST_FLAGS) == 0) st = st_load(status + j);
                     if (--budget == 0) break;
@@ -106,7 +139,6 @@ __device__ __forceinline__ unsigned long long lookback_prefix(unsigned long long
                 const uint64_t inc_mask = ballot((st & ST_FLAGS) == ST_INC);
                 const int stop = inc_mask ? (__ffsll((unsigned long long)inc_mask) - 1) : 64;
                 unsigned long long v = lane <= stop ? (st & ~ST_FLAGS) : 0ull;
-                // sum over lanes (order irrelevant: integers)
 #pragma unroll
                 for (int d = 32; d >= 1; d >>= 1) {
                     const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, d, 64);
@@ -127,20 +159,48 @@ __device__ __forceinline__ unsigned long long lookback_prefix(unsigned long long
     return s_prefix;
 }
 
-// Compaction kernel.  Words: functor with
-//     bool skip() const                       -- whole launch is a no-op (uniform)
-//     uint32_t get(uint32_t w) const          -- frontier bits of word w (may consume/modify state)
-//     void partial(uint32_t cnt)              -- called by every thread before the group publishes
-//                                                (may reduce per-thread side results)
-//     void control(uint32_t nf, uint32_t mf)  -- called by every thread of the last group with the totals
-// Every thread owns `wpt` consecutive words starting at (block*256 + thread)*wpt.
-template <class Words>
+// Sum of the degrees of the vertices 32w+b with bit b of `bits` set.  The 33
+// row offsets are fetched with independent loads (vector loads when the whole
+// run lies inside R), so the latency is paid once per word, not per vertex.
+__device__ __forceinline__ uint32_t masked_degree_sum(const int32_t *R, int32_t n, uint32_t w, uint32_t bits)
+{
+    const int32_t v0 = (int32_t)(w * 32u);
+    int32_t r[33];
+    if (v0 + 32 <= n) {
+        const int4 *p = (const int4 *)(R + v0);   // R + 32w is 128-byte aligned
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int4 x = p[i];
+            r[4 * i] = x.x;
+            r[4 * i + 1] = x.y;
+            r[4 * i + 2] = x.z;
+            r[4 * i + 3] = x.w;
+        }
+        r[32] = R[v0 + 32];
+    } else {
+#pragma unroll
+        for (int i = 0; i < 33; ++i) r[i] = (v0 + i <= n) ? R[v0 + i] : 0;
+    }
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+        if ((bits >> i) & 1u) s += (uint32_t)(r[i + 1] - r[i]);
+    return s;
+}
+
+// Compaction kernel.  M: functor with
+//     bool skip() const                  whole launch is a no-op (uniform)
+//     uint32_t mask(uint32_t w)          marks of vertices 32w..32w+31 (may consume / update state)
+//     void partial(uint32_t cnt)         called by every thread before the group publishes; side
+//                                        results it sends to the last group need their own fence
+//     void control(uint32_t nf, uint32_t mf)  called by every thread of the last group
+template <class M>
 __global__ __launch_bounds__(GFR_BLOCK) void compact_kernel(const int32_t *R, int32_t n, uint32_t nwords,
-                                                            uint32_t wpt, Words W, FrontierQ q, uint32_t chunk,
+                                                            uint32_t wpt, M mk, FrontierQ q, uint32_t chunk,
                                                             unsigned long long *status2, const uint32_t *parity,
                                                             uint32_t *err)
 {
-    if (W.skip()) return;
+    if (mk.skip()) return;
     const uint32_t p = *parity;
     unsigned long long *status = status2 + (size_t)p * gridDim.x;
     const uint32_t w0 = (blockIdx.x * GFR_BLOCK + threadIdx.x) * wpt;
@@ -150,57 +210,100 @@ __global__ __launch_bounds__(GFR_BLOCK) void compact_kernel(const int32_t *R, in
     for (int i = 0; i < COMPACT_MAX_WPT; ++i) {
         words[i] = 0;
         if ((uint32_t)i < wpt && w0 + i < nwords) {
-            uint32_t bits = W.get(w0 + i);
+            const uint32_t bits = mk.mask(w0 + i);
             words[i] = bits;
-            while (bits) {
-                const int bi = __ffs(bits) - 1;
-                bits &= bits - 1;
-                const int32_t v = (int32_t)((w0 + i) * 32u) + bi;
-                if (v >= n) break;
-                const int32_t d = R[v + 1] - R[v];
-                if (d > 0) {
-                    ++cnt;
-                    edges += (uint32_t)d;
-                }
+            if (bits) {
+                cnt += __popc(bits);
+                edges += masked_degree_sum(R, n, w0 + i, bits);
             }
         }
     }
-    W.partial(cnt);
-    unsigned long long tot;
+    mk.partial(cnt);
+    unsigned long long btot;
     const unsigned long long mine = ((unsigned long long)cnt << 31) | edges;
-    const unsigned long long excl = block_excl_scan_u64(mine, &tot);
-    const unsigned long long base = lookback_prefix(status, tot, err);
-    uint32_t slot = (uint32_t)((base + excl) >> 31);
-    uint32_t off = (uint32_t)((base + excl) & 0x7FFFFFFFull);
+    const unsigned long long excl = block_excl_scan_u64(mine, &btot);
+    const unsigned long long base = lookback_prefix(status, btot, err);
+    const uint32_t bcnt = (uint32_t)(btot >> 31);
+    const uint32_t slot0 = (uint32_t)(base >> 31);
+    uint32_t eoff = (uint32_t)(base & 0x7FFFFFFFull);   // edge offset of the next staged entry
+
+    // pass 2: stage entries in LDS round by round, write them contiguously
+    __shared__ int32_t s_v[COMPACT_STAGE];
+    __shared__ uint32_t s_e[GFR_WAVES];
+    uint32_t my = (uint32_t)(excl >> 31);   // block-local index of this thread's next entry
+    int wi = 0;
+    uint32_t cur = words[0];
+    for (uint32_t r0 = 0; r0 < bcnt; r0 += COMPACT_STAGE) {
+        const uint32_t r1 = r0 + COMPACT_STAGE;
+        // this thread's entries falling into [r0, r1)
+        while (my < r1 && wi < (int)wpt) {
+            if (!cur) {
+                if (++wi < (int)wpt) {
 #pragma unroll
-    for (int i = 0; i < COMPACT_MAX_WPT; ++i) {
-        uint32_t bits = words[i];
-        while (bits) {
-            const int bi = __ffs(bits) - 1;
-            bits &= bits - 1;
-            const int32_t v = (int32_t)((w0 + i) * 32u) + bi;
-            if (v >= n) break;
-            const int32_t r0 = R[v], d = R[v + 1] - r0;
-            if (d > 0) {
-                q.v[slot] = v;
-                q.off[slot] = off;
-                q.row[slot] = r0;
-                for (uint32_t c = (off + chunk - 1) / chunk; (uint64_t)c * chunk < (uint64_t)off + (uint32_t)d; ++c)
-                    q.part[c] = (int32_t)slot;
-                ++slot;
-                off += (uint32_t)d;
+                    for (int i = 1; i < COMPACT_MAX_WPT; ++i)
+                        if (i == wi) cur = words[i];
+                }
+                continue;
+            }
+            const int bi = __ffs(cur) - 1;
+            cur &= cur - 1;
+            s_v[my - r0] = (int32_t)((w0 + wi) * 32u) + bi;
+            ++my;
+        }
+        __syncthreads();
+        const uint32_t cntr = min((uint32_t)COMPACT_STAGE, bcnt - r0);
+        // each thread takes COMPACT_EPT consecutive staged entries
+        const uint32_t j0 = threadIdx.x * COMPACT_EPT;
+        int32_t vv[COMPACT_EPT], rr[COMPACT_EPT];
+        uint32_t dd[COMPACT_EPT], tsum = 0;
+#pragma unroll
+        for (int k = 0; k < COMPACT_EPT; ++k) {
+            dd[k] = 0;
+            vv[k] = 0;
+            rr[k] = 0;
+            if (j0 + k < cntr) {
+                vv[k] = s_v[j0 + k];
+                rr[k] = R[vv[k]];
+                dd[k] = (uint32_t)(R[vv[k] + 1] - rr[k]);
+                tsum += dd[k];
             }
         }
+        // exclusive scan of the per-thread degree sums
+        uint32_t inc = wave_incl_scan(tsum);
+        if (lane_id() == 63) s_e[threadIdx.x / 64] = inc;
+        __syncthreads();
+        uint32_t before = 0, rtot = 0;
+#pragma unroll
+        for (int i = 0; i < GFR_WAVES; ++i) {
+            if (i < (int)(threadIdx.x / 64)) before += s_e[i];
+            rtot += s_e[i];
+        }
+        uint32_t o = eoff + before + inc - tsum;
+#pragma unroll
+        for (int k = 0; k < COMPACT_EPT; ++k) {
+            if (j0 + k < cntr) {
+                const uint32_t slot = slot0 + r0 + j0 + k;
+                q.v[slot] = vv[k];
+                q.off[slot] = o;
+                q.row[slot] = rr[k];
+                for (uint32_t c = (o + chunk - 1) / chunk; (uint64_t)c * chunk < (uint64_t)o + dd[k]; ++c)
+                    q.part[c] = (int32_t)slot;
+                o += dd[k];
+            }
+        }
+        eoff += rtot;
+        __syncthreads();
     }
     // clear this group's slot of the other parity for the next launch
     if (threadIdx.x == 0) status2[(size_t)(p ^ 1u) * gridDim.x + blockIdx.x] = 0ull;
     if (blockIdx.x == gridDim.x - 1) {   // whole group: control may reduce per-group partials
-        const unsigned long long all = base + tot;
-        W.control((uint32_t)(all >> 31), (uint32_t)(all & 0x7FFFFFFFull));
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);   // see the side results of partial()
+        const unsigned long long all = base + btot;
+        mk.control((uint32_t)(all >> 31), (uint32_t)(all & 0x7FFFFFFFull));
     }
 }
 
-// launch geometry for a bitmap of nwords words
+// launch geometry for nwords words of 32 vertices
 struct CompactGeom {
     uint32_t blocks, wpt;
 };
@@ -214,7 +317,8 @@ static inline CompactGeom compact_geom(uint32_t nwords, int num_cu)
     if (g.wpt < 1) g.wpt = 1;
     if (g.wpt > (uint32_t)COMPACT_MAX_WPT) {
         g.wpt = COMPACT_MAX_WPT;
-        g.blocks = (uint32_t)((nwords + (uint64_t)GFR_BLOCK * COMPACT_MAX_WPT - 1) / ((uint64_t)GFR_BLOCK * COMPACT_MAX_WPT));
+        g.blocks = (uint32_t)((nwords + (uint64_t)GFR_BLOCK * COMPACT_MAX_WPT - 1) /
+                              ((uint64_t)GFR_BLOCK * COMPACT_MAX_WPT));
     }
     return g;
 }

@@ -6,13 +6,14 @@
 //   sssp_relax   the advance over the near queue with the same load-balanced
 //                edge chunks as BFS; each edge does
 //                atomicMin(dist[v], dist[u] + w) and, if that improved v, marks
-//                v in the near bitmap when its new distance is inside the
-//                current bucket, otherwise in the far bitmap (the bitmap flags
-//                of Sec. 5.2 remove redundant vertices).
-//   compact      the filter.  In a relax iteration it consumes the near bitmap
+//                v (one plain byte store) as near when its new distance is
+//                inside the current bucket, otherwise as far.  Marks stand in
+//                for the flag array of Sec. 5.2 that removes redundant
+//                vertices: many improvers of one vertex leave one mark.
+//   compact      the filter.  In a relax iteration it consumes the near marks
 //                into the next near queue (vertex order).  When the near queue
 //                has run dry the bucket advances by delta and the same kernel
-//                splits the far bitmap instead: settled entries are dropped,
+//                splits the far marks instead: settled entries are dropped,
 //                entries inside the new bucket become the near queue, the rest
 //                stay far (Sec. 4.5).  The last work-group runs the control.
 // The host enqueues iterations speculatively (see bfs.hip).
@@ -30,8 +31,9 @@ struct SsspCtl {
     uint32_t iter;
     uint32_t lo, hi;             // current bucket [lo, hi)
     uint32_t delta;
-    uint32_t far_pop;            // vertices marked in the far bitmap
+    uint32_t far_any;            // the far set may be non-empty
     uint32_t split_kept;         // far vertices left by the running split
+    uint32_t split_seen;         // far vertices examined by the running split
     uint32_t split_min;          // smallest distance among them
     uint32_t overflow;
     uint32_t parity;
@@ -48,10 +50,10 @@ struct SsspArgs {
     int32_t n;
     uint32_t nwords;
     uint32_t *dist;
-    uint32_t *nb;          // near bitmap (marks of the queue being built)
-    uint32_t *fbm;         // far bitmap
+    uint8_t *near;         // marks of the near queue being built, one byte per vertex
+    uint8_t *far;          // marks of the far set
     FrontierQ q;
-    uint32_t *part;        // per work-group [improvements, new far marks]
+    uint32_t *part;        // per work-group [improvements, far marks written]
     SsspCtl *ctl;
 };
 
@@ -94,11 +96,11 @@ __global__ __launch_bounds__(GFR_BLOCK) void sssp_relax(SsspArgs a)
                 } else {
                     const uint32_t nd = (uint32_t)nd64;
                     if (nd < a.dist[v] && nd < atomicMin(a.dist + v, nd)) {
-                        const uint32_t bit = 1u << (v & 31);
                         ++nimp;
                         if (nd < hi) {
-                            atomicOr(a.nb + (v >> 5), bit);
-                        } else if (!(atomicOr(a.fbm + (v >> 5), bit) & bit)) {
+                            a.near[v] = 1;
+                        } else {
+                            a.far[v] = 1;
                             ++nfar;
                         }
                     }
@@ -126,63 +128,70 @@ __global__ __launch_bounds__(GFR_BLOCK) void sssp_relax(SsspArgs a)
     }
 }
 
-struct SsspWords {
+struct SsspMarks {
     SsspArgs a;
     uint32_t nparts;   // work-groups of sssp_relax
     // per-thread split results
     uint32_t kept = 0;
+    uint32_t seen = 0;
     uint32_t kmin = 0xFFFFFFFFu;
 
     __device__ bool skip() const { return a.ctl->mode == SS_DONE; }
 
-    __device__ uint32_t get(uint32_t w)
+    __device__ uint32_t mask(uint32_t w)
     {
         SsspCtl *ctl = a.ctl;
         if (ctl->mode == SS_RELAX) {   // consume the near marks
-            const uint32_t bits = a.nb[w];
-            if (bits) a.nb[w] = 0u;
-            return bits;
+            const uint32_t m = marks_to_mask(a.near + 32ull * w);
+            if (m) clear_marks(a.near + 32ull * w);
+            return m;
         }
-        const uint32_t f = a.fbm[w];   // split the far marks with the new bucket [lo, hi)
+        // split the far marks with the new bucket [lo, hi)
+        const uint32_t f = marks_to_mask(a.far + 32ull * w);
         if (!f) return 0u;
         const uint32_t lo = ctl->lo, hi = ctl->hi;
-        uint32_t out = 0, keep = f, bits = f;
+        uint32_t out = 0, bits = f;
+        seen += __popc(f);
         while (bits) {
             const int bi = __ffs(bits) - 1;
             bits &= bits - 1;
-            const uint32_t d = a.dist[w * 32u + bi];
+            const uint32_t v = w * 32u + bi;
+            const uint32_t d = a.dist[v];
             if (d < hi) {
-                keep &= ~(1u << bi);
+                a.far[v] = 0;
                 if (d >= lo) out |= 1u << bi;
             } else {
                 ++kept;
                 kmin = min(kmin, d);
             }
         }
-        if (keep != f) a.fbm[w] = keep;
         return out;
     }
 
     __device__ void partial(uint32_t)
     {
         if (a.ctl->mode != SS_SPLIT) return;
-        __shared__ uint32_t s_k[GFR_WAVES], s_m[GFR_WAVES];
-        const uint32_t k = wave_sum_u32(kept), mn = wave_min_u32(kmin);
+        __shared__ uint32_t s_k[GFR_WAVES], s_m[GFR_WAVES], s_s[GFR_WAVES];
+        const uint32_t k = wave_sum_u32(kept), mn = wave_min_u32(kmin), sn = wave_sum_u32(seen);
         if (lane_id() == 0) {
             s_k[threadIdx.x / 64] = k;
             s_m[threadIdx.x / 64] = mn;
+            s_s[threadIdx.x / 64] = sn;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            uint32_t tk = 0, tm = 0xFFFFFFFFu;
+            uint32_t tk = 0, tm = 0xFFFFFFFFu, ts = 0;
             for (int i = 0; i < GFR_WAVES; ++i) {
                 tk += s_k[i];
                 tm = min(tm, s_m[i]);
+                ts += s_s[i];
             }
             if (tk) {
                 atomicAdd(&a.ctl->split_kept, tk);
                 atomicMin(&a.ctl->split_min, tm);
             }
+            if (ts) atomicAdd(&a.ctl->split_seen, ts);
+            __threadfence();   // the split totals are visible before this group publishes
         }
     }
 
@@ -217,12 +226,13 @@ struct SsspWords {
             ctl->near_entries += ctl->nf;
             ctl->relaxed += ctl->mf;
             ctl->improvements += imp;
-            ctl->far_pop += far;
+            if (far) ctl->far_any = 1u;
         } else {
-            ctl->far_entries += ctl->far_pop;
-            ctl->far_pop = atomicAdd(&ctl->split_kept, 0u);
+            ctl->far_entries += atomicAdd(&ctl->split_seen, 0u);
+            ctl->far_any = atomicAdd(&ctl->split_kept, 0u) != 0u;
             split_min = atomicAdd(&ctl->split_min, 0u);
             ctl->split_kept = 0u;
+            ctl->split_seen = 0u;
             ctl->split_min = 0xFFFFFFFFu;
             ctl->splits += 1u;
         }
@@ -231,7 +241,7 @@ struct SsspWords {
             nm = SS_DONE;
         } else if (nf2 > 0) {
             nm = SS_RELAX;
-        } else if (ctl->far_pop > 0) {
+        } else if (ctl->far_any) {
             nm = SS_SPLIT;
             unsigned long long nhi = (unsigned long long)hi + D;
             if (mode == SS_SPLIT && split_min != 0xFFFFFFFFu) {
@@ -267,8 +277,9 @@ __global__ void sssp_init(SsspArgs a, int32_t src, uint32_t chunk, uint32_t delt
         ctl->lo = 0;
         ctl->hi = delta;
         ctl->delta = delta;
-        ctl->far_pop = 0;
+        ctl->far_any = 0;
         ctl->split_kept = 0;
+        ctl->split_seen = 0;
         ctl->split_min = 0xFFFFFFFFu;
         ctl->overflow = 0;
         ctl->parity = 0;
@@ -298,7 +309,7 @@ void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s)
     const uint32_t delta = c.opt.sssp_delta > 0 ? (uint32_t)c.opt.sssp_delta : sssp_auto_delta(g);
     const int G = grid_blocks(c, 4);
     const CompactGeom cg = compact_geom(nwords, c.num_cu);
-    size_t need = 2 * al256(nwords * 4ull) + 3 * al256(4ull * n) + al256(4 * nparts) + al256(8ull * G) +
+    size_t need = 2 * al256(nwords * 32ull) + 3 * al256(4ull * n) + al256(4 * nparts) + al256(8ull * G) +
                   al256(16ull * cg.blocks) + al256(sizeof(SsspCtl));
     c.arena.reserve(need);
     SsspArgs a;
@@ -308,8 +319,8 @@ void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s)
     a.n = n;
     a.nwords = nwords;
     a.dist = dist;
-    a.nb = c.arena.take<uint32_t>(nwords);
-    a.fbm = c.arena.take<uint32_t>(nwords);
+    a.near = c.arena.take<uint8_t>(32ull * nwords);
+    a.far = c.arena.take<uint8_t>(32ull * nwords);
     a.q.v = c.arena.take<int32_t>(n);
     a.q.off = c.arena.take<uint32_t>(n);
     a.q.row = c.arena.take<int32_t>(n);
@@ -319,13 +330,13 @@ void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s)
     a.ctl = c.arena.take<SsspCtl>(1);
 
     fill_u32(dist, 0xFFFFFFFFu, (size_t)n, s);
-    fill_u32(a.nb, 0u, nwords, s);
-    fill_u32(a.fbm, 0u, nwords, s);
+    fill_u32(a.near, 0u, 8ull * nwords, s);
+    fill_u32(a.far, 0u, 8ull * nwords, s);
     fill_u32(status, 0u, 4ull * cg.blocks, s);
     hipLaunchKernelGGL(sssp_init, dim3(1), dim3(GFR_BLOCK), 0, s, a, src, chunk, delta);
     GFR_LAUNCH_CHECK();
 
-    SsspWords words{a, (uint32_t)G};
+    SsspMarks marks{a, (uint32_t)G};
     auto launch = [&]() {
         c.ktimer.run("sssp_relax", s, [&]() {
             switch (chunk) {
@@ -337,8 +348,8 @@ void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s)
             }
         });
         c.ktimer.run("sssp_compact", s, [&]() {
-            hipLaunchKernelGGL(compact_kernel<SsspWords>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R, n, nwords,
-                               cg.wpt, words, a.q, chunk, status, &a.ctl->parity, &a.ctl->err);
+            hipLaunchKernelGGL(compact_kernel<SsspMarks>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R, n, nwords,
+                               cg.wpt, marks, a.q, chunk, status, &a.ctl->parity, &a.ctl->err);
         });
     };
     // every iteration relaxes or splits; the loop is bounded well below this cap
