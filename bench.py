@@ -52,6 +52,22 @@ def bfs_bytes(st: dict, solves: int, n: int) -> float:
     return push + pull
 
 
+def bsssp_bytes(st: dict, n: int) -> float:
+    """Algorithmic bytes of bsssp_relax (64 queries per pass): per edge visit the
+    column and weight (8 B) and the target's 256-byte distance row; per
+    improvement one 4-byte atomic and one mark byte."""
+    return (8 + 256) * st["relaxations"] + 5 * st["improvements"]
+
+
+def msbfs_bytes(st: dict, n: int) -> float:
+    """Algorithmic bytes of msbfs_level: push edges read column + visited and
+    next masks (20 B); a pull level reads every row offset and visited mask
+    (12 B per vertex) plus, per inspected edge, column and frontier mask (12 B),
+    bounded here by one full sweep of the edges."""
+    m_edges = st.get("m", 0)
+    return 20 * st.get("push_edges", 0) + st.get("pull_levels", 0) * (12 * n + 12 * m_edges)
+
+
 def sssp_bytes(st: dict) -> float:
     """Algorithmic bytes of sssp_relax: per near entry its queue slot and distance (16 B),
     per relaxed edge column, weight and target distance (12 B), per improvement one
@@ -59,7 +75,7 @@ def sssp_bytes(st: dict) -> float:
     return 16 * st["near_entries"] + 12 * st["relaxations"] + 8 * st["improvements"]
 
 
-STAT_KEYS = ["push_entries", "push_edges", "push_new", "pull_levels", "pull_unvisited",
+STAT_KEYS = ["m", "push_entries", "push_edges", "push_new", "pull_levels", "pull_unvisited",
              "pull_inspected", "pull_new", "near_entries", "relaxations", "improvements",
              "far_entries", "iterations", "levels", "launches", "solves"]
 
@@ -148,24 +164,23 @@ def main():
     ctx.set_option("profile.kernels", 1)
     ctx.bfs_batch(g, srcs, out=dep)
     sb = read_stats(ctx, STAT_KEYS)
-    kb_ms, kb_n = ctx.stat("t.bfs_level.ms"), ctx.stat("t.bfs_level.n")
-    kbc_ms, kbc_n = ctx.stat("t.bfs_compact.ms"), ctx.stat("t.bfs_compact.n")
+    sb["m"] = m
+    def kstat(name):
+        try:
+            return ctx.stat("t.%s.ms" % name), ctx.stat("t.%s.n" % name)
+        except Exception:
+            return 0.0, 0.0
+    ktimes = {k: kstat(k) for k in ("msbfs_level", "msbfs_finalize", "msbfs_compact")}
     ctx.sssp_batch(g, srcs, out=dist)
     ss = read_stats(ctx, STAT_KEYS)
-    ks_ms, ks_n = ctx.stat("t.sssp_relax.ms"), ctx.stat("t.sssp_relax.n")
-    ksc_ms, ksc_n = ctx.stat("t.sssp_compact.ms"), ctx.stat("t.sssp_compact.n")
+    ktimes.update({k: kstat(k) for k in ("bsssp_relax", "bsssp_compact")})
     ctx.set_option("profile.kernels", 0)
-    b_bytes = bfs_bytes(sb, args.sources, n)
-    s_bytes = sssp_bytes(ss)
-    kernels = {
-        "bfs_level": {"ms": kb_ms, "launches": kb_n, "bytes": b_bytes,
-                      "GBs": b_bytes / (kb_ms * 1e-3) / 1e9},
-        "sssp_relax": {"ms": ks_ms, "launches": ks_n, "bytes": s_bytes,
-                       "GBs": s_bytes / (ks_ms * 1e-3) / 1e9},
-        "bfs_compact": {"ms": kbc_ms, "launches": kbc_n},
-        "sssp_compact": {"ms": ksc_ms, "launches": ksc_n},
-    }
-    dom = max(("bfs_level", "sssp_relax"), key=lambda k: kernels[k]["ms"])
+    kernels = {k: {"ms": v[0], "launches": v[1]} for k, v in ktimes.items()}
+    kernels["bsssp_relax"]["bytes"] = bsssp_bytes(ss, n)
+    kernels["msbfs_level"]["bytes"] = msbfs_bytes(sb, n)
+    for k in ("bsssp_relax", "msbfs_level"):
+        kernels[k]["GBs"] = kernels[k]["bytes"] / max(kernels[k]["ms"], 1e-9) / 1e6
+    dom = max(("msbfs_level", "bsssp_relax"), key=lambda k: kernels[k]["ms"])
     kd = kernels[dom]
     achieved = kd["bytes"] / kd["launches"] / (kd["ms"] / kd["launches"] * 1e-3) / 1e9
     traffic = None

@@ -75,6 +75,10 @@ const char *gfr_last_error(const gfr_ctx *ctx);
  *                     one of 256, 512, 1024, 2048, 4096
  *   "lb.threshold"    frontier size below which the advance balances over vertices
  *                     instead of edges (Sec. 4.4; the paper uses 4096)
+ *   "msbfs.alpha"     batched BFS: pull when the frontier's edges exceed m / alpha
+ *   "profile.kernels" 1: time every launch of the level kernels with HIP events
+ *                     (statistics "t.<kernel>.ms" and "t.<kernel>.n")
+ *   "serve.budget_bytes"  device bytes the serving runtime may hold for queries
  * GFR_E_INVALID for an unknown key or an out-of-range value.
  */
 gfr_status gfr_set_option(gfr_ctx *ctx, const char *key, double value);

@@ -212,6 +212,7 @@ static const OptKey kOptKeys[] = {
     {"bfs.direction", 0, 2},  {"bfs.alpha", 1e-6, 1e9},       {"bfs.beta", 1e-6, 1e9},
     {"bfs.dedup", 0, 1},      {"sssp.delta", 0, 4.0e9},       {"advance.chunk", 256, 4096},
     {"lb.threshold", 0, 2e9}, {"serve.budget_bytes", 0, 1e15}, {"profile.kernels", 0, 1},
+    {"msbfs.alpha", 1e-6, 1e9},
 };
 
 static double *opt_slot(Options &o, const std::string &k, double &tmp)
@@ -222,6 +223,7 @@ static double *opt_slot(Options &o, const std::string &k, double &tmp)
     if (k == "bfs.beta") return &o.bfs_beta;
     if (k == "sssp.delta") return &o.sssp_delta;
     if (k == "serve.budget_bytes") return &o.serve_budget;
+    if (k == "msbfs.alpha") return &o.msbfs_alpha;
     return &dummy;
 }
 
@@ -260,6 +262,7 @@ static double get_option(Ctx &c, const std::string &key)
     if (key == "lb.threshold") return o.lb_threshold;
     if (key == "serve.budget_bytes") return o.serve_budget;
     if (key == "profile.kernels") return o.profile_kernels;
+    if (key == "msbfs.alpha") return o.msbfs_alpha;
     fail(GFR_E_INVALID, "unknown option '" + key + "'");
 }
 

@@ -23,8 +23,8 @@
 // 31-61, edge count in bits 0-30.  Sums of packed values stay packed because
 // entries < 2^31 and edges < 2^31.
 //
-// Every marked vertex must have at least one edge (marks come from edges of a
-// symmetric graph), so each entry carries work for the next advance.
+// Marked vertices without edges are dropped from the queue (they have no work
+// for the next advance and would break the one-entry-per-chunk-start rule).
 #pragma once
 
 #include "device.h"
@@ -159,10 +159,11 @@ __device__ __forceinline__ unsigned long long lookback_prefix(unsigned long long
     return s_prefix;
 }
 
-// Sum of the degrees of the vertices 32w+b with bit b of `bits` set.  The 33
-// row offsets are fetched with independent loads (vector loads when the whole
-// run lies inside R), so the latency is paid once per word, not per vertex.
-__device__ __forceinline__ uint32_t masked_degree_sum(const int32_t *R, int32_t n, uint32_t w, uint32_t bits)
+// Keep only the vertices of `bits` (vertices 32w+b) that have edges, and
+// return the sum of their degrees.  The 33 row offsets are fetched with
+// independent loads (vector loads when the run lies inside R), so the latency
+// is paid once per word, not once per vertex.
+__device__ __forceinline__ uint32_t word_degrees(const int32_t *R, int32_t n, uint32_t w, uint32_t &bits)
 {
     const int32_t v0 = (int32_t)(w * 32u);
     int32_t r[33];
@@ -179,12 +180,18 @@ __device__ __forceinline__ uint32_t masked_degree_sum(const int32_t *R, int32_t 
         r[32] = R[v0 + 32];
     } else {
 #pragma unroll
-        for (int i = 0; i < 33; ++i) r[i] = (v0 + i <= n) ? R[v0 + i] : 0;
+        for (int i = 0; i < 33; ++i) r[i] = (v0 + i <= n) ? R[v0 + i] : r[i > 0 ? i - 1 : 0];
     }
-    uint32_t s = 0;
+    uint32_t s = 0, keep = 0;
 #pragma unroll
-    for (int i = 0; i < 32; ++i)
-        if ((bits >> i) & 1u) s += (uint32_t)(r[i + 1] - r[i]);
+    for (int i = 0; i < 32; ++i) {
+        const uint32_t d = (uint32_t)(r[i + 1] - r[i]);
+        if (((bits >> i) & 1u) && d) {
+            s += d;
+            keep |= 1u << i;
+        }
+    }
+    bits = keep;
     return s;
 }
 
@@ -210,12 +217,12 @@ __global__ __launch_bounds__(GFR_BLOCK) void compact_kernel(const int32_t *R, in
     for (int i = 0; i < COMPACT_MAX_WPT; ++i) {
         words[i] = 0;
         if ((uint32_t)i < wpt && w0 + i < nwords) {
-            const uint32_t bits = mk.mask(w0 + i);
-            words[i] = bits;
+            uint32_t bits = mk.mask(w0 + i);
             if (bits) {
+                edges += word_degrees(R, n, w0 + i, bits);   // drops vertices without edges
                 cnt += __popc(bits);
-                edges += masked_degree_sum(R, n, w0 + i, bits);
             }
+            words[i] = bits;
         }
     }
     mk.partial(cnt);

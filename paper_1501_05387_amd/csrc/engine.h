@@ -110,6 +110,7 @@ struct Options {
     int lb_threshold = 4096;
     double serve_budget = 8.0e9;
     int profile_kernels = 0;
+    double msbfs_alpha = 24.0;  // batched BFS: pull when frontier edges > m / alpha
 };
 
 struct Stats {

@@ -1,0 +1,301 @@
+// msbfs.hip -- up to 64 BFS from different sources in one traversal
+// (bitmask-packed multi-source BFS).  Each vertex carries 64-bit masks
+// (bit q = source q): visited, current frontier and next frontier.  One read
+// of a neighbour list serves every source whose frontier holds the vertex, so
+// k sources cost about one traversal's worth of CSR traffic instead of k.
+// The per-source results equal k single-source BFS (Sec. 5.1): a vertex gets
+// depth L+1 for source q exactly when it is unvisited for q and has a
+// neighbour in q's level-L frontier.
+//
+// Every level is three launches:
+//   msbfs_level     advance.  Push: load-balanced edge chunks over the queue
+//                   of frontier vertices (as in bfs.hip); an edge u->v adds
+//                   fr[u] & ~vis[v] to nx[v] (one 64-bit atomicOr, issued only
+//                   when it contributes new bits).  Pull (Sec. 4.5): a
+//                   load-balanced sweep over all neighbour lists ORs the
+//                   frontier masks of every vertex's neighbours, limited to
+//                   the sources the vertex still needs; with many sources a
+//                   vertex rarely finds all of them early, so the sweep is
+//                   balanced over edges rather than cut short per vertex.
+//   msbfs_finalize  lane = vertex: new = nx[v]; vis |= new; fr = new; the
+//                   depths L+1 are written row by row of the [k][n] output,
+//                   64 consecutive vertices per store, and the vertex gets a
+//                   mark byte if its mask is non-empty.
+//   compact         queue of the new frontier + level control (compact.h).
+#include <algorithm>
+#include <vector>
+
+#include "compact.h"
+#include "device.h"
+#include "engine.h"
+
+namespace gfr {
+
+enum : uint32_t { MS_PUSH = 0, MS_PULL = 1, MS_DONE = 2 };
+
+struct MsCtl {
+    uint32_t dir;
+    int32_t level;     // depth of the current frontier (-1 before the sources are placed)
+    uint32_t nf, mf;
+    uint32_t parity, err;
+    float alpha;       // pull when frontier edges > m / alpha
+    uint32_t pad;
+    unsigned long long m;
+    unsigned long long push_edges, pull_levels, push_levels;
+};
+
+struct MsArgs {
+    const int32_t *R;
+    const int32_t *C;
+    int32_t n;
+    uint32_t nwords;
+    unsigned long long *vis, *fr, *nx;
+    uint8_t *mark;
+    int32_t *depth;    // [k][n]
+    int32_t k;
+    unsigned long long allq;
+    FrontierQ q;
+    FrontierQ full;            // every vertex with edges (pull sweeps)
+    uint32_t full_nf, full_mf;
+    MsCtl *ctl;
+};
+
+template <int CH>
+__global__ __launch_bounds__(GFR_BLOCK) void msbfs_level(MsArgs a)
+{
+    MsCtl *ctl = a.ctl;
+    const uint32_t dir = ctl->dir;
+    if (dir == MS_DONE || ctl->level < 0) return;
+    if (dir == MS_PUSH) {
+        __shared__ uint32_t s_off[CH + 1];
+        __shared__ int32_t s_row[CH + 1];
+        __shared__ unsigned long long s_m[CH + 1];
+        const uint32_t mf = ctl->mf, nf = ctl->nf;
+        const FrontierQ q = a.q;
+        const uint32_t nchunks = (mf + CH - 1) / CH;
+        for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+            const uint32_t e0 = c * CH;
+            const uint32_t e1 = min(e0 + (uint32_t)CH, mf);
+            const int s = q.part[c];
+            const int t = (c + 1 < nchunks) ? q.part[c + 1] : (int)nf - 1;
+            const int cnt = t - s + 1;
+            __syncthreads();
+            for (int i = threadIdx.x; i < cnt; i += GFR_BLOCK) {
+                s_off[i] = q.off[s + i];
+                s_row[i] = q.row[s + i];
+                s_m[i] = a.fr[q.v[s + i]];
+            }
+            __syncthreads();
+#pragma unroll 2
+            for (uint32_t k = 0; k < (uint32_t)CH; k += GFR_BLOCK) {
+                const uint32_t e = e0 + k + threadIdx.x;
+                if (e < e1) {
+                    const int i = upper_index(s_off, 0, cnt - 1, e);
+                    const int32_t v = a.C[s_row[i] + (int32_t)(e - s_off[i])];
+                    const unsigned long long add = s_m[i] & ~(a.vis[v] | a.nx[v]);
+                    if (add) atomicOr(a.nx + v, add);
+                }
+            }
+        }
+    } else {
+        // pull: load-balanced sweep over every vertex's list (the whole-graph
+        // queue), OR of the neighbours' frontier masks per vertex in LDS,
+        // restricted to the sources the vertex still needs
+        __shared__ uint32_t s_off[CH + 1];
+        __shared__ int32_t s_row[CH + 1];
+        __shared__ int32_t s_v[CH + 1];
+        __shared__ unsigned long long s_need[CH + 1], s_acc[CH + 1];
+        const FrontierQ q = a.full;
+        const uint32_t nf = a.full_nf, mf = a.full_mf;
+        const uint32_t nchunks = (mf + CH - 1) / CH;
+        for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+            const uint32_t e0 = c * CH;
+            const uint32_t e1 = min(e0 + (uint32_t)CH, mf);
+            const int s = q.part[c];
+            const int t = (c + 1 < nchunks) ? q.part[c + 1] : (int)nf - 1;
+            const int cnt = t - s + 1;
+            __syncthreads();
+            for (int i = threadIdx.x; i < cnt; i += GFR_BLOCK) {
+                const int32_t v = q.v[s + i];
+                s_off[i] = q.off[s + i];
+                s_row[i] = q.row[s + i];
+                s_v[i] = v;
+                s_need[i] = a.allq & ~a.vis[v];
+                s_acc[i] = 0ull;
+            }
+            __syncthreads();
+            for (uint32_t k = threadIdx.x; k < e1 - e0; k += GFR_BLOCK) {
+                const uint32_t e = e0 + k;
+                const int i = upper_index(s_off, 0, cnt - 1, e);
+                if (s_need[i]) {
+                    const unsigned long long f = a.fr[a.C[s_row[i] + (int32_t)(e - s_off[i])]] & s_need[i];
+                    if (f) atomicOr(s_acc + i, f);
+                }
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < cnt; i += GFR_BLOCK)
+                if (s_acc[i]) atomicOr(a.nx + s_v[i], s_acc[i]);
+        }
+    }
+}
+
+// lane = vertex: fold the next-frontier masks into visited / frontier, write
+// depths L+1 row by row (64 consecutive vertices per store), mark non-empty
+// vertices for the compaction.
+__global__ __launch_bounds__(GFR_BLOCK) void msbfs_finalize(MsArgs a)
+{
+    MsCtl *ctl = a.ctl;
+    if (ctl->dir == MS_DONE) return;
+    const int32_t L = ctl->level;
+    const uint32_t waves = gridDim.x * GFR_WAVES;
+    for (uint32_t grp = blockIdx.x * GFR_WAVES + threadIdx.x / 64; grp * 64u < (uint32_t)a.n; grp += waves) {
+        const int32_t v = (int32_t)(grp * 64u) + lane_id();
+        unsigned long long nw = 0;
+        if (v < a.n) {
+            nw = a.nx[v];
+            const unsigned long long old = a.fr[v];
+            if (nw) {
+                a.nx[v] = 0ull;
+                a.vis[v] |= nw;
+                a.mark[v] = 1;
+            }
+            if (nw || old) a.fr[v] = nw;
+        }
+        // OR of the wave's masks -> the sources that need a row store
+        unsigned long long any = nw;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)any, d, 64);
+            const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(any >> 32), d, 64);
+            any |= ((unsigned long long)hi << 32) | lo;
+        }
+        while (any) {
+            const int qq = __ffsll(any) - 1;
+            any &= any - 1;
+            if ((nw >> qq) & 1ull) a.depth[(size_t)qq * a.n + v] = L + 1;
+        }
+    }
+}
+
+struct MsMarks {
+    MsArgs a;
+    __device__ bool skip() const { return a.ctl->dir == MS_DONE; }
+    __device__ uint32_t mask(uint32_t w) const
+    {
+        const uint32_t m = marks_to_mask(a.mark + 32ull * w);
+        if (m) clear_marks(a.mark + 32ull * w);
+        return m;
+    }
+    __device__ void partial(uint32_t) {}
+    __device__ void control(uint32_t nf2, uint32_t mf2) const
+    {
+        if (threadIdx.x != 0) return;
+        MsCtl *ctl = a.ctl;
+        if (ctl->level >= 0) {
+            if (ctl->dir == MS_PUSH) {
+                ctl->push_levels += 1;
+                ctl->push_edges += ctl->mf;
+            } else {
+                ctl->pull_levels += 1;
+            }
+        }
+        uint32_t nd;
+        if (nf2 == 0) nd = MS_DONE;
+        else nd = ((double)mf2 > (double)ctl->m / ctl->alpha) ? MS_PULL : MS_PUSH;
+        ctl->nf = nf2;
+        ctl->mf = mf2;
+        ctl->level += 1;
+        ctl->parity ^= 1u;
+        ctl->dir = nd;
+    }
+};
+
+__global__ void msbfs_init(MsArgs a, const int32_t *src, float alpha)
+{
+    if (threadIdx.x == 0) {
+        for (int32_t q = 0; q < a.k; ++q) a.nx[src[q]] |= 1ull << q;
+        MsCtl *ctl = a.ctl;
+        ctl->dir = MS_PUSH;
+        ctl->level = -1;
+        ctl->nf = ctl->mf = 0;
+        ctl->parity = 0;
+        ctl->err = 0;
+        ctl->alpha = alpha;
+        ctl->m = (unsigned long long)a.R[a.n];
+        ctl->push_edges = ctl->pull_levels = ctl->push_levels = 0ull;
+    }
+}
+
+void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t *depth, hipStream_t s)
+{
+    const int32_t n = g.n;
+    const uint32_t chunk = 1024;
+    const uint32_t nwords = (uint32_t)(((int64_t)n + 63) / 64) * 2u;
+    const size_t nparts = (size_t)(g.m / chunk) + 2;
+    const int G = grid_blocks(c, 4);
+    const CompactGeom cg = compact_geom(nwords, c.num_cu);
+    c.arena.reserve(3 * al256(8ull * n) + al256(32ull * nwords) + 3 * al256(4ull * n) + al256(4 * nparts) +
+                    al256(16ull * cg.blocks) + al256(sizeof(MsCtl)) + al256(4 * 64));
+    MsArgs a;
+    a.R = g.R.as<int32_t>();
+    a.C = g.C.as<int32_t>();
+    a.n = n;
+    a.nwords = nwords;
+    a.full = g.full;
+    a.full_nf = (uint32_t)g.full_nf;
+    a.full_mf = (uint32_t)g.m;
+    a.vis = c.arena.take<unsigned long long>(n);
+    a.fr = c.arena.take<unsigned long long>(n);
+    a.nx = c.arena.take<unsigned long long>(n);
+    a.mark = c.arena.take<uint8_t>(32ull * nwords);
+    a.q.v = c.arena.take<int32_t>(n);
+    a.q.off = c.arena.take<uint32_t>(n);
+    a.q.row = c.arena.take<int32_t>(n);
+    a.q.part = c.arena.take<int32_t>(nparts);
+    unsigned long long *status = c.arena.take<unsigned long long>(2ull * cg.blocks);
+    a.ctl = c.arena.take<MsCtl>(1);
+    int32_t *dsrc = c.arena.take<int32_t>(64);
+    double levels = 0, pull_levels = 0, push_edges = 0;
+    for (int32_t g0 = 0; g0 < k; g0 += 64) {
+        const int32_t kk = std::min<int32_t>(64, k - g0);
+        a.k = kk;
+        a.allq = kk == 64 ? ~0ull : ((1ull << kk) - 1ull);
+        a.depth = depth + (size_t)g0 * n;
+        fill_u32(a.vis, 0u, 2ull * n, s);
+        fill_u32(a.fr, 0u, 2ull * n, s);
+        fill_u32(a.nx, 0u, 2ull * n, s);
+        fill_u32(a.mark, 0u, 8ull * nwords, s);
+        fill_u32(status, 0u, 4ull * cg.blocks, s);
+        fill_u32(a.depth, 0xFFFFFFFFu, (size_t)kk * n, s);
+        GFR_HIP(hipMemcpyAsync(dsrc, sources + g0, 4ull * kk, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(msbfs_init, dim3(1), dim3(64), 0, s, a, dsrc, (float)c.opt.msbfs_alpha);
+        GFR_LAUNCH_CHECK();
+        auto launch = [&]() {
+            c.ktimer.run("msbfs_level", s, [&]() {
+                hipLaunchKernelGGL(msbfs_level<GATHER_CH>, dim3(G), dim3(GFR_BLOCK), 0, s, a);
+            });
+            c.ktimer.run("msbfs_finalize", s, [&]() {
+                hipLaunchKernelGGL(msbfs_finalize, dim3(G), dim3(GFR_BLOCK), 0, s, a);
+            });
+            c.ktimer.run("msbfs_compact", s, [&]() {
+                hipLaunchKernelGGL(compact_kernel<MsMarks>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R, n, nwords,
+                                   cg.wpt, MsMarks{a}, a.q, chunk, status, &a.ctl->parity, &a.ctl->err);
+            });
+        };
+        run_until_done(c, &a.ctl->dir, MS_DONE, g.bfs_levels_hint + 2, (int64_t)n + 8, s, launch);
+        MsCtl h;
+        GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, s));
+        GFR_HIP(hipStreamSynchronize(s));
+        memcpy(&h, c.pinned, sizeof(MsCtl));
+        if (h.err) fail(GFR_E_DEVICE, "bfs_batch: frontier compaction look-back timed out");
+        levels += h.level;
+        pull_levels += (double)h.pull_levels;
+        push_edges += (double)h.push_edges;
+    }
+    c.stats.v["levels"] += levels;
+    c.stats.v["pull_levels"] += pull_levels;
+    c.stats.v["push_edges"] += push_edges;
+    c.stats.v["solves"] += k;
+}
+
+}  // namespace gfr

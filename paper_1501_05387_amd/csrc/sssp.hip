@@ -95,7 +95,11 @@ __global__ __launch_bounds__(GFR_BLOCK) void sssp_relax(SsspArgs a)
                     ovf = true;
                 } else {
                     const uint32_t nd = (uint32_t)nd64;
-                    if (nd < a.dist[v] && nd < atomicMin(a.dist + v, nd)) {
+                    // non-returning atomicMin; marking on the pre-check marks a
+                    // superset of the true improvements, which only re-relaxes
+                    // such a vertex with its current distance
+                    if (nd < a.dist[v]) {
+                        atomicMin(a.dist + v, nd);
                         ++nimp;
                         if (nd < hi) {
                             a.near[v] = 1;

@@ -1,0 +1,456 @@
+// sssp_batch.hip -- up to 64 SSSP queries in one traversal, lane = query.
+//
+// Distances are stored per vertex as a row of 64 uint32 (one per query, 256
+// bytes).  A wave relaxes one edge u->v for all queries at once: lane q reads
+// dist[u][q] and dist[v][q] inside two coalesced rows and applies the
+// relaxation of Sec. 4.1 Algorithm 1 (atomicMin on improvement) only if u is
+// in query q's frontier.  So a random access into the distance array costs
+// one 256-byte row for up to 64 queries instead of one 64-byte line per
+// query, and every CSR read is shared.  Each query's result equals its
+// single-source SSSP; the queries share the near/far bucket bound of the
+// priority queue (Sec. 4.5), which only changes the schedule, not the result.
+//
+// Marks are bytes: mark[v][q] for the (vertex, query) pairs improved in an
+// iteration plus any[v] for the vertex, written with plain stores.
+//
+// Every iteration is two launches:
+//   bsssp_relax   load-balanced edge chunks over the near queue; each wave
+//                 walks a quarter of the chunk, eight edges in flight.
+//   compact       near queue in vertex order with its per-vertex query masks,
+//                 or, when the near queue has run dry, the far split with
+//                 the next bucket (compact.h), plus the control.
+#include <algorithm>
+
+#include "compact.h"
+#include "device.h"
+#include "engine.h"
+
+namespace gfr {
+
+enum : uint32_t { BS_RELAX = 0, BS_SPLIT = 1, BS_DONE = 2 };
+
+struct BsCtl {
+    uint32_t mode;
+    uint32_t nf, mf;
+    uint32_t iter;
+    uint32_t lo, hi, delta;
+    uint32_t far_any;
+    uint32_t split_kept, split_min;
+    uint32_t overflow, parity, err, splits;
+    unsigned long long relaxed, improvements, pair_entries;
+};
+
+struct BsArgs {
+    const int32_t *R;
+    const int32_t *C;
+    const uint32_t *W;
+    int32_t n;
+    uint32_t nwords;
+    uint32_t *D;                 // [n][64]
+    unsigned long long *qm;      // query mask of every queued vertex
+    uint8_t *nmark, *fmark;      // [n][64]
+    uint8_t *nany, *fany;        // [n] (padded)
+    FrontierQ q;
+    uint32_t *part;              // per work-group [improvements, far marks written]
+    BsCtl *ctl;
+};
+
+constexpr int BS_UNROLL = 16;
+
+template <int CH>
+__global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
+{
+    BsCtl *ctl = a.ctl;
+    if (ctl->mode != BS_RELAX) return;
+    const uint32_t hi = ctl->hi, nf = ctl->nf, mf = ctl->mf;
+    const FrontierQ q = a.q;
+    __shared__ uint32_t s_off[CH + 1];
+    __shared__ int32_t s_row[CH + 1];
+    __shared__ int32_t s_v[CH + 1];
+    const int lane = lane_id(), wave = threadIdx.x / 64;
+    constexpr uint32_t QW = CH / GFR_WAVES;
+    const uint32_t nchunks = (mf + CH - 1) / CH;
+    uint32_t nimp = 0, nfar = 0;
+    bool ovf = false;
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const uint32_t e0 = c * CH;
+        const uint32_t e1 = min(e0 + (uint32_t)CH, mf);
+        const int s = q.part[c];
+        const int t = (c + 1 < nchunks) ? q.part[c + 1] : (int)nf - 1;
+        const int cnt = t - s + 1;
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += GFR_BLOCK) {
+            s_off[i] = q.off[s + i];
+            s_row[i] = q.row[s + i];
+            s_v[i] = q.v[s + i];
+        }
+        __syncthreads();
+        const uint32_t eb = e0 + wave * QW, ee = min(eb + QW, e1);
+        if (eb >= ee) continue;
+        int i = upper_index(s_off, 0, cnt - 1, eb);
+        int32_t u = s_v[i];
+        uint32_t du = a.D[(size_t)u * 64 + lane];
+        bool act = (a.qm[u] >> lane) & 1ull;
+        for (uint32_t e = eb; e < ee; e += BS_UNROLL) {
+            int32_t vv[BS_UNROLL];
+            uint32_t ww[BS_UNROLL], dd[BS_UNROLL], dv[BS_UNROLL];
+            bool aa[BS_UNROLL];
+            // resolve sources and fetch targets/weights (wave-uniform)
+#pragma unroll
+            for (int j = 0; j < BS_UNROLL; ++j) {
+                const uint32_t ej = e + j;
+                aa[j] = false;
+                vv[j] = 0;
+                ww[j] = 0;
+                dd[j] = 0;
+                if (ej < ee) {
+                    while (i + 1 < cnt && s_off[i + 1] <= ej) {
+                        ++i;
+                        u = s_v[i];
+                        du = a.D[(size_t)u * 64 + lane];
+                        act = (a.qm[u] >> lane) & 1ull;
+                    }
+                    const int32_t idx = s_row[i] + (int32_t)(ej - s_off[i]);
+                    vv[j] = a.C[idx];
+                    ww[j] = a.W[idx];
+                    dd[j] = du;
+                    aa[j] = act;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < BS_UNROLL; ++j) dv[j] = aa[j] ? a.D[(size_t)vv[j] * 64 + lane] : 0u;
+#pragma unroll
+            for (int j = 0; j < BS_UNROLL; ++j) {
+                bool near_imp = false, far_imp = false;
+                if (aa[j]) {
+                    const unsigned long long nd64 = (unsigned long long)dd[j] + ww[j];
+                    if (nd64 >= 0xFFFFFFFFull) {
+                        ovf = true;
+                    } else {
+                        const uint32_t nd = (uint32_t)nd64;
+                        // non-returning atomicMin: the mark follows the pre-check, a
+                        // superset of the true improvements (a marked vertex is simply
+                        // relaxed again with its current distance)
+                        if (nd < dv[j]) {
+                            atomicMin(a.D + (size_t)vv[j] * 64 + lane, nd);
+                            ++nimp;
+                            if (nd < hi) {
+                                a.nmark[(size_t)vv[j] * 64 + lane] = 1;
+                                near_imp = true;
+                            } else {
+                                a.fmark[(size_t)vv[j] * 64 + lane] = 1;
+                                far_imp = true;
+                            }
+                        }
+                    }
+                }
+                const uint64_t bn = ballot(near_imp), bf = ballot(far_imp);
+                if (lane == 0) {
+                    if (bn) a.nany[vv[j]] = 1;
+                    if (bf) {
+                        a.fany[vv[j]] = 1;
+                        ++nfar;
+                    }
+                }
+            }
+        }
+    }
+    if (ovf) ctl->overflow = 1u;
+    __shared__ uint32_t s_a[GFR_WAVES], s_b[GFR_WAVES];
+    nimp = wave_sum_u32(nimp);
+    if (lane == 0) {
+        s_a[wave] = nimp;
+        s_b[wave] = nfar;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t x = 0, y = 0;
+        for (int k = 0; k < GFR_WAVES; ++k) {
+            x += s_a[k];
+            y += s_b[k];
+        }
+        a.part[2 * blockIdx.x] = x;
+        a.part[2 * blockIdx.x + 1] = y;
+    }
+}
+
+// 64 mark bytes (0/1) of one vertex -> query mask; clears them when `clear`
+__device__ __forceinline__ unsigned long long row_mask(uint8_t *p, bool clear)
+{
+    unsigned long long m = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t part = marks_to_mask(p + 32 * h);
+        m |= (unsigned long long)part << (32 * h);
+        if (clear && part) clear_marks(p + 32 * h);
+    }
+    return m;
+}
+
+struct BsMarks {
+    BsArgs a;
+    uint32_t nparts;
+    uint32_t kept = 0, kmin = 0xFFFFFFFFu;
+
+    __device__ bool skip() const { return a.ctl->mode == BS_DONE; }
+
+    __device__ uint32_t mask(uint32_t w)
+    {
+        BsCtl *ctl = a.ctl;
+        if (ctl->mode == BS_RELAX) {
+            const uint32_t m = marks_to_mask(a.nany + 32ull * w);
+            if (!m) return 0u;
+            clear_marks(a.nany + 32ull * w);
+            uint32_t bits = m;
+            while (bits) {
+                const int bi = __ffs(bits) - 1;
+                bits &= bits - 1;
+                const uint32_t v = w * 32u + bi;
+                a.qm[v] = row_mask(a.nmark + (size_t)v * 64, true);
+            }
+            return m;
+        }
+        const uint32_t f = marks_to_mask(a.fany + 32ull * w);
+        if (!f) return 0u;
+        const uint32_t lo = ctl->lo, hi = ctl->hi;
+        uint32_t out = 0, bits = f;
+        while (bits) {
+            const int bi = __ffs(bits) - 1;
+            bits &= bits - 1;
+            const uint32_t v = w * 32u + bi;
+            unsigned long long fm = row_mask(a.fmark + (size_t)v * 64, false), nm = 0, left = 0;
+            while (fm) {
+                const int qq = __ffsll(fm) - 1;
+                fm &= fm - 1;
+                const uint32_t d = a.D[(size_t)v * 64 + qq];
+                if (d < hi) {
+                    a.fmark[(size_t)v * 64 + qq] = 0;
+                    if (d >= lo) nm |= 1ull << qq;
+                } else {
+                    left |= 1ull << qq;
+                    ++kept;
+                    kmin = min(kmin, d);
+                }
+            }
+            if (!left) a.fany[v] = 0;
+            if (nm) {
+                a.qm[v] = nm;
+                out |= 1u << bi;
+            }
+        }
+        return out;
+    }
+
+    __device__ void partial(uint32_t)
+    {
+        if (a.ctl->mode != BS_SPLIT) return;
+        __shared__ uint32_t s_k[GFR_WAVES], s_m[GFR_WAVES];
+        const uint32_t k = wave_sum_u32(kept), mn = wave_min_u32(kmin);
+        if (lane_id() == 0) {
+            s_k[threadIdx.x / 64] = k;
+            s_m[threadIdx.x / 64] = mn;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tk = 0, tm = 0xFFFFFFFFu;
+            for (int i = 0; i < GFR_WAVES; ++i) {
+                tk += s_k[i];
+                tm = min(tm, s_m[i]);
+            }
+            if (tk) {
+                atomicAdd(&a.ctl->split_kept, tk);
+                atomicMin(&a.ctl->split_min, tm);
+            }
+            __threadfence();
+        }
+    }
+
+    __device__ void control(uint32_t nf2, uint32_t mf2) const
+    {
+        BsCtl *ctl = a.ctl;
+        const uint32_t mode = ctl->mode;
+        uint32_t imp = 0, far = 0;
+        if (mode == BS_RELAX) {
+            for (uint32_t i = threadIdx.x; i < nparts; i += GFR_BLOCK) {
+                imp += a.part[2 * i];
+                far += a.part[2 * i + 1];
+            }
+            __shared__ uint32_t s_i[GFR_WAVES], s_f[GFR_WAVES];
+            imp = wave_sum_u32(imp);
+            far = wave_sum_u32(far);
+            if (lane_id() == 0) {
+                s_i[threadIdx.x / 64] = imp;
+                s_f[threadIdx.x / 64] = far;
+            }
+            __syncthreads();
+            imp = far = 0;
+            for (int i = 0; i < GFR_WAVES; ++i) {
+                imp += s_i[i];
+                far += s_f[i];
+            }
+        }
+        if (threadIdx.x != 0) return;
+        const uint32_t D = ctl->delta, hi = ctl->hi;
+        uint32_t split_min = 0xFFFFFFFFu;
+        if (mode == BS_RELAX) {
+            ctl->relaxed += ctl->mf;
+            ctl->improvements += imp;
+            if (far) ctl->far_any = 1u;
+        } else {
+            ctl->far_any = atomicAdd(&ctl->split_kept, 0u) != 0u;
+            split_min = atomicAdd(&ctl->split_min, 0u);
+            ctl->split_kept = 0u;
+            ctl->split_min = 0xFFFFFFFFu;
+            ctl->splits += 1u;
+        }
+        uint32_t nm;
+        if (ctl->overflow) {
+            nm = BS_DONE;
+        } else if (nf2 > 0) {
+            nm = BS_RELAX;
+        } else if (ctl->far_any) {
+            nm = BS_SPLIT;
+            unsigned long long nhi = (unsigned long long)hi + D;
+            if (mode == BS_SPLIT && split_min != 0xFFFFFFFFu) {
+                const unsigned long long j = ((unsigned long long)split_min / D + 1ull) * D;
+                if (j > nhi) nhi = j;
+            }
+            ctl->lo = hi;
+            ctl->hi = nhi > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)nhi;
+        } else {
+            nm = BS_DONE;
+        }
+        ctl->nf = nf2;
+        ctl->mf = mf2;
+        ctl->iter += 1u;
+        ctl->parity ^= 1u;
+        ctl->mode = nm;
+    }
+};
+
+__global__ void bsssp_init(BsArgs a, const int32_t *src, int32_t k, uint32_t delta)
+{
+    if (threadIdx.x == 0) {
+        for (int32_t q = 0; q < k; ++q) {
+            const int32_t v = src[q];
+            a.D[(size_t)v * 64 + q] = 0u;
+            a.nmark[(size_t)v * 64 + q] = 1;
+            a.nany[v] = 1;
+        }
+        BsCtl *ctl = a.ctl;
+        ctl->mode = BS_RELAX;
+        ctl->nf = ctl->mf = 0;
+        ctl->iter = 0;
+        ctl->lo = 0;
+        ctl->hi = delta;
+        ctl->delta = delta;
+        ctl->far_any = 0;
+        ctl->split_kept = 0;
+        ctl->split_min = 0xFFFFFFFFu;
+        ctl->overflow = ctl->parity = ctl->err = ctl->splits = 0;
+        ctl->relaxed = ctl->improvements = ctl->pair_entries = 0ull;
+    }
+}
+
+// out[q][v] = D[v][q] for q < k: 64 vertices x 64 queries per tile through LDS
+__global__ __launch_bounds__(GFR_BLOCK) void bsssp_transpose(const uint32_t *D, int32_t n, int32_t k, uint32_t *out)
+{
+    __shared__ uint32_t tile[64][65];
+    const int32_t ntiles = (n + 63) / 64;
+    for (int32_t tb = blockIdx.x; tb < ntiles; tb += gridDim.x) {
+        const int32_t v0 = tb * 64;
+        __syncthreads();
+        for (int i = threadIdx.x; i < 64 * 64; i += GFR_BLOCK) {
+            const int r = i / 64, q = i % 64;
+            tile[r][q] = (v0 + r < n) ? D[(size_t)(v0 + r) * 64 + q] : 0u;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < 64 * 64; i += GFR_BLOCK) {
+            const int q = i / 64, r = i % 64;
+            if (q < k && v0 + r < n) out[(size_t)q * n + v0 + r] = tile[r][q];
+        }
+    }
+}
+
+uint32_t sssp_auto_delta(const Graph &g);
+
+void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_t *dist, hipStream_t s)
+{
+    if (!g.weighted) fail(GFR_E_INVALID, "sssp_batch: graph was loaded without weights");
+    const int32_t n = g.n;
+    const uint32_t chunk = 1024;
+    const uint32_t nwords = (uint32_t)(((int64_t)n + 63) / 64) * 2u;
+    const size_t nparts = (size_t)(g.m / chunk) + 2;
+    const int G = grid_blocks(c, 4);
+    const CompactGeom cg = compact_geom(nwords, c.num_cu);
+    const uint32_t delta = c.opt.sssp_delta > 0 ? (uint32_t)c.opt.sssp_delta : sssp_auto_delta(g);
+    c.arena.reserve(al256(256ull * n) + al256(8ull * n) + 2 * al256(64ull * n) + 2 * al256(32ull * nwords) +
+                    3 * al256(4ull * n) + al256(4 * nparts) + al256(8ull * G) + al256(16ull * cg.blocks) +
+                    al256(sizeof(BsCtl)) + al256(4 * 64));
+    BsArgs a;
+    a.R = g.R.as<int32_t>();
+    a.C = g.C.as<int32_t>();
+    a.W = g.W.as<uint32_t>();
+    a.n = n;
+    a.nwords = nwords;
+    a.D = c.arena.take<uint32_t>(64ull * n);
+    a.qm = c.arena.take<unsigned long long>(n);
+    a.nmark = c.arena.take<uint8_t>(64ull * n);
+    a.fmark = c.arena.take<uint8_t>(64ull * n);
+    a.nany = c.arena.take<uint8_t>(32ull * nwords);
+    a.fany = c.arena.take<uint8_t>(32ull * nwords);
+    a.q.v = c.arena.take<int32_t>(n);
+    a.q.off = c.arena.take<uint32_t>(n);
+    a.q.row = c.arena.take<int32_t>(n);
+    a.q.part = c.arena.take<int32_t>(nparts);
+    a.part = c.arena.take<uint32_t>(2ull * G);
+    unsigned long long *status = c.arena.take<unsigned long long>(2ull * cg.blocks);
+    a.ctl = c.arena.take<BsCtl>(1);
+    int32_t *dsrc = c.arena.take<int32_t>(64);
+    double iters = 0, relaxed = 0, imps = 0;
+    for (int32_t g0 = 0; g0 < k; g0 += 64) {
+        const int32_t kk = std::min<int32_t>(64, k - g0);
+        fill_u32(a.D, 0xFFFFFFFFu, 64ull * n, s);
+        fill_u32(a.nmark, 0u, 16ull * n, s);
+        fill_u32(a.fmark, 0u, 16ull * n, s);
+        fill_u32(a.nany, 0u, 8ull * nwords, s);
+        fill_u32(a.fany, 0u, 8ull * nwords, s);
+        fill_u32(a.part, 0u, 2ull * G, s);
+        fill_u32(status, 0u, 4ull * cg.blocks, s);
+        GFR_HIP(hipMemcpyAsync(dsrc, sources + g0, 4ull * kk, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(bsssp_init, dim3(1), dim3(64), 0, s, a, dsrc, kk, delta);
+        BsMarks marks{a, (uint32_t)G};
+        auto compact = [&]() {
+            c.ktimer.run("bsssp_compact", s, [&]() {
+                hipLaunchKernelGGL(compact_kernel<BsMarks>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R, n, nwords,
+                                   cg.wpt, marks, a.q, chunk, status, &a.ctl->parity, &a.ctl->err);
+            });
+        };
+        compact();   // queue of the sources
+        GFR_LAUNCH_CHECK();
+        auto launch = [&]() {
+            c.ktimer.run("bsssp_relax", s, [&]() {
+                hipLaunchKernelGGL(bsssp_relax<1024>, dim3(G), dim3(GFR_BLOCK), 0, s, a);
+            });
+            compact();
+        };
+        run_until_done(c, &a.ctl->mode, BS_DONE, g.sssp_iter_hint + 1, 64ll * n + 1024, s, launch);
+        BsCtl h;
+        GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(BsCtl), hipMemcpyDeviceToHost, s));
+        GFR_HIP(hipStreamSynchronize(s));
+        memcpy(&h, c.pinned, sizeof(BsCtl));
+        if (h.err) fail(GFR_E_DEVICE, "sssp_batch: frontier compaction look-back timed out");
+        if (h.overflow) fail(GFR_E_INVALID, "sssp_batch: a path weight does not fit below 0xFFFFFFFF");
+        hipLaunchKernelGGL(bsssp_transpose, dim3(G), dim3(GFR_BLOCK), 0, s, a.D, n, kk, dist + (size_t)g0 * n);
+        GFR_LAUNCH_CHECK();
+        iters += h.iter;
+        relaxed += (double)h.relaxed;
+        imps += (double)h.improvements;
+    }
+    c.stats.v["iterations"] += iters;
+    c.stats.v["relaxations"] += relaxed;   // edge visits, each serving up to 64 queries
+    c.stats.v["improvements"] += imps;
+    c.stats.v["solves"] += k;
+}
+
+}  // namespace gfr

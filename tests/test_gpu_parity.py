@@ -308,3 +308,62 @@ def test_batch_equals_single(ctx):
         assert np.array_equal(d[i], oracle.bfs(row, col, x))
         assert np.array_equal(s[i], oracle.sssp(row, col, w, x))
     g.free()
+
+
+@pytest.mark.parametrize("name", ["rmat12", "grid96", "star5000", "path3000", "forest"])
+@pytest.mark.parametrize("k", [1, 64, 70])
+def test_batch_many_sources(ctx, name, k):
+    row, col, w = graph(name)
+    n = row.size - 1
+    rng = np.random.default_rng(k)
+    src = rng.integers(0, n, size=k).astype(np.int32)
+    src[0] = 0
+    if k > 2:
+        src[1] = src[2]                                  # a duplicated source
+        iso = np.nonzero(np.diff(row) == 0)[0]
+        if iso.size:
+            src[-1] = iso[0]                             # an isolated source
+    g = _load(ctx, row, col, w)
+    _say("batch", name, "k", k)
+    d = _host(ctx.bfs_batch(g, src)).reshape(k, n)
+    s = _host(ctx.sssp_batch(g, src)).view(np.uint32).reshape(k, n)
+    for i in range(0, k, max(1, k // 9)):
+        assert np.array_equal(d[i], oracle.bfs(row, col, src[i])), (name, k, i)
+        assert np.array_equal(s[i], oracle.sssp(row, col, w, src[i])), (name, k, i)
+    assert np.array_equal(d[-1], oracle.bfs(row, col, src[-1]))
+    assert np.array_equal(s[-1], oracle.sssp(row, col, w, src[-1]))
+    g.free()
+
+
+@pytest.mark.parametrize("delta", [1, 50, 1 << 30])
+def test_sssp_batch_buckets(ctx, delta):
+    row, col, w = graph("grid96")
+    n = row.size - 1
+    src = np.arange(0, n, n // 40, dtype=np.int32)[:40]
+    g = _load(ctx, row, col, w)
+    ctx.set_option("sssp.delta", delta)
+    try:
+        _say("sssp_batch grid96 delta", delta)
+        s = _host(ctx.sssp_batch(g, src)).view(np.uint32).reshape(len(src), n)
+        for i in (0, 7, 39):
+            assert np.array_equal(s[i], oracle.sssp(row, col, w, src[i]))
+    finally:
+        ctx.set_option("sssp.delta", 0)
+        g.free()
+
+
+@pytest.mark.parametrize("alpha", [1e-6, 24, 1e9])
+def test_bfs_batch_directions(ctx, alpha):
+    row, col, _ = graph("rmat16")
+    n = row.size - 1
+    src = graphgen.sample_sources(row, col, 64)
+    g = _load(ctx, row, col)
+    ctx.set_option("msbfs.alpha", alpha)
+    try:
+        _say("bfs_batch rmat16 alpha", alpha)
+        d = _host(ctx.bfs_batch(g, src)).reshape(64, n)
+        for i in (0, 31, 63):
+            assert np.array_equal(d[i], oracle.bfs(row, col, src[i]))
+    finally:
+        ctx.set_option("msbfs.alpha", 24)
+        g.free()
