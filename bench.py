@@ -90,6 +90,48 @@ def read_stats(ctx, keys):
     return out
 
 
+def serve_leg(ctx, g, row, col, n, nq, log):
+    """Serve a Poisson stream of 70 % BFS / 30 % SSSP queries (sources uniform
+    over the largest component) at a ladder of offered rates, batched (up to 64
+    per traversal) and one at a time, on the same GPU and code path."""
+    import torch
+
+    import graphgen
+    import paper_1501_05387_amd as gfr
+    rng = np.random.default_rng(graphgen.SEED_ARRIVALS)
+    pool = graphgen.sample_sources(row, col, 512, seed=graphgen.SEED_ARRIVALS)
+    srcs = pool[rng.integers(0, pool.size, size=nq)]
+    kinds = np.where(rng.random(nq) < 0.7, gfr.GFR_Q_BFS, gfr.GFR_Q_SSSP)
+    outs = torch.empty((nq, n), dtype=torch.int32, device="cuda:0")
+    res = {}
+    for mode, mb in (("batched", 64), ("one_at_a_time", 1)):
+        ctx.set_option("serve.max_batch", mb)
+        pts = []
+        for rate in (1000.0, 4000.0, 1e9):
+            gaps = rng.exponential(1.0 / rate, size=nq)
+            arrive = np.cumsum(gaps) - gaps[0]
+            ctx.stat("serve.reset")
+            done = set()
+            t0 = time.perf_counter()
+            tickets = []
+            for i in range(nq):
+                while time.perf_counter() - t0 < arrive[i]:
+                    done.update(t for t, _ in ctx.poll(256, 0))
+                tickets += ctx.submit_queries([(int(kinds[i]), g, int(srcs[i]), outs[i])])
+            while len(done) < nq:
+                done.update(t for t, _ in ctx.poll(256, 100000))
+            span = time.perf_counter() - t0
+            pts.append({"offered_qps": rate if rate < 1e8 else None, "qps": round(nq / span, 1),
+                        "p50_ms": round(ctx.stat("serve.p50_ms"), 3), "p99_ms": round(ctx.stat("serve.p99_ms"), 3),
+                        "mean_batch": round(ctx.stat("serve.mean_batch"), 2)})
+            log("serve %s rate %s: %s" % (mode, rate, pts[-1]))
+        res[mode] = pts
+    ctx.set_option("serve.max_batch", 64)
+    res["queries_per_point"] = nq
+    res["mix"] = "70% BFS / 30% SSSP, sources uniform over the largest component, Poisson arrivals"
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +142,7 @@ def main():
     ap.add_argument("--sources", type=int, default=64)
     ap.add_argument("--cpu-sources", type=int, default=1, help="oracle sample size (sources)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-queries", type=int, default=256, help="queries per serving point (0: skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -220,6 +263,11 @@ def main():
         parity = ok
         log("cpu oracle: %.3f GTEPS on %d source(s), parity %s" % (te / tc / 1e9, k, ok))
 
+    serving = None
+    if args.serve_queries > 0:
+        serving = serve_leg(ctx, g, row, col, n, args.serve_queries, log)
+        log("serving:", json.dumps(serving))
+
     line = {
         "metric": "BFS/SSSP GTEPS on R-MAT s22 ef16 (HBM GB/s); batched queries/s + p99 latency",
         "value": round(value, 3),
@@ -242,7 +290,8 @@ def main():
                    "gteps_sssp": round(te_sssp / (ms_sssp * 1e-3) / 1e9, 3),
                    "ms_bfs_64": round(ms_bfs, 3), "ms_sssp_64": round(ms_sssp, 3),
                    "edges_traversed_per_step": te_bfs + te_sssp, "kernels": kernels,
-                   "parity_sample_ok": parity, "source_digest": kernel_source_digest()},
+                   "parity_sample_ok": parity, "source_digest": kernel_source_digest(),
+                   "serving": serving},
     }
     print(json.dumps(line), flush=True)
     g.free()

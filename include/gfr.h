@@ -52,9 +52,22 @@ typedef void *gfr_stream;         /* hipStream_t or NULL                        
 /* ---------------------------------------------------------------- context */
 /*
  * Create a context on HIP device `device`.  `tuning_json` may be NULL or a
- * JSON object of option overrides (see gfr_set_option for the keys).
- * On success *out receives the context.  GFR_E_DEVICE if the device is
- * missing or not gfx950.
+ * JSON object (the tuning file) whose members are either
+ *   "<option>": number        a context-wide value (keys as for gfr_set_option), or
+ *   "<class>": {"<option>": number, ...}
+ *                             values used for graphs of that class, where
+ *                             <class> is "scalefree" (largest degree at least
+ *                             16 times the mean degree) or "mesh" (all others);
+ *                             only solver options (bfs.*, sssp.*, advance.*,
+ *                             msbfs.*, batch.*) may be given per class.
+ * Per-class values apply during each call on a graph of that class, except for
+ * options later set explicitly with gfr_set_option, which win.  Options change
+ * how the result is reached, never the result.  The string is only read
+ * during the call.
+ * On success *out receives the context.  GFR_E_INVALID if the tuning file is
+ * malformed or names an unknown option or an out-of-range value (checked
+ * before the device is touched); GFR_E_DEVICE if the device is missing or
+ * not gfx950.
  */
 gfr_status gfr_ctx_create(int32_t device, const char *tuning_json, gfr_ctx **out);
 
@@ -70,12 +83,16 @@ const char *gfr_last_error(const gfr_ctx *ctx);
  *   "bfs.alpha"       push->pull when frontier edges > unvisited edges / alpha
  *   "bfs.beta"        pull->push when frontier vertices < n / beta
  *   "bfs.dedup"       0 atomic claim (each vertex enqueued once), 1 idempotent (Sec. 4.5)
- *   "sssp.delta"      bucket width of the near/far priority queue (Sec. 4.5); 0 = automatic
+ *   "sssp.delta"      bucket width of the near/far priority queue (Sec. 4.5);
+ *                     0 = "sssp.delta_factor" (default 2) times the mean edge weight
  *   "advance.chunk"   edges per work-group chunk of the load-balanced advance (Sec. 4.4),
  *                     one of 256, 512, 1024, 2048, 4096
- *   "lb.threshold"    frontier size below which the advance balances over vertices
- *                     instead of edges (Sec. 4.4; the paper uses 4096)
  *   "msbfs.alpha"     batched BFS: pull when the frontier's edges exceed m / alpha
+ *   "batch.delta"     batched SSSP bucket width; 0 = "batch.delta_factor" times the
+ *                     mean edge weight, where factor 0 (default) = a single bucket
+ *   "serve.max_batch" largest number of queries the serving runtime runs together (1..64)
+ *   "batch.min_bfs", "batch.min_sssp"  batches smaller than this run as sequential
+ *                     single-source solves (same results, lower cost for few sources)
  *   "profile.kernels" 1: time every launch of the level kernels with HIP events
  *                     (statistics "t.<kernel>.ms" and "t.<kernel>.n")
  *   "serve.budget_bytes"  device bytes the serving runtime may hold for queries
@@ -87,6 +104,9 @@ gfr_status gfr_get_option(gfr_ctx *ctx, const char *key, double *value);
 /*
  * Statistics of the last solve on this context: "levels", "push_levels",
  * "pull_levels", "edges_inspected", "iterations", "relaxations", "kernel_ms".
+ * Serving statistics since the last "serve.reset": "serve.completed",
+ * "serve.batches", "serve.mean_batch", "serve.p50_ms", "serve.p99_ms"
+ * (submission to completion), "serve.queued".
  */
 gfr_status gfr_get_stat(gfr_ctx *ctx, const char *key, double *value);
 

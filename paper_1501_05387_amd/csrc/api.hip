@@ -206,97 +206,167 @@ static void timed_end(Ctx &c, hipStream_t s)
 struct OptKey {
     const char *name;
     double lo, hi;
+    bool per_graph;   // may be set per graph class by a tuning file
 };
 
 static const OptKey kOptKeys[] = {
-    {"bfs.direction", 0, 2},  {"bfs.alpha", 1e-6, 1e9},       {"bfs.beta", 1e-6, 1e9},
-    {"bfs.dedup", 0, 1},      {"sssp.delta", 0, 4.0e9},       {"advance.chunk", 256, 4096},
-    {"lb.threshold", 0, 2e9}, {"serve.budget_bytes", 0, 1e15}, {"profile.kernels", 0, 1},
-    {"msbfs.alpha", 1e-6, 1e9},
+    {"bfs.direction", 0, 2, true},       {"bfs.alpha", 1e-6, 1e9, true},
+    {"bfs.beta", 1e-6, 1e9, true},       {"bfs.dedup", 0, 1, true},
+    {"sssp.delta", 0, 4.0e9, true},      {"advance.chunk", 256, 4096, true},
+    {"sssp.delta_factor", 1e-3, 1e6, true}, {"batch.delta_factor", 0, 1e6, true},
+    {"msbfs.alpha", 1e-6, 1e9, true},    {"batch.delta", 0, 4.0e9, true},
+    {"batch.min_bfs", 1, 1e9, true},     {"batch.min_sssp", 1, 1e9, true},
+    {"serve.budget_bytes", 0, 1e15, false}, {"serve.max_batch", 1, 64, false},
+    {"profile.kernels", 0, 1, false},
 };
 
-static double *opt_slot(Options &o, const std::string &k, double &tmp)
+static const OptKey &opt_key(const std::string &key)
 {
-    (void)tmp;
-    static double dummy;
-    if (k == "bfs.alpha") return &o.bfs_alpha;
-    if (k == "bfs.beta") return &o.bfs_beta;
-    if (k == "sssp.delta") return &o.sssp_delta;
-    if (k == "serve.budget_bytes") return &o.serve_budget;
-    if (k == "msbfs.alpha") return &o.msbfs_alpha;
-    return &dummy;
+    for (const auto &e : kOptKeys)
+        if (key == e.name) return e;
+    fail(GFR_E_INVALID, "unknown option '" + key + "'");
 }
 
-static void set_option(Ctx &c, const std::string &key, double v)
+void option_set(Options &o, const std::string &key, double v)
 {
-    const OptKey *k = nullptr;
-    for (const auto &e : kOptKeys)
-        if (key == e.name) k = &e;
-    if (!k) fail(GFR_E_INVALID, "unknown option '" + key + "'");
-    if (!(v >= k->lo && v <= k->hi)) fail(GFR_E_INVALID, "option '" + key + "' out of range");
-    Options &o = c.opt;
+    const OptKey &k = opt_key(key);
+    if (!(v >= k.lo && v <= k.hi)) fail(GFR_E_INVALID, "option '" + key + "' out of range");
     if (key == "bfs.direction") o.bfs_direction = (int)v;
+    else if (key == "bfs.alpha") o.bfs_alpha = v;
+    else if (key == "bfs.beta") o.bfs_beta = v;
     else if (key == "bfs.dedup") o.bfs_dedup = (int)v;
-    else if (key == "lb.threshold") o.lb_threshold = (int)v;
+    else if (key == "sssp.delta") o.sssp_delta = v;
+    else if (key == "sssp.delta_factor") o.sssp_delta_factor = v;
+    else if (key == "batch.delta_factor") o.batch_delta_factor = v;
+    else if (key == "msbfs.alpha") o.msbfs_alpha = v;
+    else if (key == "batch.delta") o.batch_delta = v;
+    else if (key == "batch.min_bfs") o.batch_min_bfs = (int)v;
+    else if (key == "batch.min_sssp") o.batch_min_sssp = (int)v;
+    else if (key == "serve.budget_bytes") o.serve_budget = v;
+    else if (key == "serve.max_batch") o.serve_max_batch = (int)v;
     else if (key == "profile.kernels") o.profile_kernels = (int)v;
     else if (key == "advance.chunk") {
         const int iv = (int)v;
         if (iv != 256 && iv != 512 && iv != 1024 && iv != 2048 && iv != 4096)
             fail(GFR_E_INVALID, "advance.chunk must be 256, 512, 1024, 2048 or 4096");
         o.advance_chunk = iv;
-    } else {
-        double tmp;
-        *opt_slot(o, key, tmp) = v;
     }
 }
 
-static double get_option(Ctx &c, const std::string &key)
+static double option_get(const Options &o, const std::string &key)
 {
-    const Options &o = c.opt;
+    (void)opt_key(key);
     if (key == "bfs.direction") return o.bfs_direction;
     if (key == "bfs.alpha") return o.bfs_alpha;
     if (key == "bfs.beta") return o.bfs_beta;
     if (key == "bfs.dedup") return o.bfs_dedup;
     if (key == "sssp.delta") return o.sssp_delta;
+    if (key == "sssp.delta_factor") return o.sssp_delta_factor;
+    if (key == "batch.delta_factor") return o.batch_delta_factor;
     if (key == "advance.chunk") return o.advance_chunk;
-    if (key == "lb.threshold") return o.lb_threshold;
-    if (key == "serve.budget_bytes") return o.serve_budget;
-    if (key == "profile.kernels") return o.profile_kernels;
     if (key == "msbfs.alpha") return o.msbfs_alpha;
-    fail(GFR_E_INVALID, "unknown option '" + key + "'");
+    if (key == "batch.delta") return o.batch_delta;
+    if (key == "batch.min_bfs") return o.batch_min_bfs;
+    if (key == "batch.min_sssp") return o.batch_min_sssp;
+    if (key == "serve.budget_bytes") return o.serve_budget;
+    if (key == "serve.max_batch") return o.serve_max_batch;
+    return o.profile_kernels;
 }
 
-// Minimal parser for a flat JSON object of numeric options: {"key": number, ...}
-static void apply_tuning_json(Ctx &c, const char *js)
+const char *const kClassNames[kNumGraphClasses] = {"scalefree", "mesh"};
+
+int classify_graph(int32_t n, int64_t m, int32_t max_deg)
+{
+    const double mean = n > 0 ? (double)m / n : 0.0;
+    return (double)max_deg >= 16.0 * (mean > 1.0 ? mean : 1.0) ? GRAPH_SCALEFREE : GRAPH_MESH;
+}
+
+// Parser for the tuning file: a JSON object whose members are numeric options
+// (context-wide values) or objects named after a graph class holding
+// per-graph numeric options for graphs of that class.  Validates every key
+// and value; nothing is applied on error.
+static void parse_tuning(const char *js, Tuning &t)
 {
     std::string s(js);
     size_t i = 0;
     auto skip = [&]() {
-        while (i < s.size() && (s[i] == ' ' || s[i] == '\n' || s[i] == '\t' || s[i] == '\r' || s[i] == ','))
-            ++i;
+        while (i < s.size() && (s[i] == ' ' || s[i] == '\n' || s[i] == '\t' || s[i] == '\r')) ++i;
     };
-    skip();
-    if (i >= s.size() || s[i] != '{') fail(GFR_E_INVALID, "tuning_json: expected an object");
-    ++i;
-    for (;;) {
+    auto key = [&]() {
         skip();
-        if (i < s.size() && s[i] == '}') break;
         if (i >= s.size() || s[i] != '"') fail(GFR_E_INVALID, "tuning_json: expected a key");
         size_t j = s.find('"', i + 1);
         if (j == std::string::npos) fail(GFR_E_INVALID, "tuning_json: unterminated key");
-        std::string key = s.substr(i + 1, j - i - 1);
+        std::string k = s.substr(i + 1, j - i - 1);
         i = j + 1;
         skip();
-        if (i >= s.size() || s[i] != ':') fail(GFR_E_INVALID, "tuning_json: expected ':'");
+        if (i >= s.size() || s[i] != ':') fail(GFR_E_INVALID, "tuning_json: expected ':' after " + k);
         ++i;
         skip();
+        return k;
+    };
+    auto number = [&](const std::string &k) {
         char *endp = nullptr;
         double v = strtod(s.c_str() + i, &endp);
-        if (endp == s.c_str() + i) fail(GFR_E_INVALID, "tuning_json: expected a number for " + key);
+        if (endp == s.c_str() + i) fail(GFR_E_INVALID, "tuning_json: expected a number for " + k);
         i = endp - s.c_str();
-        set_option(c, key, v);
+        return v;
+    };
+    // after a member: ',' then another member, or the closing brace
+    auto next = [&]() {
+        skip();
+        if (i < s.size() && s[i] == ',') {
+            ++i;
+            return true;
+        }
+        if (i < s.size() && s[i] == '}') {
+            ++i;
+            return false;
+        }
+        fail(GFR_E_INVALID, "tuning_json: expected ',' or '}'");
+    };
+    auto open = [&]() {
+        skip();
+        if (i >= s.size() || s[i] != '{') fail(GFR_E_INVALID, "tuning_json: expected an object");
+        ++i;
+        skip();
+        if (i < s.size() && s[i] == '}') {
+            ++i;
+            return false;
+        }
+        return true;
+    };
+    Options probe;
+    for (bool more = open(); more; more = next()) {
+        std::string k = key();
+        int cls = -1;
+        for (int c = 0; c < kNumGraphClasses; ++c)
+            if (k == kClassNames[c]) cls = c;
+        if (cls < 0) {
+            double v = number(k);
+            option_set(probe, k, v);
+            t.global.push_back({k, v});
+            continue;
+        }
+        for (bool inner = open(); inner; inner = next()) {
+            std::string ck = key();
+            double v = number(ck);
+            if (!opt_key(ck).per_graph) fail(GFR_E_INVALID, "tuning_json: '" + ck + "' cannot be set per graph class");
+            option_set(probe, ck, v);
+            t.cls[cls].push_back({ck, v});
+        }
     }
+    skip();
+    if (i != s.size()) fail(GFR_E_INVALID, "tuning_json: trailing characters");
 }
+
+OptScope::OptScope(Ctx &c, const Graph &g) : c(c), saved(c.opt)
+{
+    for (const auto &kv : c.tuning.cls[g.cls])
+        if (!c.user_keys.count(kv.first)) option_set(c.opt, kv.first, kv.second);
+}
+
+OptScope::~OptScope() { c.opt = saved; }
 
 }  // namespace gfr
 
@@ -308,6 +378,16 @@ gfr_status gfr_ctx_create(int32_t device, const char *tuning_json, gfr_ctx **out
 {
     if (!out) return GFR_E_INVALID;
     *out = nullptr;
+    Tuning tuning;
+    if (tuning_json) {
+        try {
+            parse_tuning(tuning_json, tuning);
+        } catch (const Error &e) {
+            return e.code;
+        } catch (...) {
+            return GFR_E_INVALID;
+        }
+    }
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
         (void)hipGetLastError();
@@ -330,7 +410,8 @@ gfr_status gfr_ctx_create(int32_t device, const char *tuning_json, gfr_ctx **out
         cc.zero_word.alloc(256);
         GFR_HIP(hipMemsetAsync(cc.zero_word.p, 0, 256, cc.stream));
         GFR_HIP(hipStreamSynchronize(cc.stream));
-        if (tuning_json) apply_tuning_json(cc, tuning_json);
+        for (const auto &kv : tuning.global) option_set(cc.opt, kv.first, kv.second);
+        cc.tuning = tuning;
     });
     if (st != GFR_OK) {
         gfr_ctx_destroy((gfr_ctx *)c);
@@ -368,7 +449,8 @@ gfr_status gfr_set_option(gfr_ctx *ctx, const char *key, double value)
 {
     return guard(ctx, [&](Ctx &c) {
         if (!key) fail(GFR_E_INVALID, "null key");
-        set_option(c, key, value);
+        option_set(c.opt, key, value);
+        c.user_keys.insert(key);
     });
 }
 
@@ -376,7 +458,7 @@ gfr_status gfr_get_option(gfr_ctx *ctx, const char *key, double *value)
 {
     return guard(ctx, [&](Ctx &c) {
         if (!key || !value) fail(GFR_E_INVALID, "null argument");
-        *value = get_option(c, key);
+        *value = option_get(c.opt, key);
     });
 }
 
@@ -384,6 +466,7 @@ gfr_status gfr_get_stat(gfr_ctx *ctx, const char *key, double *value)
 {
     return guard(ctx, [&](Ctx &c) {
         if (!key || !value) fail(GFR_E_INVALID, "null argument");
+        if (serve_stat(c, key, value)) return;
         auto it = c.stats.v.find(key);
         if (it == c.stats.v.end()) fail(GFR_E_NOT_FOUND, std::string("no statistic '") + key + "'");
         *value = it->second;
@@ -435,10 +518,14 @@ gfr_status gfr_graph_load_csr(gfr_ctx *ctx, int32_t n, int64_t m, const int32_t 
         int32_t md = 0;
         for (int32_t i = 0; i < n; ++i) md = std::max(md, R[i + 1] - R[i]);
         g->max_deg = md;
+        g->cls = classify_graph(n, m, md);
         build_full_queue(c, *g, R);
         GFR_HIP(hipStreamSynchronize(c.stream));
         const int64_t h = c.next_handle++;
-        c.graphs[h] = std::move(g);
+        {
+            std::lock_guard<std::mutex> lr(c.reg_mu);
+            c.graphs[h] = std::move(g);
+        }
         *out = h;
     });
 }
@@ -448,6 +535,7 @@ gfr_status gfr_graph_free(gfr_ctx *ctx, gfr_graph g)
     return guard(ctx, [&](Ctx &c) {
         get_graph(c, g);
         GFR_HIP(hipStreamSynchronize(c.stream));
+        std::lock_guard<std::mutex> lr(c.reg_mu);
         c.graphs.erase(g);
     });
 }
@@ -466,6 +554,7 @@ gfr_status gfr_bfs(gfr_ctx *ctx, gfr_graph gh, int32_t source, int32_t *depth_ou
 {
     return guard(ctx, [&](Ctx &c) {
         Graph &g = get_graph(c, gh);
+        OptScope os(c, g);
         if (source < 0 || source >= g.n) fail(GFR_E_INVALID, "bfs: source out of range");
         hipStream_t s = pick_stream(c, stream);
         OutBuf o(c, depth_out, 4ull * g.n);
@@ -480,6 +569,7 @@ gfr_status gfr_sssp(gfr_ctx *ctx, gfr_graph gh, int32_t source, uint32_t *dist_o
 {
     return guard(ctx, [&](Ctx &c) {
         Graph &g = get_graph(c, gh);
+        OptScope os(c, g);
         if (source < 0 || source >= g.n) fail(GFR_E_INVALID, "sssp: source out of range");
         if (!g.weighted) fail(GFR_E_INVALID, "sssp: graph was loaded without weights");
         hipStream_t s = pick_stream(c, stream);
@@ -496,6 +586,7 @@ gfr_status gfr_bc(gfr_ctx *ctx, gfr_graph gh, const int32_t *sources, int32_t k,
 {
     return guard(ctx, [&](Ctx &c) {
         Graph &g = get_graph(c, gh);
+        OptScope os(c, g);
         if (k < 0 || (k > 0 && !sources)) fail(GFR_E_INVALID, "bc: bad source list");
         std::vector<int32_t> src(sources, sources + k);
         for (int32_t i = 0; i < k; ++i)
@@ -518,6 +609,7 @@ gfr_status gfr_cc(gfr_ctx *ctx, gfr_graph gh, int32_t *label_out, int32_t *num_c
 {
     return guard(ctx, [&](Ctx &c) {
         Graph &g = get_graph(c, gh);
+        OptScope os(c, g);
         hipStream_t s = pick_stream(c, stream);
         OutBuf o(c, label_out, 4ull * g.n);
         int32_t nc = 0;
@@ -534,6 +626,7 @@ gfr_status gfr_pagerank(gfr_ctx *ctx, gfr_graph gh, float damping, double l1_tol
 {
     return guard(ctx, [&](Ctx &c) {
         Graph &g = get_graph(c, gh);
+        OptScope os(c, g);
         if (!(damping > 0.f && damping < 1.f)) fail(GFR_E_INVALID, "pagerank: damping must be in (0,1)");
         if (max_iter < 1) fail(GFR_E_INVALID, "pagerank: max_iter must be >= 1");
         if (!(l1_tol >= 0.0)) fail(GFR_E_INVALID, "pagerank: l1_tol must be >= 0");
@@ -555,6 +648,7 @@ gfr_status gfr_bfs_batch(gfr_ctx *ctx, gfr_graph gh, const int32_t *sources, int
 {
     return guard(ctx, [&](Ctx &c) {
         Graph &g = get_graph(c, gh);
+        OptScope os(c, g);
         if (k < 1 || !sources) fail(GFR_E_INVALID, "bfs_batch: need k >= 1 sources");
         for (int32_t i = 0; i < k; ++i)
             if (sources[i] < 0 || sources[i] >= g.n) fail(GFR_E_INVALID, "bfs_batch: source out of range");
@@ -572,6 +666,7 @@ gfr_status gfr_sssp_batch(gfr_ctx *ctx, gfr_graph gh, const int32_t *sources, in
 {
     return guard(ctx, [&](Ctx &c) {
         Graph &g = get_graph(c, gh);
+        OptScope os(c, g);
         if (k < 1 || !sources) fail(GFR_E_INVALID, "sssp_batch: need k >= 1 sources");
         if (!g.weighted) fail(GFR_E_INVALID, "sssp_batch: graph was loaded without weights");
         for (int32_t i = 0; i < k; ++i)

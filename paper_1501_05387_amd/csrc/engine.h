@@ -10,6 +10,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -80,8 +81,16 @@ struct Arena {
 
 static inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Graph classes for per-class tuning, chosen at load from the degree
+// distribution (Sec. 7 suggests predicting parameters from it).
+enum { GRAPH_SCALEFREE = 0, GRAPH_MESH = 1, kNumGraphClasses = 2 };
+extern const char *const kClassNames[kNumGraphClasses];
+// scale-free when the largest degree is at least 16 times the mean degree
+int classify_graph(int32_t n, int64_t m, int32_t max_deg);
+
 struct Graph {
     int32_t n = 0;
+    int cls = GRAPH_MESH;
     int64_t m = 0;
     DevMem R, C, W;
     bool weighted = false;
@@ -105,13 +114,26 @@ struct Options {
     double bfs_alpha = 15.0;
     double bfs_beta = 18.0;
     int bfs_dedup = 0;          // 0 atomic, 1 idempotent
-    double sssp_delta = 0.0;    // 0 -> automatic
+    double sssp_delta = 0.0;    // 0 -> sssp_delta_factor x mean edge weight
+    double sssp_delta_factor = 2.0;
     int advance_chunk = 1024;
-    int lb_threshold = 4096;
     double serve_budget = 8.0e9;
     int profile_kernels = 0;
-    double msbfs_alpha = 24.0;  // batched BFS: pull when frontier edges > m / alpha
+    double msbfs_alpha = 4.0;   // batched BFS: pull when frontier edges > m / alpha
+    double batch_delta = 0.0;   // batched SSSP bucket width; 0 -> batch_delta_factor
+    double batch_delta_factor = 0.0;   // x mean edge weight; 0 -> one bucket (frontier order)
+    int serve_max_batch = 64;
+    int batch_min_bfs = 8;      // fewer sources than this: sequential single-source BFS
+    int batch_min_sssp = 24;    // fewer queries than this: sequential single-source SSSP
 };
+
+// Options from a tuning file: context-wide values and per-graph-class values.
+struct Tuning {
+    std::vector<std::pair<std::string, double>> global;
+    std::vector<std::pair<std::string, double>> cls[kNumGraphClasses];
+};
+
+void option_set(Options &o, const std::string &key, double v);
 
 struct Stats {
     std::map<std::string, double> v;
@@ -175,7 +197,9 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int num_cu = 256;
-    std::recursive_mutex mu;
+    std::recursive_mutex mu;      // serialises device work and most API calls
+    std::mutex reg_mu;            // graph registry: held (with mu) to insert/erase, alone to look up
+    std::mutex srv_mu;            // creation of the serving runtime
     std::string err;
     std::map<int64_t, std::unique_ptr<Graph>> graphs;
     int64_t next_handle = 1;
@@ -183,11 +207,23 @@ struct Ctx {
     DevMem stage;                 // device staging for host output buffers
     DevMem zero_word;             // a device word that always holds 0
     uint32_t *pinned = nullptr;   // small pinned host buffer for control readbacks
-    Options opt;
+    Options opt;                  // in effect; per-class values are applied by OptScope
+    Tuning tuning;
+    std::set<std::string> user_keys;   // options set by gfr_set_option (they beat the tuning file)
     Stats stats;
     Server *server = nullptr;     // owned; destroyed by serve_shutdown
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     KernelTimer ktimer;
+};
+
+// While alive, c.opt holds the options for graph g: the tuning file's
+// values for g's class over the context-wide ones, except for options the
+// caller set explicitly.  The caller holds c.mu.
+struct OptScope {
+    Ctx &c;
+    Options saved;
+    OptScope(Ctx &c, const Graph &g);
+    ~OptScope();
 };
 
 Graph &get_graph(Ctx &c, gfr_graph h);
@@ -197,6 +233,8 @@ int grid_blocks(const Ctx &c, int per_cu = 4);
 // Solvers (outputs are device pointers on the context's device).
 void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s);
 void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s);
+// Bucket width factor x mean edge weight, clamped to [1, 1e9].
+uint32_t sssp_auto_delta(const Graph &g, double factor);
 void run_cc(Ctx &c, Graph &g, int32_t *label, int32_t *ncomp, hipStream_t s);
 void run_pagerank(Ctx &c, Graph &g, float damping, double tol, int32_t max_iter, float *rank,
                   int32_t *iters, double *l1, hipStream_t s);
@@ -211,6 +249,8 @@ constexpr uint32_t GATHER_CH = 1024;
 
 // Stops the serving runtime of a context (no-op if none).
 void serve_shutdown(Ctx &c);
+// Serving statistics ("serve.*" keys); false if the key is not a serving key.
+bool serve_stat(Ctx &c, const std::string &key, double *value);
 
 // Fill helpers.
 void fill_u32(void *p, uint32_t value, size_t count, hipStream_t s);

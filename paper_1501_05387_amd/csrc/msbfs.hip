@@ -229,6 +229,10 @@ __global__ void msbfs_init(MsArgs a, const int32_t *src, float alpha)
 void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t *depth, hipStream_t s)
 {
     const int32_t n = g.n;
+    if (k < c.opt.batch_min_bfs) {   // a shared traversal costs about the same for few sources
+        for (int32_t i = 0; i < k; ++i) run_bfs(c, g, sources[i], depth + (size_t)i * n, s);
+        return;
+    }
     const uint32_t chunk = 1024;
     const uint32_t nwords = (uint32_t)(((int64_t)n + 63) / 64) * 2u;
     const size_t nparts = (size_t)(g.m / chunk) + 2;

@@ -295,9 +295,9 @@ __global__ void sssp_init(SsspArgs a, int32_t src, uint32_t chunk, uint32_t delt
     for (uint32_t c = threadIdx.x; (uint64_t)c * chunk < (uint64_t)deg; c += blockDim.x) a.q.part[c] = 0;
 }
 
-uint32_t sssp_auto_delta(const Graph &g)
+uint32_t sssp_auto_delta(const Graph &g, double factor)
 {
-    double d = g.mean_w * 2.0;
+    double d = g.mean_w * factor;
     if (d < 1.0) d = 1.0;
     if (d > 1.0e9) d = 1.0e9;
     return (uint32_t)d;
@@ -310,7 +310,7 @@ void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s)
     const uint32_t chunk = (uint32_t)c.opt.advance_chunk;
     const uint32_t nwords = (uint32_t)(((int64_t)n + 63) / 64) * 2u;
     const size_t nparts = (size_t)(g.m / chunk) + 2;
-    const uint32_t delta = c.opt.sssp_delta > 0 ? (uint32_t)c.opt.sssp_delta : sssp_auto_delta(g);
+    const uint32_t delta = c.opt.sssp_delta > 0 ? (uint32_t)c.opt.sssp_delta : sssp_auto_delta(g, c.opt.sssp_delta_factor);
     const int G = grid_blocks(c, 4);
     const CompactGeom cg = compact_geom(nwords, c.num_cu);
     size_t need = 2 * al256(nwords * 32ull) + 3 * al256(4ull * n) + al256(4 * nparts) + al256(8ull * G) +

@@ -372,18 +372,26 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_transpose(const uint32_t *D, 
     }
 }
 
-uint32_t sssp_auto_delta(const Graph &g);
-
 void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_t *dist, hipStream_t s)
 {
     if (!g.weighted) fail(GFR_E_INVALID, "sssp_batch: graph was loaded without weights");
     const int32_t n = g.n;
+    if (k < c.opt.batch_min_sssp) {   // a shared traversal costs about the same for few queries
+        for (int32_t i = 0; i < k; ++i) run_sssp(c, g, sources[i], dist + (size_t)i * n, s);
+        return;
+    }
     const uint32_t chunk = 1024;
     const uint32_t nwords = (uint32_t)(((int64_t)n + 63) / 64) * 2u;
     const size_t nparts = (size_t)(g.m / chunk) + 2;
     const int G = grid_blocks(c, 4);
     const CompactGeom cg = compact_geom(nwords, c.num_cu);
-    const uint32_t delta = c.opt.sssp_delta > 0 ? (uint32_t)c.opt.sssp_delta : sssp_auto_delta(g);
+    // one shared bucket serves all queries; a narrow bucket desynchronises the
+    // queries' frontiers and multiplies edge visits, so the default is a
+    // single bucket (plain frontier order); "batch.delta" sets a width, or
+    // "batch.delta_factor" one relative to the mean edge weight
+    uint32_t delta = 0xFFFFFFFFu;
+    if (c.opt.batch_delta > 0) delta = (uint32_t)c.opt.batch_delta;
+    else if (c.opt.batch_delta_factor > 0) delta = sssp_auto_delta(g, c.opt.batch_delta_factor);
     c.arena.reserve(al256(256ull * n) + al256(8ull * n) + 2 * al256(64ull * n) + 2 * al256(32ull * nwords) +
                     3 * al256(4ull * n) + al256(4 * nparts) + al256(8ull * G) + al256(16ull * cg.blocks) +
                     al256(sizeof(BsCtl)) + al256(4 * 64));

@@ -88,3 +88,31 @@ def test_structural_checks_without_validate_flag():
     col = np.array([1], np.int32)
     assert gfr.validate_csr(row, col, validate=False)[0]          # asymmetric passes the basic check
     assert not gfr.validate_csr(np.array([1, 1], np.int32), np.zeros(0, np.int32), validate=False)[0]
+
+
+@pytest.mark.parametrize("text,ok", [
+    ('{}', True),
+    ('{"advance.chunk": 2048, "bfs.alpha": 12.5}', True),
+    ('{"scalefree": {"bfs.alpha": 20, "batch.min_sssp": 16}, "mesh": {"sssp.delta": 3000}}', True),
+    (' { "mesh" : { } , "serve.max_batch" : 32 } ', True),
+    ('{"no.such.option": 1}', False),
+    ('{"advance.chunk": 300}', False),                     # not a power of two in range
+    ('{"bfs.alpha": -1}', False),                          # out of range
+    ('{"mesh": {"serve.max_batch": 8}}', False),          # not a per-class option
+    ('{"planar": {"bfs.alpha": 3}}', False),               # unknown class
+    ('{"bfs.alpha": "fast"}', False),
+    ('{"bfs.alpha": 3', False),
+    ('{"bfs.alpha": 3} x', False),
+    ('[1, 2]', False),
+])
+def test_tuning_file_is_checked_before_the_device(text, ok):
+    L = gfr.lib()
+    p = ctypes.c_void_p()
+    st = L.gfr_ctx_create(0, text.encode(), ctypes.byref(p))
+    if ok:
+        # accepted: fails only for want of a device (or succeeds on a GPU host)
+        assert st in (gfr.GFR_OK, gfr.GFR_E_DEVICE), st
+        if st == gfr.GFR_OK:
+            L.gfr_ctx_destroy(p.value)
+    else:
+        assert st == gfr.GFR_E_INVALID, st

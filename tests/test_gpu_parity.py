@@ -325,8 +325,16 @@ def test_batch_many_sources(ctx, name, k):
             src[-1] = iso[0]                             # an isolated source
     g = _load(ctx, row, col, w)
     _say("batch", name, "k", k)
-    d = _host(ctx.bfs_batch(g, src)).reshape(k, n)
-    s = _host(ctx.sssp_batch(g, src)).view(np.uint32).reshape(k, n)
+    for mb in (1, 10 ** 6):      # shared traversal for every k, then sequential solves
+        ctx.set_option("batch.min_bfs", mb)
+        ctx.set_option("batch.min_sssp", mb)
+        d = _host(ctx.bfs_batch(g, src)).reshape(k, n)
+        s = _host(ctx.sssp_batch(g, src)).view(np.uint32).reshape(k, n)
+        if mb == 1:
+            d1, s1 = d.copy(), s.copy()
+    ctx.set_option("batch.min_bfs", 8)
+    ctx.set_option("batch.min_sssp", 24)
+    assert np.array_equal(d, d1) and np.array_equal(s, s1)
     for i in range(0, k, max(1, k // 9)):
         assert np.array_equal(d[i], oracle.bfs(row, col, src[i])), (name, k, i)
         assert np.array_equal(s[i], oracle.sssp(row, col, w, src[i])), (name, k, i)
@@ -341,14 +349,16 @@ def test_sssp_batch_buckets(ctx, delta):
     n = row.size - 1
     src = np.arange(0, n, n // 40, dtype=np.int32)[:40]
     g = _load(ctx, row, col, w)
-    ctx.set_option("sssp.delta", delta)
+    ctx.set_option("batch.delta", delta)
+    ctx.set_option("batch.min_sssp", 1)
     try:
         _say("sssp_batch grid96 delta", delta)
         s = _host(ctx.sssp_batch(g, src)).view(np.uint32).reshape(len(src), n)
         for i in (0, 7, 39):
             assert np.array_equal(s[i], oracle.sssp(row, col, w, src[i]))
     finally:
-        ctx.set_option("sssp.delta", 0)
+        ctx.set_option("batch.delta", 0)
+        ctx.set_option("batch.min_sssp", 24)
         g.free()
 
 
@@ -365,5 +375,5 @@ def test_bfs_batch_directions(ctx, alpha):
         for i in (0, 31, 63):
             assert np.array_equal(d[i], oracle.bfs(row, col, src[i]))
     finally:
-        ctx.set_option("msbfs.alpha", 24)
+        ctx.set_option("msbfs.alpha", 4)
         g.free()
