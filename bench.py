@@ -140,9 +140,12 @@ def main():
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--edge-factor", type=int, default=16)
     ap.add_argument("--sources", type=int, default=64)
-    ap.add_argument("--cpu-sources", type=int, default=1, help="oracle sample size (sources)")
+    ap.add_argument("--cpu-sources", type=int, default=4, help="oracle sample size (sources)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-queries", type=int, default=256, help="queries per serving point (0: skip)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="finish with one device copy of this many MiB (a known-size kernel that "
+                         "calibrates the HBM byte counters of a profiler run)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -294,6 +297,16 @@ def main():
                    "serving": serving},
     }
     print(json.dumps(line), flush=True)
+    if args.copy_probe_mib > 0:
+        # an elementwise kernel (not a DMA copy) that reads and writes exactly nb bytes
+        nw = (args.copy_probe_mib << 20) // 4
+        a = torch.ones(nw, dtype=torch.int32, device=dev)
+        b = torch.empty(nw, dtype=torch.int32, device=dev)
+        torch.cuda.synchronize()
+        torch.bitwise_not(a, out=b)
+        torch.cuda.synchronize()
+        log("copy probe: bitwise_not over %d MiB (reads and writes %d bytes)" % (args.copy_probe_mib, nw * 4))
+        del a, b
     g.free()
     ctx.close()
 

@@ -55,7 +55,7 @@ struct BsArgs {
     BsCtl *ctl;
 };
 
-constexpr int BS_UNROLL = 16;
+constexpr int BS_UNROLL = 8;
 
 template <int CH>
 __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
@@ -383,7 +383,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     const uint32_t chunk = 1024;
     const uint32_t nwords = (uint32_t)(((int64_t)n + 63) / 64) * 2u;
     const size_t nparts = (size_t)(g.m / chunk) + 2;
-    const int G = grid_blocks(c, 4);
+    const int G = grid_blocks(c, 7);   // 68 VGPRs: seven 4-wave work-groups fit per CU
     const CompactGeom cg = compact_geom(nwords, c.num_cu);
     // one shared bucket serves all queries; a narrow bucket desynchronises the
     // queries' frontiers and multiplies edge visits, so the default is a
