@@ -199,6 +199,19 @@ def main():
     value = (te_bfs + te_sssp) / t_step / 1e9
     log("timed %d steps: %.2f ms/step, %.1f GTEPS" % (args.steps, t_step * 1e3, value))
 
+    # the same step with host output buffers (results cross PCIe inside the calls)
+    hdep = np.empty(args.sources * n, np.int32)
+    hdist = np.empty(args.sources * n, np.uint32)
+    torch.cuda.synchronize()
+    th = time.perf_counter()
+    ctx.bfs_batch(g, srcs, out=hdep)
+    ctx.sssp_batch(g, srcs, out=hdist)
+    t_host = time.perf_counter() - th
+    host_ok = bool(np.array_equal(hdep, dep.cpu().numpy()) and np.array_equal(hdist.view(np.int32), dist.cpu().numpy()))
+    log("host-output step: %.2f ms (%.1f GTEPS incl. PCIe), same results %s"
+        % (t_host * 1e3, (te_bfs + te_sssp) / t_host / 1e9, host_ok))
+    del hdep, hdist
+
     # per-primitive split of one step (library event timing of each whole call)
     torch.cuda.synchronize()
     ctx.bfs_batch(g, srcs, out=dep)
@@ -294,7 +307,10 @@ def main():
                    "ms_bfs_64": round(ms_bfs, 3), "ms_sssp_64": round(ms_sssp, 3),
                    "edges_traversed_per_step": te_bfs + te_sssp, "kernels": kernels,
                    "parity_sample_ok": parity, "source_digest": kernel_source_digest(),
-                   "serving": serving},
+                   "serving": serving,
+                   "host_output_step_ms": round(t_host * 1e3, 3),
+                   "host_output_gteps": round((te_bfs + te_sssp) / t_host / 1e9, 3),
+                   "host_output_same": host_ok},
     }
     print(json.dumps(line), flush=True)
     if args.copy_probe_mib > 0:

@@ -66,10 +66,13 @@ __global__ __launch_bounds__(GFR_BLOCK) void msbfs_level(MsArgs a)
     MsCtl *ctl = a.ctl;
     const uint32_t dir = ctl->dir;
     if (dir == MS_DONE || ctl->level < 0) return;
+    // one LDS block serves both directions (28.7 KB at CH = 1024: five
+    // work-groups per CU)
+    __shared__ unsigned long long s_raw[2 * (CH + 1) + 3 * (CH + 2) / 2];
     if (dir == MS_PUSH) {
-        __shared__ uint32_t s_off[CH + 1];
-        __shared__ int32_t s_row[CH + 1];
-        __shared__ unsigned long long s_m[CH + 1];
+        unsigned long long *s_m = s_raw;
+        uint32_t *s_off = (uint32_t *)(s_raw + (CH + 1));
+        int32_t *s_row = (int32_t *)(s_off + (CH + 1));
         const uint32_t mf = ctl->mf, nf = ctl->nf;
         const FrontierQ q = a.q;
         const uint32_t nchunks = (mf + CH - 1) / CH;
@@ -86,25 +89,40 @@ __global__ __launch_bounds__(GFR_BLOCK) void msbfs_level(MsArgs a)
                 s_m[i] = a.fr[q.v[s + i]];
             }
             __syncthreads();
-#pragma unroll 2
-            for (uint32_t k = 0; k < (uint32_t)CH; k += GFR_BLOCK) {
-                const uint32_t e = e0 + k + threadIdx.x;
-                if (e < e1) {
-                    const int i = upper_index(s_off, 0, cnt - 1, e);
-                    const int32_t v = a.C[s_row[i] + (int32_t)(e - s_off[i])];
-                    const unsigned long long add = s_m[i] & ~(a.vis[v] | a.nx[v]);
-                    if (add) atomicOr(a.nx + v, add);
-                }
+            // each thread takes every GFR_BLOCK-th edge of the chunk; all its
+            // column loads are issued first, then all mask loads (an edge past
+            // the chunk end repeats the chunk's first edge and adds nothing)
+            constexpr int PER = CH / GFR_BLOCK;
+            int32_t vv[PER];
+            unsigned long long mm[PER], vis[PER], nx[PER];
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const uint32_t e = e0 + p * GFR_BLOCK + threadIdx.x;
+                const bool ok = e < e1;
+                const uint32_t ec = ok ? e : e0;
+                const int i = upper_index(s_off, 0, cnt - 1, ec);
+                vv[p] = a.C[s_row[i] + (int32_t)(ec - s_off[i])];
+                mm[p] = ok ? s_m[i] : 0ull;
+            }
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                vis[p] = a.vis[vv[p]];
+                nx[p] = a.nx[vv[p]];
+            }
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const unsigned long long add = mm[p] & ~(vis[p] | nx[p]);
+                if (add) atomicOr(a.nx + vv[p], add);
             }
         }
     } else {
         // pull: load-balanced sweep over every vertex's list (the whole-graph
         // queue), OR of the neighbours' frontier masks per vertex in LDS,
         // restricted to the sources the vertex still needs
-        __shared__ uint32_t s_off[CH + 1];
-        __shared__ int32_t s_row[CH + 1];
-        __shared__ int32_t s_v[CH + 1];
-        __shared__ unsigned long long s_need[CH + 1], s_acc[CH + 1];
+        unsigned long long *s_need = s_raw, *s_acc = s_raw + (CH + 1);
+        uint32_t *s_off = (uint32_t *)(s_raw + 2 * (CH + 1));
+        int32_t *s_row = (int32_t *)(s_off + (CH + 1));
+        int32_t *s_v = s_row + (CH + 1);
         const FrontierQ q = a.full;
         const uint32_t nf = a.full_nf, mf = a.full_mf;
         const uint32_t nchunks = (mf + CH - 1) / CH;
@@ -236,7 +254,7 @@ void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t 
     const uint32_t chunk = 1024;
     const uint32_t nwords = (uint32_t)(((int64_t)n + 63) / 64) * 2u;
     const size_t nparts = (size_t)(g.m / chunk) + 2;
-    const int G = grid_blocks(c, 4);
+    const int G = grid_blocks(c, 5);   // the level kernel (28.7 KB of LDS) fits five work-groups per CU
     const CompactGeom cg = compact_geom(nwords, c.num_cu);
     c.arena.reserve(3 * al256(8ull * n) + al256(32ull * nwords) + 3 * al256(4ull * n) + al256(4 * nparts) +
                     al256(16ull * cg.blocks) + al256(sizeof(MsCtl)) + al256(4 * 64));

@@ -15,7 +15,10 @@
 //
 // Every iteration is two launches:
 //   bsssp_relax   load-balanced edge chunks over the near queue; each wave
-//                 walks a quarter of the chunk, eight edges in flight.
+//                 takes a quarter of the chunk, 64 edges at a time: lane l
+//                 fetches edge l's target, weight, source and query mask
+//                 (coalesced), then the wave relaxes the 64 edges eight at a
+//                 time with their sixteen distance rows in flight.
 //   compact       near queue in vertex order with its per-vertex query masks,
 //                 or, when the near queue has run dry, the far split with
 //                 the next bucket (compact.h), plus the control.
@@ -55,7 +58,9 @@ struct BsArgs {
     BsCtl *ctl;
 };
 
-constexpr int BS_UNROLL = 8;
+constexpr int BS_UNROLL = 8;   // edges relaxed together (two distance rows each)
+
+__device__ __forceinline__ int32_t lane_bcast(int32_t x, int j) { return __builtin_amdgcn_readlane(x, j); }
 
 template <int CH>
 __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
@@ -67,7 +72,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
     __shared__ uint32_t s_off[CH + 1];
     __shared__ int32_t s_row[CH + 1];
     __shared__ int32_t s_v[CH + 1];
-    const int lane = lane_id(), wave = threadIdx.x / 64;
+    const int lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     constexpr uint32_t QW = CH / GFR_WAVES;
     const uint32_t nchunks = (mf + CH - 1) / CH;
     uint32_t nimp = 0, nfar = 0;
@@ -87,69 +92,67 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
         __syncthreads();
         const uint32_t eb = e0 + wave * QW, ee = min(eb + QW, e1);
         if (eb >= ee) continue;
-        int i = upper_index(s_off, 0, cnt - 1, eb);
-        int32_t u = s_v[i];
-        uint32_t du = a.D[(size_t)u * 64 + lane];
-        bool act = (a.qm[u] >> lane) & 1ull;
-        for (uint32_t e = eb; e < ee; e += BS_UNROLL) {
-            int32_t vv[BS_UNROLL];
-            uint32_t ww[BS_UNROLL], dd[BS_UNROLL], dv[BS_UNROLL];
-            bool aa[BS_UNROLL];
-            // resolve sources and fetch targets/weights (wave-uniform)
-#pragma unroll
-            for (int j = 0; j < BS_UNROLL; ++j) {
-                const uint32_t ej = e + j;
-                aa[j] = false;
-                vv[j] = 0;
-                ww[j] = 0;
-                dd[j] = 0;
-                if (ej < ee) {
-                    while (i + 1 < cnt && s_off[i + 1] <= ej) {
-                        ++i;
-                        u = s_v[i];
-                        du = a.D[(size_t)u * 64 + lane];
-                        act = (a.qm[u] >> lane) & 1ull;
-                    }
-                    const int32_t idx = s_row[i] + (int32_t)(ej - s_off[i]);
-                    vv[j] = a.C[idx];
-                    ww[j] = a.W[idx];
-                    dd[j] = du;
-                    aa[j] = act;
-                }
+        int ilo = upper_index(s_off, 0, cnt - 1, eb);
+        for (uint32_t e = eb; e < ee; e += 64) {
+            // lane l describes edge e + l: its target, weight, source and the
+            // source's query mask.  ilo holds edge e - 1 (or e), and every
+            // queued vertex has an edge, so edge e + l lies in entry
+            // ilo + l + 1 at the latest.
+            const int nb = (int)min(64u, ee - e);
+            int32_t vl = 0, wl = 0, ul = 0, il = ilo;
+            unsigned long long ql = 0;
+            if (lane < nb) {
+                const uint32_t el = e + lane;
+                il = upper_index(s_off, ilo, min(cnt - 1, ilo + lane + 1), el);
+                const int32_t idx = s_row[il] + (int32_t)(el - s_off[il]);
+                vl = a.C[idx];
+                wl = (int32_t)a.W[idx];
+                ul = s_v[il];
+                ql = a.qm[ul];
             }
+            ilo = lane_bcast(il, nb - 1);
+            const int32_t qlo = (int32_t)(uint32_t)ql, qhi = (int32_t)(uint32_t)(ql >> 32);
+            for (int j0 = 0; j0 < nb; j0 += BS_UNROLL) {
+                // every load is unconditional (a padded edge repeats the last
+                // one) and the tests are computed for every lane, so that no
+                // load is moved into a branch and waited for there
+                uint32_t du[BS_UNROLL], dv[BS_UNROLL], ww[BS_UNROLL], qw[BS_UNROLL];
+                int32_t vv[BS_UNROLL];
 #pragma unroll
-            for (int j = 0; j < BS_UNROLL; ++j) dv[j] = aa[j] ? a.D[(size_t)vv[j] * 64 + lane] : 0u;
-#pragma unroll
-            for (int j = 0; j < BS_UNROLL; ++j) {
-                bool near_imp = false, far_imp = false;
-                if (aa[j]) {
-                    const unsigned long long nd64 = (unsigned long long)dd[j] + ww[j];
-                    if (nd64 >= 0xFFFFFFFFull) {
-                        ovf = true;
-                    } else {
-                        const uint32_t nd = (uint32_t)nd64;
-                        // non-returning atomicMin: the mark follows the pre-check, a
-                        // superset of the true improvements (a marked vertex is simply
-                        // relaxed again with its current distance)
-                        if (nd < dv[j]) {
-                            atomicMin(a.D + (size_t)vv[j] * 64 + lane, nd);
-                            ++nimp;
-                            if (nd < hi) {
-                                a.nmark[(size_t)vv[j] * 64 + lane] = 1;
-                                near_imp = true;
-                            } else {
-                                a.fmark[(size_t)vv[j] * 64 + lane] = 1;
-                                far_imp = true;
-                            }
-                        }
-                    }
+                for (int j = 0; j < BS_UNROLL; ++j) {
+                    const int src = min(j0 + j, nb - 1);
+                    const int32_t u = lane_bcast(ul, src);
+                    vv[j] = lane_bcast(vl, src);
+                    ww[j] = (uint32_t)lane_bcast(wl, src);
+                    const uint32_t q0 = (uint32_t)lane_bcast(qlo, src), q1 = (uint32_t)lane_bcast(qhi, src);
+                    qw[j] = lane < 32 ? q0 : q1;
+                    du[j] = a.D[(size_t)u * 64 + lane];
+                    dv[j] = a.D[(size_t)vv[j] * 64 + lane];
                 }
-                const uint64_t bn = ballot(near_imp), bf = ballot(far_imp);
-                if (lane == 0) {
-                    if (bn) a.nany[vv[j]] = 1;
-                    if (bf) {
-                        a.fany[vv[j]] = 1;
-                        ++nfar;
+#pragma unroll
+                for (int j = 0; j < BS_UNROLL; ++j) {
+                    const bool act = (j0 + j < nb) & (((qw[j] >> (lane & 31)) & 1u) != 0);
+                    const unsigned long long nd64 = (unsigned long long)du[j] + ww[j];
+                    const bool fits = nd64 < 0xFFFFFFFFull;
+                    const uint32_t nd = (uint32_t)nd64;
+                    const bool imp = act & fits & (nd < dv[j]);
+                    ovf |= act & !fits;
+                    // non-returning atomicMin: the mark follows the pre-check, a
+                    // superset of the true improvements (a marked vertex is simply
+                    // relaxed again with its current distance)
+                    const bool near_imp = imp & (nd < hi), far_imp = imp & (nd >= hi);
+                    if (imp) {
+                        atomicMin(a.D + (size_t)vv[j] * 64 + lane, nd);
+                        ++nimp;
+                        (near_imp ? a.nmark : a.fmark)[(size_t)vv[j] * 64 + lane] = 1;
+                    }
+                    const uint64_t bn = ballot(near_imp), bf = ballot(far_imp);
+                    if (lane == 0) {
+                        if (bn) a.nany[vv[j]] = 1;
+                        if (bf) {
+                            a.fany[vv[j]] = 1;
+                            ++nfar;
+                        }
                     }
                 }
             }
@@ -383,7 +386,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     const uint32_t chunk = 1024;
     const uint32_t nwords = (uint32_t)(((int64_t)n + 63) / 64) * 2u;
     const size_t nparts = (size_t)(g.m / chunk) + 2;
-    const int G = grid_blocks(c, 7);   // 68 VGPRs: seven 4-wave work-groups fit per CU
+    const int G = grid_blocks(c, 7);   // the relax kernel fits seven work-groups per CU
     const CompactGeom cg = compact_geom(nwords, c.num_cu);
     // one shared bucket serves all queries; a narrow bucket desynchronises the
     // queries' frontiers and multiplies edge visits, so the default is a
