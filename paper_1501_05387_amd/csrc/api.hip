@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "engine.h"
@@ -49,6 +50,63 @@ void fill_u32(void *p, uint32_t value, size_t count, hipStream_t s)
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t *)p, value, count);
     GFR_LAUNCH_CHECK();
+}
+
+static bool is_pinned_host(const void *p)
+{
+    hipPointerAttribute_t attr;
+    memset(&attr, 0, sizeof attr);
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeHost;
+}
+
+static void parallel_memcpy(char *dst, const char *src, size_t bytes)
+{
+    constexpr size_t kSlice = 4u << 20;
+    const size_t nt = std::min<size_t>(8, (bytes + kSlice - 1) / kSlice);
+    if (nt <= 1) {
+        memcpy(dst, src, bytes);
+        return;
+    }
+    const size_t per = (bytes + nt - 1) / nt;
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < nt; ++t) {
+        const size_t o = t * per, l = o < bytes ? std::min(per, bytes - o) : 0;
+        if (l) th.emplace_back([=]() { memcpy(dst + o, src + o, l); });
+    }
+    memcpy(dst, src, std::min(per, bytes));
+    for (auto &x : th) x.join();
+}
+
+void copy_to_host(Ctx &c, void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return;
+    if (is_pinned_host(dst)) {
+        GFR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+        GFR_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    constexpr size_t kChunk = 32u << 20;
+    for (int i = 0; i < 2; ++i) {
+        if (!c.bounce[i]) GFR_HIP(hipHostMalloc((void **)&c.bounce[i], kChunk, hipHostMallocDefault));
+        if (!c.bounce_ev[i]) GFR_HIP(hipEventCreateWithFlags(&c.bounce_ev[i], hipEventDisableTiming));
+    }
+    const size_t nch = (bytes + kChunk - 1) / kChunk;
+    auto len = [&](size_t j) { return std::min(kChunk, bytes - j * kChunk); };
+    auto enqueue = [&](size_t j) {
+        GFR_HIP(hipMemcpyAsync(c.bounce[j & 1], (const char *)src + j * kChunk, len(j), hipMemcpyDeviceToHost, s));
+        GFR_HIP(hipEventRecord(c.bounce_ev[j & 1], s));
+    };
+    enqueue(0);
+    for (size_t j = 0; j < nch; ++j) {
+        // buffer (j+1)&1 was drained by the host copy of chunk j-1 just below
+        if (j + 1 < nch) enqueue(j + 1);
+        GFR_HIP(hipEventSynchronize(c.bounce_ev[j & 1]));
+        parallel_memcpy((char *)dst + j * kChunk, c.bounce[j & 1], len(j));
+    }
 }
 
 // Host check of a CSR graph; returns an empty string when it is acceptable.
@@ -153,9 +211,9 @@ struct OutBuf {
             staged = true;
         }
     }
-    void finish(hipStream_t s)
+    void finish(Ctx &c, hipStream_t s)
     {
-        if (staged) GFR_HIP(hipMemcpyAsync(user, dev, bytes, hipMemcpyDeviceToHost, s));
+        if (staged) copy_to_host(c, user, dev, bytes, s);
         GFR_HIP(hipStreamSynchronize(s));
     }
 };
@@ -432,6 +490,10 @@ gfr_status gfr_ctx_destroy(gfr_ctx *ctx)
     c->stage.release();
     c->zero_word.release();
     if (c->pinned) (void)hipHostFree(c->pinned);
+    for (int i = 0; i < 2; ++i) {
+        if (c->bounce[i]) (void)hipHostFree(c->bounce[i]);
+        if (c->bounce_ev[i]) (void)hipEventDestroy(c->bounce_ev[i]);
+    }
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -561,7 +623,7 @@ gfr_status gfr_bfs(gfr_ctx *ctx, gfr_graph gh, int32_t source, int32_t *depth_ou
         timed_begin(c, s);
         run_bfs(c, g, source, (int32_t *)o.dev, s);
         timed_end(c, s);
-        o.finish(s);
+        o.finish(c, s);
     });
 }
 
@@ -577,7 +639,7 @@ gfr_status gfr_sssp(gfr_ctx *ctx, gfr_graph gh, int32_t source, uint32_t *dist_o
         timed_begin(c, s);
         run_sssp(c, g, source, (uint32_t *)o.dev, s);
         timed_end(c, s);
-        o.finish(s);
+        o.finish(c, s);
     });
 }
 
@@ -600,7 +662,7 @@ gfr_status gfr_bc(gfr_ctx *ctx, gfr_graph gh, const int32_t *sources, int32_t k,
         timed_begin(c, s);
         run_bc(c, g, src.data(), k, (float *)o.dev, s);
         timed_end(c, s);
-        o.finish(s);
+        o.finish(c, s);
     });
 }
 
@@ -616,7 +678,7 @@ gfr_status gfr_cc(gfr_ctx *ctx, gfr_graph gh, int32_t *label_out, int32_t *num_c
         timed_begin(c, s);
         run_cc(c, g, (int32_t *)o.dev, &nc, s);
         timed_end(c, s);
-        o.finish(s);
+        o.finish(c, s);
         if (num_components_out) *num_components_out = nc;
     });
 }
@@ -637,7 +699,7 @@ gfr_status gfr_pagerank(gfr_ctx *ctx, gfr_graph gh, float damping, double l1_tol
         timed_begin(c, s);
         run_pagerank(c, g, damping, l1_tol, max_iter, (float *)o.dev, &it, &l1, s);
         timed_end(c, s);
-        o.finish(s);
+        o.finish(c, s);
         if (iters_out) *iters_out = it;
         if (final_l1_out) *final_l1_out = l1;
     });
@@ -657,7 +719,7 @@ gfr_status gfr_bfs_batch(gfr_ctx *ctx, gfr_graph gh, const int32_t *sources, int
         timed_begin(c, s);
         run_bfs_batch(c, g, sources, k, (int32_t *)o.dev, s);
         timed_end(c, s);
-        o.finish(s);
+        o.finish(c, s);
     });
 }
 
@@ -676,7 +738,7 @@ gfr_status gfr_sssp_batch(gfr_ctx *ctx, gfr_graph gh, const int32_t *sources, in
         timed_begin(c, s);
         run_sssp_batch(c, g, sources, k, (uint32_t *)o.dev, s);
         timed_end(c, s);
-        o.finish(s);
+        o.finish(c, s);
     });
 }
 

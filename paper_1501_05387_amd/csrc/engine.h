@@ -214,7 +214,16 @@ struct Ctx {
     Server *server = nullptr;     // owned; destroyed by serve_shutdown
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     KernelTimer ktimer;
+    // bounce buffers for results written to pageable host memory
+    char *bounce[2] = {nullptr, nullptr};
+    hipEvent_t bounce_ev[2] = {nullptr, nullptr};
 };
+
+// Copy `bytes` of device memory to host memory `dst` on stream s and wait for
+// it.  Pinned destinations take one DMA; pageable ones go through two pinned
+// bounce buffers, the DMA of one chunk overlapping the threaded host copy of
+// the previous one.
+void copy_to_host(Ctx &c, void *dst, const void *src, size_t bytes, hipStream_t s);
 
 // While alive, c.opt holds the options for graph g: the tuning file's
 // values for g's class over the context-wide ones, except for options the

@@ -137,8 +137,10 @@ static void worker_loop(Server *sv)
                         std::lock_guard<std::mutex> lk(sv->mu);
                         q = sv->tickets[batch[i]].q;
                     }
-                    GFR_HIP(hipMemcpyAsync(q.out, (char *)sv->stage.p + row * i, row,
-                                           q.out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+                    if (q.out_on_device)
+                        GFR_HIP(hipMemcpyAsync(q.out, (char *)sv->stage.p + row * i, row, hipMemcpyDeviceToDevice, s));
+                    else
+                        copy_to_host(c, q.out, (char *)sv->stage.p + row * i, row, s);
                 }
                 GFR_HIP(hipStreamSynchronize(s));
             } catch (const Error &e) {

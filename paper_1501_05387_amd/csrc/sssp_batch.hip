@@ -18,7 +18,9 @@
 //                 takes a quarter of the chunk, 64 edges at a time: lane l
 //                 fetches edge l's target, weight, source and query mask
 //                 (coalesced), then the wave relaxes the 64 edges eight at a
-//                 time with their sixteen distance rows in flight.
+//                 time with their sixteen distance rows in flight; a group
+//                 whose 64 edges all leave one vertex loads that vertex's
+//                 row once.
 //   compact       near queue in vertex order with its per-vertex query masks,
 //                 or, when the near queue has run dry, the far split with
 //                 the next bucket (compact.h), plus the control.
@@ -112,48 +114,71 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
             }
             ilo = lane_bcast(il, nb - 1);
             const int32_t qlo = (int32_t)(uint32_t)ql, qhi = (int32_t)(uint32_t)(ql >> 32);
-            for (int j0 = 0; j0 < nb; j0 += BS_UNROLL) {
-                // every load is unconditional (a padded edge repeats the last
-                // one) and the tests are computed for every lane, so that no
-                // load is moved into a branch and waited for there
-                uint32_t du[BS_UNROLL], dv[BS_UNROLL], ww[BS_UNROLL], qw[BS_UNROLL];
-                int32_t vv[BS_UNROLL];
-#pragma unroll
-                for (int j = 0; j < BS_UNROLL; ++j) {
-                    const int src = min(j0 + j, nb - 1);
-                    const int32_t u = lane_bcast(ul, src);
-                    vv[j] = lane_bcast(vl, src);
-                    ww[j] = (uint32_t)lane_bcast(wl, src);
-                    const uint32_t q0 = (uint32_t)lane_bcast(qlo, src), q1 = (uint32_t)lane_bcast(qhi, src);
-                    qw[j] = lane < 32 ? q0 : q1;
-                    du[j] = a.D[(size_t)u * 64 + lane];
-                    dv[j] = a.D[(size_t)vv[j] * 64 + lane];
+            // one relaxation of edge (u, v, w) for this lane's query; the test
+            // is computed for every lane, so that no load is moved into a
+            // branch and waited for there
+            auto relax = [&](int32_t v, uint32_t w, uint32_t du, uint32_t dv, bool act) {
+                const unsigned long long nd64 = (unsigned long long)du + w;
+                const bool fits = nd64 < 0xFFFFFFFFull;
+                const uint32_t nd = (uint32_t)nd64;
+                const bool imp = act & fits & (nd < dv);
+                ovf |= act & !fits;
+                // non-returning atomicMin: the mark follows the pre-check, a
+                // superset of the true improvements (a marked vertex is simply
+                // relaxed again with its current distance)
+                const bool near_imp = imp & (nd < hi), far_imp = imp & (nd >= hi);
+                if (imp) {
+                    atomicMin(a.D + (size_t)v * 64 + lane, nd);
+                    ++nimp;
+                    (near_imp ? a.nmark : a.fmark)[(size_t)v * 64 + lane] = 1;
                 }
+                const uint64_t bn = ballot(near_imp), bf = ballot(far_imp);
+                if (lane == 0) {
+                    if (bn) a.nany[v] = 1;
+                    if (bf) {
+                        a.fany[v] = 1;
+                        ++nfar;
+                    }
+                }
+            };
+            const int32_t u_first = lane_bcast(ul, 0);
+            if (u_first == lane_bcast(ul, nb - 1)) {
+                // the whole group leaves one vertex (edges are in source
+                // order): its distance row and query bit are loaded once
+                const uint32_t du = a.D[(size_t)u_first * 64 + lane];
+                const uint32_t q0 = (uint32_t)lane_bcast(qlo, 0), q1 = (uint32_t)lane_bcast(qhi, 0);
+                const bool act_u = (((lane < 32 ? q0 : q1) >> (lane & 31)) & 1u) != 0;
+                for (int j0 = 0; j0 < nb; j0 += BS_UNROLL) {
+                    uint32_t dv[BS_UNROLL], ww[BS_UNROLL];
+                    int32_t vv[BS_UNROLL];
 #pragma unroll
-                for (int j = 0; j < BS_UNROLL; ++j) {
-                    const bool act = (j0 + j < nb) & (((qw[j] >> (lane & 31)) & 1u) != 0);
-                    const unsigned long long nd64 = (unsigned long long)du[j] + ww[j];
-                    const bool fits = nd64 < 0xFFFFFFFFull;
-                    const uint32_t nd = (uint32_t)nd64;
-                    const bool imp = act & fits & (nd < dv[j]);
-                    ovf |= act & !fits;
-                    // non-returning atomicMin: the mark follows the pre-check, a
-                    // superset of the true improvements (a marked vertex is simply
-                    // relaxed again with its current distance)
-                    const bool near_imp = imp & (nd < hi), far_imp = imp & (nd >= hi);
-                    if (imp) {
-                        atomicMin(a.D + (size_t)vv[j] * 64 + lane, nd);
-                        ++nimp;
-                        (near_imp ? a.nmark : a.fmark)[(size_t)vv[j] * 64 + lane] = 1;
+                    for (int j = 0; j < BS_UNROLL; ++j) {
+                        const int src = min(j0 + j, nb - 1);   // a padded edge repeats the last one
+                        vv[j] = lane_bcast(vl, src);
+                        ww[j] = (uint32_t)lane_bcast(wl, src);
+                        dv[j] = a.D[(size_t)vv[j] * 64 + lane];
                     }
-                    const uint64_t bn = ballot(near_imp), bf = ballot(far_imp);
-                    if (lane == 0) {
-                        if (bn) a.nany[vv[j]] = 1;
-                        if (bf) {
-                            a.fany[vv[j]] = 1;
-                            ++nfar;
-                        }
+#pragma unroll
+                    for (int j = 0; j < BS_UNROLL; ++j) relax(vv[j], ww[j], du, dv[j], act_u & (j0 + j < nb));
+                }
+            } else {
+                for (int j0 = 0; j0 < nb; j0 += BS_UNROLL) {
+                    uint32_t du[BS_UNROLL], dv[BS_UNROLL], ww[BS_UNROLL], qw[BS_UNROLL];
+                    int32_t vv[BS_UNROLL];
+#pragma unroll
+                    for (int j = 0; j < BS_UNROLL; ++j) {
+                        const int src = min(j0 + j, nb - 1);
+                        const int32_t u = lane_bcast(ul, src);
+                        vv[j] = lane_bcast(vl, src);
+                        ww[j] = (uint32_t)lane_bcast(wl, src);
+                        const uint32_t q0 = (uint32_t)lane_bcast(qlo, src), q1 = (uint32_t)lane_bcast(qhi, src);
+                        qw[j] = lane < 32 ? q0 : q1;
+                        du[j] = a.D[(size_t)u * 64 + lane];
+                        dv[j] = a.D[(size_t)vv[j] * 64 + lane];
                     }
+#pragma unroll
+                    for (int j = 0; j < BS_UNROLL; ++j)
+                        relax(vv[j], ww[j], du[j], dv[j], (j0 + j < nb) & (((qw[j] >> (lane & 31)) & 1u) != 0));
                 }
             }
         }

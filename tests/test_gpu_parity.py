@@ -377,3 +377,25 @@ def test_bfs_batch_directions(ctx, alpha):
     finally:
         ctx.set_option("msbfs.alpha", 4)
         g.free()
+
+
+def test_host_outputs_span_several_bounce_chunks(ctx):
+    """Batched results written to pageable (numpy) and pinned (torch) host
+    memory equal the device results; 64 x 2^18 x 4 bytes spans three 32 MiB
+    bounce chunks, the last one ragged."""
+    import torch
+    row, col = graphgen.rmat(18)
+    w = graphgen.weights(row, col, 64)
+    n = row.size - 1
+    g = _load(ctx, row, col, w)
+    src = graphgen.sample_sources(row, col, 64)
+    _say("host outputs rmat18 k=64")
+    dev = ctx.sssp_batch(g, src).cpu().numpy().view(np.uint32)
+    host = np.empty(64 * n, np.uint32)
+    ctx.sssp_batch(g, src, out=host)
+    assert np.array_equal(host, dev)
+    pinned = torch.empty(64 * n, dtype=torch.int32, pin_memory=True)
+    ctx.bfs_batch(g, src, out=pinned)
+    assert np.array_equal(pinned.numpy(), ctx.bfs_batch(g, src).cpu().numpy())
+    assert np.array_equal(pinned.numpy()[:n], oracle.bfs(row, col, src[0]))
+    g.free()
