@@ -168,7 +168,7 @@ def main():
     n, m = row.size - 1, col.size
     log("graph scale %d: n=%d m=%d (%.1fs)" % (args.scale, n, m, time.time() - t0))
 
-    ctx = gfr.Context(0)
+    ctx = gfr.Context(0, tuning_json=gfr.tuned_json())   # the autotuner's per-class choices (results-neutral)
     g = ctx.graph_load_csr(row, col, w)
     dev = torch.device("cuda:0")
     dep = torch.empty(args.sources * n, dtype=torch.int32, device=dev)

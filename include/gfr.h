@@ -19,7 +19,9 @@
  *     the library keeps no reference to caller buffers (except the serving
  *     calls, which lend `out` until the ticket completes).
  *   - `stream` is a hipStream_t of the context's device, or NULL for the
- *     context's own stream.  Work is enqueued on it and waited for.
+ *     context's own stream, a blocking stream: work queued earlier on the
+ *     device's null stream (PyTorch's default stream) completes before the
+ *     call's first kernel.  Work is enqueued on it and waited for.
  *   - One context may be used from several host threads; calls on one context
  *     are serialised internally.
  */

@@ -19,6 +19,15 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgfr.so")
+# tuning file written by ``python -m paper_1501_05387_amd.autotune`` on an MI355X
+# (R-MAT s16/s20/s22 for the scale-free class, a 2048^2 lattice for the mesh class)
+TUNED_PATH = os.path.join(_HERE, "tuning_mi355x.json")
+
+
+def tuned_json() -> str:
+    """The packaged MI355X tuning file (for ``Context(tuning_json=...)``)."""
+    with open(TUNED_PATH) as f:
+        return f.read()
 
 GFR_OK, GFR_E_INVALID, GFR_E_OOM, GFR_E_DEVICE = 0, -1, -2, -3
 GFR_E_NOT_FOUND, GFR_E_NOT_READY, GFR_E_CAPACITY = -4, -5, -6

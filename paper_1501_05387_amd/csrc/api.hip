@@ -461,7 +461,9 @@ gfr_status gfr_ctx_create(int32_t device, const char *tuning_json, gfr_ctx **out
         if (strncmp(p.gcnArchName, "gfx950", 6) != 0)
             fail(GFR_E_DEVICE, std::string("device is ") + p.gcnArchName + ", this library is built for gfx950");
         cc.num_cu = p.multiProcessorCount;
-        GFR_HIP(hipStreamCreateWithFlags(&cc.stream, hipStreamNonBlocking));
+        // a blocking stream: work the caller queued earlier on the device's
+        // null stream (PyTorch's default stream) finishes before ours starts
+        GFR_HIP(hipStreamCreateWithFlags(&cc.stream, hipStreamDefault));
         GFR_HIP(hipHostMalloc((void **)&cc.pinned, 4096, hipHostMallocDefault));
         GFR_HIP(hipEventCreate(&cc.ev0));
         GFR_HIP(hipEventCreate(&cc.ev1));

@@ -20,7 +20,7 @@
 //                 (coalesced), then the wave relaxes the 64 edges eight at a
 //                 time with their sixteen distance rows in flight; a group
 //                 whose 64 edges all leave one vertex loads that vertex's
-//                 row once.
+//                 row once and relaxes sixteen edges at a time.
 //   compact       near queue in vertex order with its per-vertex query masks,
 //                 or, when the near queue has run dry, the far split with
 //                 the next bucket (compact.h), plus the control.
@@ -148,18 +148,18 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
                 const uint32_t du = a.D[(size_t)u_first * 64 + lane];
                 const uint32_t q0 = (uint32_t)lane_bcast(qlo, 0), q1 = (uint32_t)lane_bcast(qhi, 0);
                 const bool act_u = (((lane < 32 ? q0 : q1) >> (lane & 31)) & 1u) != 0;
-                for (int j0 = 0; j0 < nb; j0 += BS_UNROLL) {
-                    uint32_t dv[BS_UNROLL], ww[BS_UNROLL];
-                    int32_t vv[BS_UNROLL];
+                for (int j0 = 0; j0 < nb; j0 += 16) {
+                    uint32_t dv[16], ww[16];
+                    int32_t vv[16];
 #pragma unroll
-                    for (int j = 0; j < BS_UNROLL; ++j) {
+                    for (int j = 0; j < 16; ++j) {
                         const int src = min(j0 + j, nb - 1);   // a padded edge repeats the last one
                         vv[j] = lane_bcast(vl, src);
                         ww[j] = (uint32_t)lane_bcast(wl, src);
                         dv[j] = a.D[(size_t)vv[j] * 64 + lane];
                     }
 #pragma unroll
-                    for (int j = 0; j < BS_UNROLL; ++j) relax(vv[j], ww[j], du, dv[j], act_u & (j0 + j < nb));
+                    for (int j = 0; j < 16; ++j) relax(vv[j], ww[j], du, dv[j], act_u & (j0 + j < nb));
                 }
             } else {
                 for (int j0 = 0; j0 < nb; j0 += BS_UNROLL) {

@@ -116,3 +116,14 @@ def test_tuning_file_is_checked_before_the_device(text, ok):
             L.gfr_ctx_destroy(p.value)
     else:
         assert st == gfr.GFR_E_INVALID, st
+
+
+def test_packaged_tuning_file_is_accepted():
+    """The committed MI355X tuning file parses and only holds known options
+    (checked before the device is touched)."""
+    L = gfr.lib()
+    p = ctypes.c_void_p()
+    st = L.gfr_ctx_create(0, gfr.tuned_json().encode(), ctypes.byref(p))
+    assert st in (gfr.GFR_OK, gfr.GFR_E_DEVICE), st
+    if st == gfr.GFR_OK:
+        L.gfr_ctx_destroy(p.value)

@@ -399,3 +399,61 @@ def test_host_outputs_span_several_bounce_chunks(ctx):
     assert np.array_equal(pinned.numpy(), ctx.bfs_batch(g, src).cpu().numpy())
     assert np.array_equal(pinned.numpy()[:n], oracle.bfs(row, col, src[0]))
     g.free()
+
+
+@pytest.mark.parametrize("alpha", [1, 2, 4, 8, 16, 64])
+def test_bfs_batch_every_switch_point_rmat20(ctx, alpha):
+    """MS-BFS at each push->pull switch point the autotuner tries, on a graph
+    large enough for the switch to fall between several levels."""
+    row, col = _rmat20()
+    n = row.size - 1
+    deg = np.diff(row)
+    rng = np.random.default_rng(7)
+    src = np.concatenate([[int(np.argmax(deg))], rng.choice(np.nonzero(deg > 0)[0], 63, replace=False)]).astype(np.int32)
+    g = _load(ctx, row, col)
+    ctx.set_option("msbfs.alpha", alpha)
+    ctx.set_option("batch.min_bfs", 1)
+    try:
+        _say("bfs_batch rmat20 alpha", alpha)
+        d = _host(ctx.bfs_batch(g, src)).reshape(64, n)
+        for i in (0, 1, 17, 40, 63):
+            assert np.array_equal(d[i], oracle.bfs(row, col, src[i])), (alpha, i)
+    finally:
+        ctx.set_option("msbfs.alpha", 4)
+        ctx.set_option("batch.min_bfs", 8)
+        g.free()
+
+
+_R20 = {}
+
+
+def _rmat20():
+    if not _R20:
+        _R20["g"] = graphgen.rmat(20)
+    return _R20["g"]
+
+
+def test_output_reuse_is_ordered_with_the_default_stream(ctx):
+    """A copy of an output taken on PyTorch's default stream, immediately
+    followed by another call into the same buffer, sees the first result: the
+    call's work is ordered after work queued on the default stream."""
+    import torch
+    row, col = _rmat20()
+    n = row.size - 1
+    g = _load(ctx, row, col)
+    src = graphgen.sample_sources(row, col, 64)
+    buf = torch.empty(64 * n, dtype=torch.int32, device="cuda")
+    _say("output reuse rmat20")
+    ctx.set_option("batch.min_bfs", 1)
+    try:
+        copies = []
+        for _ in range(3):
+            ctx.bfs_batch(g, src, out=buf)
+            copies.append(buf.clone())          # queued on the default stream, not waited for
+        for c in copies:
+            h = c.cpu().numpy().reshape(64, n)
+            for i in (0, 31, 63):
+                assert np.array_equal(h[i], oracle.bfs(row, col, src[i])), i
+    finally:
+        ctx.set_option("batch.min_bfs", 8)
+        g.free()
