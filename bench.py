@@ -90,45 +90,71 @@ def read_stats(ctx, keys):
     return out
 
 
-def serve_leg(ctx, g, row, col, n, nq, log):
-    """Serve a Poisson stream of 70 % BFS / 30 % SSSP queries (sources uniform
-    over the largest component) at a ladder of offered rates, batched (up to 64
-    per traversal) and one at a time, on the same GPU and code path."""
+SERVE_SCALES = (18, 19, 20, 21, 22, 23)
+SERVE_RATES = (500.0, 2000.0, 8000.0, 1e9)
+
+
+def serve_leg(ctx, resident, nq, log):
+    """The serving workload: six resident R-MAT graphs (scales 18-23, edge
+    factor 16, weights in [1,64]); a Poisson stream of queries, 70 % BFS and
+    30 % SSSP, each on a graph drawn Zipf(s = 1.2) over the scales in
+    ascending order (scale 18 the most popular) from a random source of that
+    graph's largest component; a ladder of offered rates.  Served batched
+    (continuous batching, up to 64 queries per session) and one at a time
+    (single-source solvers), on the same GPU, with every result checked
+    against the same query solved directly."""
     import torch
 
     import graphgen
     import paper_1501_05387_amd as gfr
     rng = np.random.default_rng(graphgen.SEED_ARRIVALS)
-    pool = graphgen.sample_sources(row, col, 512, seed=graphgen.SEED_ARRIVALS)
-    srcs = pool[rng.integers(0, pool.size, size=nq)]
+    zipf = np.array([1.0 / (i + 1) ** 1.2 for i in range(len(SERVE_SCALES))])
+    zipf /= zipf.sum()
+    pools = {s: graphgen.sample_sources(r, c, 256, seed=graphgen.SEED_ARRIVALS) for s, (r, c, _, _) in resident.items()}
+    gsel = rng.choice(len(SERVE_SCALES), size=nq, p=zipf)
+    scales = [SERVE_SCALES[i] for i in gsel]
+    srcs = [int(pools[s][rng.integers(0, pools[s].size)]) for s in scales]
     kinds = np.where(rng.random(nq) < 0.7, gfr.GFR_Q_BFS, gfr.GFR_Q_SSSP)
-    outs = torch.empty((nq, n), dtype=torch.int32, device="cuda:0")
+    outs = [torch.empty(resident[s][0].size - 1, dtype=torch.int32, device="cuda:0") for s in scales]
+    # reference results, each query solved directly
+    ref = {}
+    for i in range(nq):
+        key = (scales[i], int(kinds[i]), srcs[i])
+        if key not in ref:
+            g = resident[scales[i]][3]
+            ref[key] = (ctx.bfs(g, srcs[i]) if kinds[i] == gfr.GFR_Q_BFS else ctx.sssp(g, srcs[i])).clone()
     res = {}
     for mode, mb in (("batched", 64), ("one_at_a_time", 1)):
         ctx.set_option("serve.max_batch", mb)
         pts = []
-        for rate in (1000.0, 4000.0, 1e9):
+        for rate in SERVE_RATES:
             gaps = rng.exponential(1.0 / rate, size=nq)
             arrive = np.cumsum(gaps) - gaps[0]
+            for o in outs:
+                o.fill_(-7)
+            torch.cuda.synchronize()
             ctx.stat("serve.reset")
-            done = set()
+            done = {}
             t0 = time.perf_counter()
-            tickets = []
             for i in range(nq):
                 while time.perf_counter() - t0 < arrive[i]:
-                    done.update(t for t, _ in ctx.poll(256, 0))
-                tickets += ctx.submit_queries([(int(kinds[i]), g, int(srcs[i]), outs[i])])
+                    done.update(ctx.poll(256, 0))
+                ctx.submit_queries([(int(kinds[i]), resident[scales[i]][3], srcs[i], outs[i])])
             while len(done) < nq:
-                done.update(t for t, _ in ctx.poll(256, 100000))
+                done.update(ctx.poll(256, 100000))
             span = time.perf_counter() - t0
+            ok = all(st == gfr.GFR_OK for st in done.values()) and all(
+                torch.equal(outs[i], ref[(scales[i], int(kinds[i]), srcs[i])]) for i in range(nq))
             pts.append({"offered_qps": rate if rate < 1e8 else None, "qps": round(nq / span, 1),
                         "p50_ms": round(ctx.stat("serve.p50_ms"), 3), "p99_ms": round(ctx.stat("serve.p99_ms"), 3),
-                        "mean_batch": round(ctx.stat("serve.mean_batch"), 2)})
+                        "mean_batch": round(ctx.stat("serve.mean_batch"), 2),
+                        "joined_running": int(ctx.stat("serve.joined")), "results_equal": bool(ok)})
             log("serve %s rate %s: %s" % (mode, rate, pts[-1]))
         res[mode] = pts
     ctx.set_option("serve.max_batch", 64)
     res["queries_per_point"] = nq
-    res["mix"] = "70% BFS / 30% SSSP, sources uniform over the largest component, Poisson arrivals"
+    res["mix"] = ("6 R-MAT graphs s18-s23 resident; 70% BFS / 30% SSSP; graph Zipf(1.2) over ascending scales; "
+                  "sources from each graph's largest component; Poisson arrivals")
     return res
 
 
@@ -142,7 +168,7 @@ def main():
     ap.add_argument("--sources", type=int, default=64)
     ap.add_argument("--cpu-sources", type=int, default=4, help="oracle sample size (sources)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-queries", type=int, default=256, help="queries per serving point (0: skip)")
+    ap.add_argument("--serve-queries", type=int, default=512, help="queries per serving point (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="finish with one device copy of this many MiB (a known-size kernel that "
                          "calibrates the HBM byte counters of a profiler run)")
@@ -281,8 +307,20 @@ def main():
 
     serving = None
     if args.serve_queries > 0:
-        serving = serve_leg(ctx, g, row, col, n, args.serve_queries, log)
+        resident = {}
+        for sc in SERVE_SCALES:
+            if sc == args.scale and args.edge_factor == 16:
+                resident[sc] = (row, col, w, g)
+                continue
+            r2, c2 = graphgen.rmat(sc, 16)
+            w2 = graphgen.weights(r2, c2, 64)
+            resident[sc] = (r2, c2, w2, ctx.graph_load_csr(r2, c2, w2))
+            log("serving graph scale %d loaded (n=%d m=%d)" % (sc, r2.size - 1, c2.size))
+        serving = serve_leg(ctx, resident, args.serve_queries, log)
         log("serving:", json.dumps(serving))
+        for sc, (_, _, _, g2) in resident.items():
+            if g2 is not g:
+                g2.free()
 
     line = {
         "metric": "BFS/SSSP GTEPS on R-MAT s22 ef16 (HBM GB/s); batched queries/s + p99 latency",

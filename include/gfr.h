@@ -107,8 +107,11 @@ gfr_status gfr_get_option(gfr_ctx *ctx, const char *key, double *value);
  * Statistics of the last solve on this context: "levels", "push_levels",
  * "pull_levels", "edges_inspected", "iterations", "relaxations", "kernel_ms".
  * Serving statistics since the last "serve.reset": "serve.completed",
- * "serve.batches", "serve.mean_batch", "serve.p50_ms", "serve.p99_ms"
- * (submission to completion), "serve.queued".
+ * "serve.batches" (session steps: one level or relaxation round of one
+ * session), "serve.mean_batch" (queries in flight per step), "serve.joined"
+ * (queries admitted into a session while other queries of it were running),
+ * "serve.p50_ms", "serve.p99_ms" (submission to completion), "serve.queued";
+ * current: "serve.sessions", "serve.session_bytes".
  */
 gfr_status gfr_get_stat(gfr_ctx *ctx, const char *key, double *value);
 
@@ -139,7 +142,8 @@ gfr_status gfr_graph_load_csr(gfr_ctx *ctx, int32_t n, int64_t m, const int32_t 
                               const int32_t *col_idx, const uint32_t *weights, uint32_t flags,
                               gfr_graph *out);
 
-/* Release a resident graph.  GFR_E_NOT_FOUND for an unknown handle. */
+/* Release a resident graph.  GFR_E_NOT_FOUND for an unknown handle;
+ * GFR_E_NOT_READY while served queries on it are queued or running. */
 gfr_status gfr_graph_free(gfr_ctx *ctx, gfr_graph g);
 
 /* Vertex count, entry count and device bytes held by the graph (any may be NULL). */
@@ -227,9 +231,13 @@ typedef struct gfr_query {
 
 /*
  * Queue `count` queries for asynchronous execution; tickets_out[i] receives
- * the ticket of queries[i].  Queries are admitted when their device footprint
- * fits the context's budget ("serve.budget_bytes") and are batched with other
- * admitted queries on the same graph as they arrive (continuous batching).
+ * the ticket of queries[i].  Queries on one graph and of one kind share a
+ * 64-lane batched traversal (a session); a query joins a running session at
+ * its next level boundary as soon as a lane is free and leaves it when its own
+ * traversal ends (continuous batching), so a query may start while others
+ * are half done.  A session is created when its device footprint fits the
+ * context's budget ("serve.budget_bytes") beside the running ones; sessions
+ * of different graphs or kinds run concurrently on their own streams.
  * A query that could never fit the budget -> GFR_E_CAPACITY for the whole
  * call, nothing queued.  A query with a bad source or graph is queued and
  * completes with that error status.

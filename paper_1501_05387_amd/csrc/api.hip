@@ -81,7 +81,7 @@ static void parallel_memcpy(char *dst, const char *src, size_t bytes)
     for (auto &x : th) x.join();
 }
 
-void copy_to_host(Ctx &c, void *dst, const void *src, size_t bytes, hipStream_t s)
+void copy_to_host(Bounce &b, void *dst, const void *src, size_t bytes, hipStream_t s)
 {
     if (bytes == 0) return;
     if (is_pinned_host(dst)) {
@@ -91,21 +91,21 @@ void copy_to_host(Ctx &c, void *dst, const void *src, size_t bytes, hipStream_t 
     }
     constexpr size_t kChunk = 32u << 20;
     for (int i = 0; i < 2; ++i) {
-        if (!c.bounce[i]) GFR_HIP(hipHostMalloc((void **)&c.bounce[i], kChunk, hipHostMallocDefault));
-        if (!c.bounce_ev[i]) GFR_HIP(hipEventCreateWithFlags(&c.bounce_ev[i], hipEventDisableTiming));
+        if (!b.buf[i]) GFR_HIP(hipHostMalloc((void **)&b.buf[i], kChunk, hipHostMallocDefault));
+        if (!b.ev[i]) GFR_HIP(hipEventCreateWithFlags(&b.ev[i], hipEventDisableTiming));
     }
     const size_t nch = (bytes + kChunk - 1) / kChunk;
     auto len = [&](size_t j) { return std::min(kChunk, bytes - j * kChunk); };
     auto enqueue = [&](size_t j) {
-        GFR_HIP(hipMemcpyAsync(c.bounce[j & 1], (const char *)src + j * kChunk, len(j), hipMemcpyDeviceToHost, s));
-        GFR_HIP(hipEventRecord(c.bounce_ev[j & 1], s));
+        GFR_HIP(hipMemcpyAsync(b.buf[j & 1], (const char *)src + j * kChunk, len(j), hipMemcpyDeviceToHost, s));
+        GFR_HIP(hipEventRecord(b.ev[j & 1], s));
     };
     enqueue(0);
     for (size_t j = 0; j < nch; ++j) {
         // buffer (j+1)&1 was drained by the host copy of chunk j-1 just below
         if (j + 1 < nch) enqueue(j + 1);
-        GFR_HIP(hipEventSynchronize(c.bounce_ev[j & 1]));
-        parallel_memcpy((char *)dst + j * kChunk, c.bounce[j & 1], len(j));
+        GFR_HIP(hipEventSynchronize(b.ev[j & 1]));
+        parallel_memcpy((char *)dst + j * kChunk, b.buf[j & 1], len(j));
     }
 }
 
@@ -213,7 +213,7 @@ struct OutBuf {
     }
     void finish(Ctx &c, hipStream_t s)
     {
-        if (staged) copy_to_host(c, user, dev, bytes, s);
+        if (staged) copy_to_host(c.bounce, user, dev, bytes, s);
         GFR_HIP(hipStreamSynchronize(s));
     }
 };
@@ -418,6 +418,15 @@ static void parse_tuning(const char *js, Tuning &t)
     if (i != s.size()) fail(GFR_E_INVALID, "tuning_json: trailing characters");
 }
 
+Options effective_options(Ctx &c, const Graph &g)
+{
+    std::lock_guard<std::mutex> lo(c.opt_mu);
+    Options o = c.base_opt;
+    for (const auto &kv : c.tuning.cls[g.cls])
+        if (!c.user_keys.count(kv.first)) option_set(o, kv.first, kv.second);
+    return o;
+}
+
 OptScope::OptScope(Ctx &c, const Graph &g) : c(c), saved(c.opt)
 {
     for (const auto &kv : c.tuning.cls[g.cls])
@@ -471,7 +480,9 @@ gfr_status gfr_ctx_create(int32_t device, const char *tuning_json, gfr_ctx **out
         GFR_HIP(hipMemsetAsync(cc.zero_word.p, 0, 256, cc.stream));
         GFR_HIP(hipStreamSynchronize(cc.stream));
         for (const auto &kv : tuning.global) option_set(cc.opt, kv.first, kv.second);
+        std::lock_guard<std::mutex> lo(cc.opt_mu);
         cc.tuning = tuning;
+        cc.base_opt = cc.opt;
     });
     if (st != GFR_OK) {
         gfr_ctx_destroy((gfr_ctx *)c);
@@ -492,10 +503,7 @@ gfr_status gfr_ctx_destroy(gfr_ctx *ctx)
     c->stage.release();
     c->zero_word.release();
     if (c->pinned) (void)hipHostFree(c->pinned);
-    for (int i = 0; i < 2; ++i) {
-        if (c->bounce[i]) (void)hipHostFree(c->bounce[i]);
-        if (c->bounce_ev[i]) (void)hipEventDestroy(c->bounce_ev[i]);
-    }
+
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -514,6 +522,8 @@ gfr_status gfr_set_option(gfr_ctx *ctx, const char *key, double value)
     return guard(ctx, [&](Ctx &c) {
         if (!key) fail(GFR_E_INVALID, "null key");
         option_set(c.opt, key, value);
+        std::lock_guard<std::mutex> lo(c.opt_mu);
+        option_set(c.base_opt, key, value);
         c.user_keys.insert(key);
     });
 }
@@ -599,8 +609,8 @@ gfr_status gfr_graph_free(gfr_ctx *ctx, gfr_graph g)
     return guard(ctx, [&](Ctx &c) {
         get_graph(c, g);
         GFR_HIP(hipStreamSynchronize(c.stream));
-        std::lock_guard<std::mutex> lr(c.reg_mu);
-        c.graphs.erase(g);
+        if (!serve_release_graph(c, g))
+            fail(GFR_E_NOT_READY, "graph_free: queries on this graph are queued or running");
     });
 }
 

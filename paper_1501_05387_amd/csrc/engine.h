@@ -117,7 +117,7 @@ struct Options {
     double sssp_delta = 0.0;    // 0 -> sssp_delta_factor x mean edge weight
     double sssp_delta_factor = 2.0;
     int advance_chunk = 1024;
-    double serve_budget = 8.0e9;
+    double serve_budget = 32.0e9;
     int profile_kernels = 0;
     double msbfs_alpha = 4.0;   // batched BFS: pull when frontier edges > m / alpha
     double batch_delta = 0.0;   // batched SSSP bucket width; 0 -> batch_delta_factor
@@ -141,6 +141,28 @@ struct Stats {
 };
 
 struct Server;
+
+// Two pinned chunks for copies into pageable host memory (see copy_to_host).
+struct Bounce {
+    char *buf[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    Bounce() = default;
+    Bounce(const Bounce &) = delete;
+    Bounce &operator=(const Bounce &) = delete;
+    ~Bounce()
+    {
+        for (int i = 0; i < 2; ++i) {
+            if (buf[i]) (void)hipHostFree(buf[i]);
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+        }
+    }
+};
+
+// Copy `bytes` of device memory to host memory `dst` on stream s and wait for
+// it.  Pinned destinations take one DMA; pageable ones go through the two
+// pinned chunks of `b`, the DMA of one chunk overlapping the threaded host
+// copy of the previous one.
+void copy_to_host(Bounce &b, void *dst, const void *src, size_t bytes, hipStream_t s);
 
 // Optional per-launch timing of named kernels with HIP events on the launch
 // stream ("profile.kernels" option).  Results land in the context statistics
@@ -214,16 +236,16 @@ struct Ctx {
     Server *server = nullptr;     // owned; destroyed by serve_shutdown
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     KernelTimer ktimer;
-    // bounce buffers for results written to pageable host memory
-    char *bounce[2] = {nullptr, nullptr};
-    hipEvent_t bounce_ev[2] = {nullptr, nullptr};
+    Bounce bounce;                // for results written to pageable host memory
+    // context-wide options as set (OptScope only changes `opt`), for the
+    // serving thread, which holds opt_mu instead of mu to read them
+    std::mutex opt_mu;
+    Options base_opt;
 };
 
-// Copy `bytes` of device memory to host memory `dst` on stream s and wait for
-// it.  Pinned destinations take one DMA; pageable ones go through two pinned
-// bounce buffers, the DMA of one chunk overlapping the threaded host copy of
-// the previous one.
-void copy_to_host(Ctx &c, void *dst, const void *src, size_t bytes, hipStream_t s);
+// Options in effect for graph g (class values of the tuning file over the
+// context-wide ones, except those set explicitly), read under c.opt_mu.
+Options effective_options(Ctx &c, const Graph &g);
 
 // While alive, c.opt holds the options for graph g: the tuning file's
 // values for g's class over the context-wide ones, except for options the
@@ -257,7 +279,40 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
 constexpr uint32_t GATHER_CH = 1024;
 
 // Stops the serving runtime of a context (no-op if none).
+// A traversal with 64 lanes (one query each) that queries join and leave
+// at level boundaries: the continuous-batching unit of the serving runtime.
+// All work is queued on the session's own stream; nothing blocks except
+// copy_to_host.  Lane results live in rows of a [64][n] stage.
+struct LaneSession {
+    virtual ~LaneSession() {}
+    // (re)start lanes: lanes[i] begins a query from sources[i] at the next step
+    virtual void admit(const int32_t *lanes, const int32_t *sources, int32_t count) = 0;
+    // lanes that left (their results were taken); they stop taking part
+    virtual void release(unsigned long long lanes) = 0;
+    // one level / relaxation round, then the status read-back; `done` records its end
+    virtual void step() = 0;
+    // after `done`: lanes that still have work, and whether the device flagged an error
+    virtual unsigned long long active() const = 0;
+    virtual gfr_status failed(std::string &msg) const = 0;
+    // make the stage rows of `lanes` hold their results (queued)
+    virtual void extract(unsigned long long lanes) = 0;
+    const void *row(int lane) const { return (const char *)stage + (size_t)lane * 4 * n; }
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    uint64_t bytes = 0;
+    int32_t n = 0;
+    void *stage = nullptr;
+};
+std::unique_ptr<LaneSession> make_bfs_session(Ctx &c, Graph &g, const Options &o);
+std::unique_ptr<LaneSession> make_sssp_session(Ctx &c, Graph &g, const Options &o);
+// device bytes of one session (state + stage) for a graph of n vertices and m edges
+uint64_t bfs_session_bytes(int64_t n, int64_t m, int num_cu);
+uint64_t sssp_session_bytes(int64_t n, int64_t m, int num_cu);
+
 void serve_shutdown(Ctx &c);
+// Remove graph gh from the registry unless served queries on it are queued or
+// running (then false); idle serving sessions on it are dropped first.
+bool serve_release_graph(Ctx &c, int64_t gh);
 // Serving statistics ("serve.*" keys); false if the key is not a serving key.
 bool serve_stat(Ctx &c, const std::string &key, double *value);
 

@@ -42,6 +42,8 @@ struct MsCtl {
     uint32_t pad;
     unsigned long long m;
     unsigned long long push_edges, pull_levels, push_levels;
+    unsigned long long allq;     // sources (lanes) in use
+    unsigned long long active;   // lanes whose frontier is non-empty after the last level
 };
 
 struct MsArgs {
@@ -54,6 +56,9 @@ struct MsArgs {
     int32_t *depth;    // [k][n]
     int32_t k;
     unsigned long long allq;
+    const int32_t *base;            // [64] depth written = level + 1 - base[lane]
+    unsigned long long *actp;       // [gridDim of finalize] per-group OR of the new frontier masks
+    uint32_t nactp;
     FrontierQ q;
     FrontierQ full;            // every vertex with edges (pull sweeps)
     uint32_t full_nf, full_mf;
@@ -125,6 +130,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void msbfs_level(MsArgs a)
         int32_t *s_v = s_row + (CH + 1);
         const FrontierQ q = a.full;
         const uint32_t nf = a.full_nf, mf = a.full_mf;
+        const unsigned long long allq = ctl->allq;
         const uint32_t nchunks = (mf + CH - 1) / CH;
         for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
             const uint32_t e0 = c * CH;
@@ -138,7 +144,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void msbfs_level(MsArgs a)
                 s_off[i] = q.off[s + i];
                 s_row[i] = q.row[s + i];
                 s_v[i] = v;
-                s_need[i] = a.allq & ~a.vis[v];
+                s_need[i] = allq & ~a.vis[v];
                 s_acc[i] = 0ull;
             }
             __syncthreads();
@@ -166,6 +172,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void msbfs_finalize(MsArgs a)
     if (ctl->dir == MS_DONE) return;
     const int32_t L = ctl->level;
     const uint32_t waves = gridDim.x * GFR_WAVES;
+    unsigned long long act = 0;   // lanes with a non-empty new frontier (wave-uniform)
     for (uint32_t grp = blockIdx.x * GFR_WAVES + threadIdx.x / 64; grp * 64u < (uint32_t)a.n; grp += waves) {
         const int32_t v = (int32_t)(grp * 64u) + lane_id();
         unsigned long long nw = 0;
@@ -187,11 +194,20 @@ __global__ __launch_bounds__(GFR_BLOCK) void msbfs_finalize(MsArgs a)
             const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(any >> 32), d, 64);
             any |= ((unsigned long long)hi << 32) | lo;
         }
+        act |= any;
         while (any) {
             const int qq = __ffsll(any) - 1;
             any &= any - 1;
-            if ((nw >> qq) & 1ull) a.depth[(size_t)qq * a.n + v] = L + 1;
+            if ((nw >> qq) & 1ull) a.depth[(size_t)qq * a.n + v] = L + 1 - a.base[qq];
         }
+    }
+    __shared__ unsigned long long s_act[GFR_WAVES];
+    if (lane_id() == 0) s_act[threadIdx.x / 64] = act;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < GFR_WAVES; ++i) t |= s_act[i];
+        a.actp[blockIdx.x] = t;
     }
 }
 
@@ -207,8 +223,22 @@ struct MsMarks {
     __device__ void partial(uint32_t) {}
     __device__ void control(uint32_t nf2, uint32_t mf2) const
     {
+        // lanes still running: OR of the finalize groups' partials
+        unsigned long long act = 0;
+        for (uint32_t i = threadIdx.x; i < a.nactp; i += GFR_BLOCK) act |= a.actp[i];
+        __shared__ unsigned long long s_or[GFR_WAVES];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)act, d, 64);
+            const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(act >> 32), d, 64);
+            act |= ((unsigned long long)hi << 32) | lo;
+        }
+        if (lane_id() == 0) s_or[threadIdx.x / 64] = act;
+        __syncthreads();
         if (threadIdx.x != 0) return;
+        for (int i = 0; i < GFR_WAVES; ++i) act |= s_or[i];
         MsCtl *ctl = a.ctl;
+        ctl->active = act;
         if (ctl->level >= 0) {
             if (ctl->dir == MS_PUSH) {
                 ctl->push_levels += 1;
@@ -241,6 +271,8 @@ __global__ void msbfs_init(MsArgs a, const int32_t *src, float alpha)
         ctl->alpha = alpha;
         ctl->m = (unsigned long long)a.R[a.n];
         ctl->push_edges = ctl->pull_levels = ctl->push_levels = 0ull;
+        ctl->allq = a.allq;
+        ctl->active = 0ull;
     }
 }
 
@@ -257,7 +289,7 @@ void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t 
     const int G = grid_blocks(c, 5);   // the level kernel (28.7 KB of LDS) fits five work-groups per CU
     const CompactGeom cg = compact_geom(nwords, c.num_cu);
     c.arena.reserve(3 * al256(8ull * n) + al256(32ull * nwords) + 3 * al256(4ull * n) + al256(4 * nparts) +
-                    al256(16ull * cg.blocks) + al256(sizeof(MsCtl)) + al256(4 * 64));
+                    al256(16ull * cg.blocks) + al256(sizeof(MsCtl)) + 2 * al256(4 * 64) + al256(8ull * G));
     MsArgs a;
     a.R = g.R.as<int32_t>();
     a.C = g.C.as<int32_t>();
@@ -277,6 +309,11 @@ void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t 
     unsigned long long *status = c.arena.take<unsigned long long>(2ull * cg.blocks);
     a.ctl = c.arena.take<MsCtl>(1);
     int32_t *dsrc = c.arena.take<int32_t>(64);
+    int32_t *base = c.arena.take<int32_t>(64);   // every source starts at level 0
+    a.base = base;
+    a.actp = c.arena.take<unsigned long long>(G);
+    a.nactp = (uint32_t)G;
+    fill_u32(base, 0u, 64, s);
     double levels = 0, pull_levels = 0, push_edges = 0;
     for (int32_t g0 = 0; g0 < k; g0 += 64) {
         const int32_t kk = std::min<int32_t>(64, k - g0);
@@ -318,6 +355,204 @@ void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t 
     c.stats.v["pull_levels"] += pull_levels;
     c.stats.v["push_edges"] += push_edges;
     c.stats.v["solves"] += k;
+}
+
+// ---------------------------------------------------------------- sessions
+// Lanes of a session join at a level boundary: their visited bits and depth
+// row are cleared, the source enters the next frontier, and base[lane] makes
+// depths count from the level it joined.  A lane whose new frontier is empty
+// is finished; its depth row is final.
+
+__global__ __launch_bounds__(GFR_BLOCK) void ms_clear_lanes(MsArgs a, unsigned long long lanes)
+{
+    const size_t n = (size_t)a.n;
+    for (size_t v = (size_t)blockIdx.x * GFR_BLOCK + threadIdx.x; v < n; v += (size_t)gridDim.x * GFR_BLOCK) {
+        a.vis[v] &= ~lanes;
+        a.fr[v] &= ~lanes;
+        a.nx[v] &= ~lanes;
+        unsigned long long m = lanes;
+        while (m) {
+            const int q = __ffsll(m) - 1;
+            m &= m - 1;
+            a.depth[(size_t)q * n + v] = -1;
+        }
+    }
+}
+
+__global__ void ms_admit(MsArgs a, const int32_t *pairs, int32_t count, unsigned long long release)
+{
+    if (threadIdx.x != 0) return;
+    MsCtl *ctl = a.ctl;
+    unsigned long long allq = ctl->allq & ~release;
+    for (int32_t i = 0; i < count; ++i) {
+        const int32_t q = pairs[2 * i], src = pairs[2 * i + 1];
+        a.nx[src] |= 1ull << q;
+        ((int32_t *)a.base)[q] = ctl->level + 1;
+        allq |= 1ull << q;
+    }
+    ctl->allq = allq;
+    if (count && ctl->dir == MS_DONE) ctl->dir = MS_PUSH;
+}
+
+__global__ void ms_session_init(MsArgs a, float alpha)
+{
+    if (threadIdx.x != 0) return;
+    MsCtl *ctl = a.ctl;
+    ctl->dir = MS_DONE;
+    ctl->level = -1;
+    ctl->nf = ctl->mf = 0;
+    ctl->parity = 0;
+    ctl->err = 0;
+    ctl->alpha = alpha;
+    ctl->m = (unsigned long long)a.R[a.n];
+    ctl->push_edges = ctl->pull_levels = ctl->push_levels = 0ull;
+    ctl->allq = 0ull;
+    ctl->active = 0ull;
+}
+
+namespace {
+struct MsLayout {
+    size_t n, nwords, nparts, G, blocks;
+    size_t total() const
+    {
+        return 3 * al256(8 * n) + al256(32 * nwords) + 3 * al256(4 * n) + al256(4 * nparts) +
+               al256(16 * blocks) + al256(sizeof(MsCtl)) + al256(4 * 64) + al256(8 * G) + al256(4 * 128) +
+               al256(4 * 64 * n);
+    }
+};
+MsLayout ms_layout(int64_t n, int64_t m, int num_cu)
+{
+    MsLayout L;
+    L.n = (size_t)n;
+    L.nwords = (size_t)((n + 63) / 64) * 2;
+    L.nparts = (size_t)(m / 1024) + 2;
+    L.G = (size_t)num_cu * 5;
+    L.blocks = compact_geom((uint32_t)L.nwords, num_cu).blocks;
+    return L;
+}
+}  // namespace
+
+uint64_t bfs_session_bytes(int64_t n, int64_t m, int num_cu) { return ms_layout(n, m, num_cu).total(); }
+
+struct MsSession final : LaneSession {
+    Ctx &c;
+    Graph &g;
+    DevMem mem;
+    MsArgs a{};
+    CompactGeom cg{};
+    int G = 0;
+    uint32_t nwords = 0;
+    unsigned long long *status = nullptr;
+    int32_t *pairs = nullptr, *pin_pairs = nullptr;
+    MsCtl *pin = nullptr;
+    unsigned long long pending_release = 0;
+
+    MsSession(Ctx &cc, Graph &gg, const Options &o) : c(cc), g(gg)
+    {
+        n = g.n;
+        const MsLayout L = ms_layout(g.n, g.m, c.num_cu);
+        nwords = (uint32_t)L.nwords;
+        G = (int)L.G;
+        cg = compact_geom(nwords, c.num_cu);
+        bytes = L.total();
+        GFR_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        GFR_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+        GFR_HIP(hipHostMalloc((void **)&pin, sizeof(MsCtl), hipHostMallocDefault));
+        GFR_HIP(hipHostMalloc((void **)&pin_pairs, 4 * 128, hipHostMallocDefault));
+        mem.alloc(bytes);
+        char *p = (char *)mem.p;
+        auto take = [&](size_t b) {
+            char *r = p;
+            p += al256(b);
+            return (void *)r;
+        };
+        a.R = g.R.as<int32_t>();
+        a.C = g.C.as<int32_t>();
+        a.n = g.n;
+        a.nwords = nwords;
+        a.full = g.full;
+        a.full_nf = (uint32_t)g.full_nf;
+        a.full_mf = (uint32_t)g.m;
+        a.vis = (unsigned long long *)take(8 * L.n);
+        a.fr = (unsigned long long *)take(8 * L.n);
+        a.nx = (unsigned long long *)take(8 * L.n);
+        a.mark = (uint8_t *)take(32 * L.nwords);
+        a.q.v = (int32_t *)take(4 * L.n);
+        a.q.off = (uint32_t *)take(4 * L.n);
+        a.q.row = (int32_t *)take(4 * L.n);
+        a.q.part = (int32_t *)take(4 * L.nparts);
+        status = (unsigned long long *)take(16 * L.blocks);
+        a.ctl = (MsCtl *)take(sizeof(MsCtl));
+        a.base = (const int32_t *)take(4 * 64);
+        a.actp = (unsigned long long *)take(8 * L.G);
+        a.nactp = (uint32_t)G;
+        pairs = (int32_t *)take(4 * 128);
+        a.depth = (int32_t *)take(4 * 64 * L.n);
+        a.k = 64;
+        a.allq = 0;
+        stage = a.depth;
+        fill_u32(mem.p, 0u, (3 * al256(8 * L.n) + al256(32 * L.nwords)) / 4, stream);   // vis, fr, nx, marks
+        fill_u32(status, 0u, 4 * L.blocks, stream);
+        fill_u32((void *)a.base, 0u, 64, stream);
+        hipLaunchKernelGGL(ms_session_init, dim3(1), dim3(64), 0, stream, a, (float)o.msbfs_alpha);
+        GFR_LAUNCH_CHECK();
+    }
+    ~MsSession() override
+    {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (pin) (void)hipHostFree(pin);
+        if (pin_pairs) (void)hipHostFree(pin_pairs);
+        if (done) (void)hipEventDestroy(done);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+    void admit(const int32_t *lanes, const int32_t *sources, int32_t count) override
+    {
+        if (count <= 0) return;
+        // the pinned staging of the previous admission must have been consumed
+        GFR_HIP(hipStreamSynchronize(stream));
+        unsigned long long mask = 0;
+        for (int32_t i = 0; i < count; ++i) {
+            pin_pairs[2 * i] = lanes[i];
+            pin_pairs[2 * i + 1] = sources[i];
+            mask |= 1ull << lanes[i];
+        }
+        GFR_HIP(hipMemcpyAsync(pairs, pin_pairs, 8ull * count, hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL(ms_clear_lanes, dim3(G), dim3(GFR_BLOCK), 0, stream, a, mask);
+        hipLaunchKernelGGL(ms_admit, dim3(1), dim3(64), 0, stream, a, pairs, count, pending_release);
+        GFR_LAUNCH_CHECK();
+        pending_release = 0;
+    }
+    void release(unsigned long long lanes) override { pending_release |= lanes; }
+    void step() override
+    {
+        if (pending_release) {
+            hipLaunchKernelGGL(ms_admit, dim3(1), dim3(64), 0, stream, a, pairs, 0, pending_release);
+            pending_release = 0;
+        }
+        hipLaunchKernelGGL(msbfs_level<GATHER_CH>, dim3(G), dim3(GFR_BLOCK), 0, stream, a);
+        hipLaunchKernelGGL(msbfs_finalize, dim3(G), dim3(GFR_BLOCK), 0, stream, a);
+        hipLaunchKernelGGL(compact_kernel<MsMarks>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, stream, a.R, a.n, nwords,
+                           cg.wpt, MsMarks{a}, a.q, 1024u, status, &a.ctl->parity, &a.ctl->err);
+        GFR_LAUNCH_CHECK();
+        GFR_HIP(hipMemcpyAsync(pin, a.ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, stream));
+        GFR_HIP(hipEventRecord(done, stream));
+    }
+    // once the level loop has stopped, every lane's frontier is empty
+    unsigned long long active() const override { return pin->dir == MS_DONE ? 0ull : pin->active; }
+    gfr_status failed(std::string &msg) const override
+    {
+        if (pin->err) {
+            msg = "bfs query: frontier compaction look-back timed out";
+            return GFR_E_DEVICE;
+        }
+        return GFR_OK;
+    }
+    void extract(unsigned long long) override {}   // depth rows are written in place
+};
+
+std::unique_ptr<LaneSession> make_bfs_session(Ctx &c, Graph &g, const Options &o)
+{
+    return std::unique_ptr<LaneSession>(new MsSession(c, g, o));
 }
 
 }  // namespace gfr

@@ -43,6 +43,7 @@ struct BsCtl {
     uint32_t split_kept, split_min;
     uint32_t overflow, parity, err, splits;
     unsigned long long relaxed, improvements, pair_entries;
+    unsigned long long active;   // queries with a (vertex, query) pair in the next near queue
 };
 
 struct BsArgs {
@@ -57,6 +58,7 @@ struct BsArgs {
     uint8_t *nany, *fany;        // [n] (padded)
     FrontierQ q;
     uint32_t *part;              // per work-group [improvements, far marks written]
+    unsigned long long *actp;    // per compaction group: OR of the query masks it queued
     BsCtl *ctl;
 };
 
@@ -218,7 +220,9 @@ __device__ __forceinline__ unsigned long long row_mask(uint8_t *p, bool clear)
 struct BsMarks {
     BsArgs a;
     uint32_t nparts;
+    uint32_t nactp;   // compaction groups
     uint32_t kept = 0, kmin = 0xFFFFFFFFu;
+    unsigned long long actq = 0;
 
     __device__ bool skip() const { return a.ctl->mode == BS_DONE; }
 
@@ -234,7 +238,9 @@ struct BsMarks {
                 const int bi = __ffs(bits) - 1;
                 bits &= bits - 1;
                 const uint32_t v = w * 32u + bi;
-                a.qm[v] = row_mask(a.nmark + (size_t)v * 64, true);
+                const unsigned long long qv = row_mask(a.nmark + (size_t)v * 64, true);
+                a.qm[v] = qv;
+                actq |= qv;
             }
             return m;
         }
@@ -271,6 +277,25 @@ struct BsMarks {
 
     __device__ void partial(uint32_t)
     {
+        if (a.ctl->mode == BS_RELAX) {
+            // OR of the queued query masks of this group
+            __shared__ unsigned long long s_q[GFR_WAVES];
+            unsigned long long x = actq;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, d, 64);
+                const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), d, 64);
+                x |= ((unsigned long long)hi << 32) | lo;
+            }
+            if (lane_id() == 0) s_q[threadIdx.x / 64] = x;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                for (int i = 0; i < GFR_WAVES; ++i) x |= s_q[i];
+                a.actp[blockIdx.x] = x;
+                __threadfence();
+            }
+            return;
+        }
         if (a.ctl->mode != BS_SPLIT) return;
         __shared__ uint32_t s_k[GFR_WAVES], s_m[GFR_WAVES];
         const uint32_t k = wave_sum_u32(kept), mn = wave_min_u32(kmin);
@@ -317,7 +342,22 @@ struct BsMarks {
                 far += s_f[i];
             }
         }
+        unsigned long long act = 0;
+        if (mode == BS_RELAX) {
+            for (uint32_t i = threadIdx.x; i < nactp; i += GFR_BLOCK) act |= a.actp[i];
+            __shared__ unsigned long long s_a[GFR_WAVES];
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)act, d, 64);
+                const uint32_t hi2 = (uint32_t)__shfl_xor((int)(uint32_t)(act >> 32), d, 64);
+                act |= ((unsigned long long)hi2 << 32) | lo;
+            }
+            if (lane_id() == 0) s_a[threadIdx.x / 64] = act;
+            __syncthreads();
+            for (int i = 0; i < GFR_WAVES; ++i) act |= s_a[i];
+        }
         if (threadIdx.x != 0) return;
+        if (mode == BS_RELAX) ctl->active = act;
         const uint32_t D = ctl->delta, hi = ctl->hi;
         uint32_t split_min = 0xFFFFFFFFu;
         if (mode == BS_RELAX) {
@@ -380,8 +420,10 @@ __global__ void bsssp_init(BsArgs a, const int32_t *src, int32_t k, uint32_t del
     }
 }
 
-// out[q][v] = D[v][q] for q < k: 64 vertices x 64 queries per tile through LDS
-__global__ __launch_bounds__(GFR_BLOCK) void bsssp_transpose(const uint32_t *D, int32_t n, int32_t k, uint32_t *out)
+// out[q][v] = D[v][q] for the queries q in `lanes`: 64 vertices x 64 queries
+// per tile through LDS
+__global__ __launch_bounds__(GFR_BLOCK) void bsssp_transpose(const uint32_t *D, int32_t n, unsigned long long lanes,
+                                                             uint32_t *out)
 {
     __shared__ uint32_t tile[64][65];
     const int32_t ntiles = (n + 63) / 64;
@@ -395,7 +437,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_transpose(const uint32_t *D, 
         __syncthreads();
         for (int i = threadIdx.x; i < 64 * 64; i += GFR_BLOCK) {
             const int q = i / 64, r = i % 64;
-            if (q < k && v0 + r < n) out[(size_t)q * n + v0 + r] = tile[r][q];
+            if (((lanes >> q) & 1ull) && v0 + r < n) out[(size_t)q * n + v0 + r] = tile[r][q];
         }
     }
 }
@@ -422,7 +464,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     else if (c.opt.batch_delta_factor > 0) delta = sssp_auto_delta(g, c.opt.batch_delta_factor);
     c.arena.reserve(al256(256ull * n) + al256(8ull * n) + 2 * al256(64ull * n) + 2 * al256(32ull * nwords) +
                     3 * al256(4ull * n) + al256(4 * nparts) + al256(8ull * G) + al256(16ull * cg.blocks) +
-                    al256(sizeof(BsCtl)) + al256(4 * 64));
+                    al256(sizeof(BsCtl)) + al256(4 * 64) + al256(8ull * cg.blocks));
     BsArgs a;
     a.R = g.R.as<int32_t>();
     a.C = g.C.as<int32_t>();
@@ -443,6 +485,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     unsigned long long *status = c.arena.take<unsigned long long>(2ull * cg.blocks);
     a.ctl = c.arena.take<BsCtl>(1);
     int32_t *dsrc = c.arena.take<int32_t>(64);
+    a.actp = c.arena.take<unsigned long long>(cg.blocks);
     double iters = 0, relaxed = 0, imps = 0;
     for (int32_t g0 = 0; g0 < k; g0 += 64) {
         const int32_t kk = std::min<int32_t>(64, k - g0);
@@ -455,7 +498,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
         fill_u32(status, 0u, 4ull * cg.blocks, s);
         GFR_HIP(hipMemcpyAsync(dsrc, sources + g0, 4ull * kk, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(bsssp_init, dim3(1), dim3(64), 0, s, a, dsrc, kk, delta);
-        BsMarks marks{a, (uint32_t)G};
+        BsMarks marks{a, (uint32_t)G, cg.blocks};
         auto compact = [&]() {
             c.ktimer.run("bsssp_compact", s, [&]() {
                 hipLaunchKernelGGL(compact_kernel<BsMarks>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R, n, nwords,
@@ -477,7 +520,8 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
         memcpy(&h, c.pinned, sizeof(BsCtl));
         if (h.err) fail(GFR_E_DEVICE, "sssp_batch: frontier compaction look-back timed out");
         if (h.overflow) fail(GFR_E_INVALID, "sssp_batch: a path weight does not fit below 0xFFFFFFFF");
-        hipLaunchKernelGGL(bsssp_transpose, dim3(G), dim3(GFR_BLOCK), 0, s, a.D, n, kk, dist + (size_t)g0 * n);
+        hipLaunchKernelGGL(bsssp_transpose, dim3(G), dim3(GFR_BLOCK), 0, s, a.D, n,
+                           kk == 64 ? ~0ull : ((1ull << kk) - 1ull), dist + (size_t)g0 * n);
         GFR_LAUNCH_CHECK();
         iters += h.iter;
         relaxed += (double)h.relaxed;
@@ -487,6 +531,201 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     c.stats.v["relaxations"] += relaxed;   // edge visits, each serving up to 64 queries
     c.stats.v["improvements"] += imps;
     c.stats.v["solves"] += k;
+}
+
+// ---------------------------------------------------------------- sessions
+// Lanes of a session join between relaxation rounds: their distance column is
+// reset, the source gets distance 0 and a mark, and the next compaction puts
+// it into the near queue.  A session uses one bucket (frontier order), so a
+// lane with no queued (vertex, lane) pair is finished and its column final.
+
+__global__ __launch_bounds__(GFR_BLOCK) void bs_clear_lanes(uint32_t *D, int32_t n, unsigned long long lanes)
+{
+    const int lane = lane_id();
+    const bool mine = (lanes >> lane) & 1ull;
+    const uint32_t waves = gridDim.x * GFR_WAVES;
+    for (uint32_t v = blockIdx.x * GFR_WAVES + threadIdx.x / 64; v < (uint32_t)n; v += waves)
+        if (mine) D[(size_t)v * 64 + lane] = 0xFFFFFFFFu;
+}
+
+__global__ void bs_admit(BsArgs a, const int32_t *pairs, int32_t count)
+{
+    if (threadIdx.x != 0) return;
+    for (int32_t i = 0; i < count; ++i) {
+        const int32_t q = pairs[2 * i], src = pairs[2 * i + 1];
+        a.D[(size_t)src * 64 + q] = 0u;
+        a.nmark[(size_t)src * 64 + q] = 1;
+        a.nany[src] = 1;
+    }
+    BsCtl *ctl = a.ctl;
+    if (count && ctl->mode == BS_DONE) {
+        ctl->mode = BS_RELAX;
+        ctl->nf = ctl->mf = 0;
+    }
+}
+
+__global__ void bs_session_init(BsArgs a)
+{
+    if (threadIdx.x != 0) return;
+    BsCtl *ctl = a.ctl;
+    ctl->mode = BS_DONE;
+    ctl->nf = ctl->mf = 0;
+    ctl->iter = 0;
+    ctl->lo = 0;
+    ctl->hi = ctl->delta = 0xFFFFFFFFu;
+    ctl->far_any = 0;
+    ctl->split_kept = 0;
+    ctl->split_min = 0xFFFFFFFFu;
+    ctl->overflow = ctl->parity = ctl->err = ctl->splits = 0;
+    ctl->relaxed = ctl->improvements = ctl->pair_entries = 0ull;
+    ctl->active = 0ull;
+}
+
+namespace {
+struct BsLayout {
+    size_t n, nwords, nparts, G, blocks;
+    size_t total() const
+    {
+        return al256(256 * n) + al256(8 * n) + 2 * al256(64 * n) + 2 * al256(32 * nwords) + 3 * al256(4 * n) +
+               al256(4 * nparts) + al256(8 * G) + al256(16 * blocks) + al256(sizeof(BsCtl)) + al256(8 * blocks) +
+               al256(4 * 128) + al256(4 * 64 * n);
+    }
+};
+BsLayout bs_layout(int64_t n, int64_t m, int num_cu)
+{
+    BsLayout L;
+    L.n = (size_t)n;
+    L.nwords = (size_t)((n + 63) / 64) * 2;
+    L.nparts = (size_t)(m / 1024) + 2;
+    L.G = (size_t)num_cu * 7;
+    L.blocks = compact_geom((uint32_t)L.nwords, num_cu).blocks;
+    return L;
+}
+}  // namespace
+
+uint64_t sssp_session_bytes(int64_t n, int64_t m, int num_cu) { return bs_layout(n, m, num_cu).total(); }
+
+struct BsSession final : LaneSession {
+    Ctx &c;
+    Graph &g;
+    DevMem mem;
+    BsArgs a{};
+    CompactGeom cg{};
+    int G = 0;
+    uint32_t nwords = 0;
+    unsigned long long *status = nullptr;
+    int32_t *pairs = nullptr, *pin_pairs = nullptr;
+    BsCtl *pin = nullptr;
+
+    BsSession(Ctx &cc, Graph &gg, const Options &) : c(cc), g(gg)
+    {
+        if (!g.weighted) fail(GFR_E_INVALID, "sssp query: graph was loaded without weights");
+        n = g.n;
+        const BsLayout L = bs_layout(g.n, g.m, c.num_cu);
+        nwords = (uint32_t)L.nwords;
+        G = (int)L.G;
+        cg = compact_geom(nwords, c.num_cu);
+        bytes = L.total();
+        GFR_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        GFR_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+        GFR_HIP(hipHostMalloc((void **)&pin, sizeof(BsCtl), hipHostMallocDefault));
+        GFR_HIP(hipHostMalloc((void **)&pin_pairs, 4 * 128, hipHostMallocDefault));
+        mem.alloc(bytes);
+        char *p = (char *)mem.p;
+        auto take = [&](size_t b) {
+            char *r = p;
+            p += al256(b);
+            return (void *)r;
+        };
+        a.R = g.R.as<int32_t>();
+        a.C = g.C.as<int32_t>();
+        a.W = g.W.as<uint32_t>();
+        a.n = g.n;
+        a.nwords = nwords;
+        a.D = (uint32_t *)take(256 * L.n);
+        a.qm = (unsigned long long *)take(8 * L.n);
+        a.nmark = (uint8_t *)take(64 * L.n);
+        a.fmark = (uint8_t *)take(64 * L.n);
+        a.nany = (uint8_t *)take(32 * L.nwords);
+        a.fany = (uint8_t *)take(32 * L.nwords);
+        a.q.v = (int32_t *)take(4 * L.n);
+        a.q.off = (uint32_t *)take(4 * L.n);
+        a.q.row = (int32_t *)take(4 * L.n);
+        a.q.part = (int32_t *)take(4 * L.nparts);
+        a.part = (uint32_t *)take(8 * L.G);
+        status = (unsigned long long *)take(16 * L.blocks);
+        a.ctl = (BsCtl *)take(sizeof(BsCtl));
+        a.actp = (unsigned long long *)take(8 * L.blocks);
+        pairs = (int32_t *)take(4 * 128);
+        stage = take(4 * 64 * L.n);
+        fill_u32(a.D, 0xFFFFFFFFu, 64 * L.n, stream);
+        fill_u32(a.nmark, 0u, 16 * L.n, stream);
+        fill_u32(a.fmark, 0u, 16 * L.n, stream);
+        fill_u32(a.nany, 0u, 8 * L.nwords, stream);
+        fill_u32(a.fany, 0u, 8 * L.nwords, stream);
+        fill_u32(a.part, 0u, 2 * L.G, stream);
+        fill_u32(status, 0u, 4 * L.blocks, stream);
+        hipLaunchKernelGGL(bs_session_init, dim3(1), dim3(64), 0, stream, a);
+        GFR_LAUNCH_CHECK();
+    }
+    ~BsSession() override
+    {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (pin) (void)hipHostFree(pin);
+        if (pin_pairs) (void)hipHostFree(pin_pairs);
+        if (done) (void)hipEventDestroy(done);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+    void admit(const int32_t *lanes, const int32_t *sources, int32_t count) override
+    {
+        if (count <= 0) return;
+        GFR_HIP(hipStreamSynchronize(stream));   // the pinned staging of the last admission is consumed
+        unsigned long long mask = 0;
+        for (int32_t i = 0; i < count; ++i) {
+            pin_pairs[2 * i] = lanes[i];
+            pin_pairs[2 * i + 1] = sources[i];
+            mask |= 1ull << lanes[i];
+        }
+        GFR_HIP(hipMemcpyAsync(pairs, pin_pairs, 8ull * count, hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL(bs_clear_lanes, dim3(G), dim3(GFR_BLOCK), 0, stream, a.D, a.n, mask);
+        hipLaunchKernelGGL(bs_admit, dim3(1), dim3(64), 0, stream, a, pairs, count);
+        GFR_LAUNCH_CHECK();
+    }
+    void release(unsigned long long) override {}   // a finished lane has no queued pairs left
+    void step() override
+    {
+        hipLaunchKernelGGL(bsssp_relax<1024>, dim3(G), dim3(GFR_BLOCK), 0, stream, a);
+        hipLaunchKernelGGL(compact_kernel<BsMarks>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, stream, a.R, a.n, nwords,
+                           cg.wpt, BsMarks{a, (uint32_t)G, cg.blocks}, a.q, 1024u, status, &a.ctl->parity,
+                           &a.ctl->err);
+        GFR_LAUNCH_CHECK();
+        GFR_HIP(hipMemcpyAsync(pin, a.ctl, sizeof(BsCtl), hipMemcpyDeviceToHost, stream));
+        GFR_HIP(hipEventRecord(done, stream));
+    }
+    unsigned long long active() const override { return pin->mode == BS_DONE ? 0ull : pin->active; }
+    gfr_status failed(std::string &msg) const override
+    {
+        if (pin->err) {
+            msg = "sssp query: frontier compaction look-back timed out";
+            return GFR_E_DEVICE;
+        }
+        if (pin->overflow) {
+            msg = "sssp query: a path weight does not fit below 0xFFFFFFFF";
+            return GFR_E_INVALID;
+        }
+        return GFR_OK;
+    }
+    void extract(unsigned long long lanes) override
+    {
+        if (!lanes) return;
+        hipLaunchKernelGGL(bsssp_transpose, dim3(G), dim3(GFR_BLOCK), 0, stream, a.D, a.n, lanes, (uint32_t *)stage);
+        GFR_LAUNCH_CHECK();
+    }
+};
+
+std::unique_ptr<LaneSession> make_sssp_session(Ctx &c, Graph &g, const Options &o)
+{
+    return std::unique_ptr<LaneSession>(new BsSession(c, g, o));
 }
 
 }  // namespace gfr

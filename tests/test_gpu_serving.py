@@ -146,3 +146,59 @@ def test_cancel_and_poll_timeout(env):
     with pytest.raises(gfr.GfrError) as ei:
         ctx.cancel(10 ** 12)
     assert ei.value.status == gfr.GFR_E_NOT_FOUND
+
+
+def test_queries_join_running_sessions(env):
+    """Queries submitted while a session is mid-traversal join it at a level
+    boundary (continuous batching) and still equal the oracle; sessions of
+    two graphs run side by side."""
+    import torch
+    gfr, ctx, graphs = env
+    ctx.stat("serve.reset")
+    ctx.set_option("batch.min_bfs", 1)      # batch from the first query on
+    ctx.set_option("batch.min_sssp", 1)
+    rng = np.random.default_rng(11)
+    tickets, checks = [], []
+    for wave in range(6):
+        qs = []
+        for i in range(8):
+            name = "grid64" if i % 2 else "rmat12"
+            row, col, w, g = graphs[name]
+            kind = gfr.GFR_Q_SSSP if (i // 2) % 2 else gfr.GFR_Q_BFS
+            src = int(rng.integers(0, row.size - 1))
+            out = torch.empty(row.size - 1, dtype=torch.int32, device="cuda:0")
+            qs.append((kind, g, src, out))
+            checks.append((name, kind, src, out))
+        tickets += ctx.submit_queries(qs)
+        time.sleep(0.002)                      # the next wave arrives mid-traversal
+    got = _drain(ctx, tickets)
+    ctx.set_option("batch.min_bfs", 8)
+    ctx.set_option("batch.min_sssp", 24)
+    assert all(st == gfr.GFR_OK for st in got.values())
+    assert ctx.stat("serve.joined") > 0
+    for name, kind, src, out in checks:
+        row, col, w, g = graphs[name]
+        want = oracle.bfs(row, col, src) if kind == gfr.GFR_Q_BFS else oracle.sssp(row, col, w, src)
+        assert np.array_equal(out.cpu().numpy().view(want.dtype), want), (name, kind, src)
+
+
+def test_graph_free_waits_for_its_queries(env):
+    import torch
+    gfr, ctx, graphs = env
+    row, col = graphgen.rmat(10)
+    w = graphgen.weights(row, col, 64)
+    g = ctx.graph_load_csr(row, col, w)
+    outs = [torch.empty(row.size - 1, dtype=torch.int32, device="cuda:0") for _ in range(4)]
+    tickets = ctx.submit_queries([(gfr.GFR_Q_SSSP, g, i, outs[i]) for i in range(4)])
+    try:
+        g.free()
+        freed = True        # the queries finished before the call
+    except gfr.GfrError as e:
+        assert e.status == gfr.GFR_E_NOT_READY
+        freed = False
+    got = _drain(ctx, tickets)
+    assert all(st == gfr.GFR_OK for st in got.values())
+    for i, out in enumerate(outs):
+        assert np.array_equal(out.cpu().numpy().view(np.uint32), oracle.sssp(row, col, w, i))
+    if not freed:
+        g.free()
