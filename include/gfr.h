@@ -93,6 +93,8 @@ const char *gfr_last_error(const gfr_ctx *ctx);
  *   "batch.delta"     batched SSSP bucket width; 0 = "batch.delta_factor" times the
  *                     mean edge weight, where factor 0 (default) = a single bucket
  *   "serve.max_batch" largest number of queries the serving runtime runs together (1..64)
+ *   "serve.hipgraph"  1 (default): serving sessions replay their rounds of steps from
+ *                     hipGraphs captured once per session; 0: plain launches
  *   "batch.min_bfs", "batch.min_sssp"  batches smaller than this run as sequential
  *                     single-source solves (same results, lower cost for few sources)
  *   "profile.kernels" 1: time every launch of the level kernels with HIP events

@@ -275,7 +275,7 @@ static const OptKey kOptKeys[] = {
     {"msbfs.alpha", 1e-6, 1e9, true},    {"batch.delta", 0, 4.0e9, true},
     {"batch.min_bfs", 1, 1e9, true},     {"batch.min_sssp", 1, 1e9, true},
     {"serve.budget_bytes", 0, 1e15, false}, {"serve.max_batch", 1, 64, false},
-    {"profile.kernels", 0, 1, false},
+    {"profile.kernels", 0, 1, false}, {"serve.hipgraph", 0, 1, false},
 };
 
 static const OptKey &opt_key(const std::string &key)
@@ -303,6 +303,7 @@ void option_set(Options &o, const std::string &key, double v)
     else if (key == "serve.budget_bytes") o.serve_budget = v;
     else if (key == "serve.max_batch") o.serve_max_batch = (int)v;
     else if (key == "profile.kernels") o.profile_kernels = (int)v;
+    else if (key == "serve.hipgraph") o.serve_graphs = (int)v;
     else if (key == "advance.chunk") {
         const int iv = (int)v;
         if (iv != 256 && iv != 512 && iv != 1024 && iv != 2048 && iv != 4096)
@@ -328,6 +329,7 @@ static double option_get(const Options &o, const std::string &key)
     if (key == "batch.min_sssp") return o.batch_min_sssp;
     if (key == "serve.budget_bytes") return o.serve_budget;
     if (key == "serve.max_batch") return o.serve_max_batch;
+    if (key == "serve.hipgraph") return o.serve_graphs;
     return o.profile_kernels;
 }
 

@@ -123,6 +123,7 @@ struct Options {
     double batch_delta = 0.0;   // batched SSSP bucket width; 0 -> batch_delta_factor
     double batch_delta_factor = 0.0;   // x mean edge weight; 0 -> one bucket (frontier order)
     int serve_max_batch = 64;
+    int serve_graphs = 1;       // serving sessions replay their rounds from captured hipGraphs
     int batch_min_bfs = 8;      // fewer sources than this: sequential single-source BFS
     int batch_min_sssp = 24;    // fewer queries than this: sequential single-source SSSP
 };
@@ -284,13 +285,24 @@ constexpr uint32_t GATHER_CH = 1024;
 // All work is queued on the session's own stream; nothing blocks except
 // copy_to_host.  Lane results live in rows of a [64][n] stage.
 struct LaneSession {
-    virtual ~LaneSession() {}
+    virtual ~LaneSession()
+    {
+        for (auto &e : exec)
+            if (e) (void)hipGraphExecDestroy(e);
+    }
     // (re)start lanes: lanes[i] begins a query from sources[i] at the next step
     virtual void admit(const int32_t *lanes, const int32_t *sources, int32_t count) = 0;
     // lanes that left (their results were taken); they stop taking part
     virtual void release(unsigned long long lanes) = 0;
-    // one level / relaxation round, then the status read-back; `done` records its end
-    virtual void step() = 0;
+    // queue one level / relaxation round and the status read-back
+    virtual void enqueue_step() = 0;
+    // work to queue once before a round (outside any captured graph)
+    virtual void pre_round() {}
+    // k steps (k = 1, 2, 4 or 8), then `done` is recorded; with `graphs` the k
+    // steps are captured into a hipGraph once and replayed from then on
+    void round(int k, bool graphs);
+    hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool capture_failed = false;
     // after `done`: lanes that still have work, and whether the device flagged an error
     virtual unsigned long long active() const = 0;
     virtual gfr_status failed(std::string &msg) const = 0;

@@ -523,19 +523,21 @@ struct MsSession final : LaneSession {
         pending_release = 0;
     }
     void release(unsigned long long lanes) override { pending_release |= lanes; }
-    void step() override
+    void pre_round() override
     {
         if (pending_release) {
             hipLaunchKernelGGL(ms_admit, dim3(1), dim3(64), 0, stream, a, pairs, 0, pending_release);
             pending_release = 0;
         }
+    }
+    void enqueue_step() override
+    {
         hipLaunchKernelGGL(msbfs_level<GATHER_CH>, dim3(G), dim3(GFR_BLOCK), 0, stream, a);
         hipLaunchKernelGGL(msbfs_finalize, dim3(G), dim3(GFR_BLOCK), 0, stream, a);
         hipLaunchKernelGGL(compact_kernel<MsMarks>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, stream, a.R, a.n, nwords,
                            cg.wpt, MsMarks{a}, a.q, 1024u, status, &a.ctl->parity, &a.ctl->err);
         GFR_LAUNCH_CHECK();
         GFR_HIP(hipMemcpyAsync(pin, a.ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, stream));
-        GFR_HIP(hipEventRecord(done, stream));
     }
     // once the level loop has stopped, every lane's frontier is empty
     unsigned long long active() const override { return pin->dir == MS_DONE ? 0ull : pin->active; }

@@ -20,7 +20,9 @@
 // pool of threads that solve them one by one with the single-source solvers,
 // concurrently with the sessions (four threads, each with its own stream and
 // scratch memory).  While no query waits for a session it runs
-// several steps per round (up to 8) before it is looked at again.
+// several steps per round (up to 8) before it is looked at again; the steps
+// of a round are captured into a hipGraph once per session and replayed
+// ("serve.hipgraph").
 // With `serve.max_batch` = 1 every query takes the single-source path (the
 // unbatched reference).
 //
@@ -81,6 +83,36 @@ struct Server {
     uint64_t steps = 0, lane_steps = 0;
     uint64_t joined = 0;           // queries that joined a session with other lanes running
 };
+
+void LaneSession::round(int k, bool graphs)
+{
+    pre_round();
+    const int idx = k >= 8 ? 3 : k >= 4 ? 2 : k >= 2 ? 1 : 0;
+    k = 1 << idx;
+    if (graphs && !capture_failed && !exec[idx]) {
+        // capture the k steps once; kernel arguments never change, all state
+        // lives in the session's device memory
+        hipGraph_t gr = nullptr;
+        bool ok = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            for (int i = 0; i < k; ++i) enqueue_step();
+            ok = hipStreamEndCapture(stream, &gr) == hipSuccess && gr;
+        }
+        if (ok) ok = hipGraphInstantiate(&exec[idx], gr, nullptr, nullptr, 0) == hipSuccess;
+        if (gr) (void)hipGraphDestroy(gr);
+        if (!ok) {
+            (void)hipGetLastError();
+            exec[idx] = nullptr;
+            capture_failed = true;
+        }
+    }
+    if (graphs && exec[idx]) {
+        GFR_HIP(hipGraphLaunch(exec[idx], stream));
+    } else {
+        for (int i = 0; i < k; ++i) enqueue_step();
+    }
+    GFR_HIP(hipEventRecord(done, stream));
+}
 
 static uint64_t session_bytes(const Ctx &c, const Graph &g, int32_t kind)
 {
@@ -259,10 +291,12 @@ static void worker_loop(Server *sv)
     for (;;) {
         int max_batch;
         double budget;
+        bool use_graphs;
         {
             std::lock_guard<std::mutex> lo(c.opt_mu);
             max_batch = std::max(1, std::min(64, c.base_opt.serve_max_batch));
             budget = c.base_opt.serve_budget;
+            use_graphs = c.base_opt.serve_graphs != 0;
         }
         // unbatched reference: every query through the single-source thread
         if (max_batch == 1) {
@@ -461,7 +495,7 @@ static void worker_loop(Server *sv)
                         const bool wait = std::find(waiting.begin(), waiting.end(),
                                                     std::make_pair(e.graph, e.kind)) != waiting.end();
                         e.round = wait ? 1 : std::min(8, e.round * 2);
-                        for (int k = 0; k < e.round; ++k) e.s->step();
+                        e.s->round(e.round, use_graphs);
                         e.in_flight = true;
                         std::lock_guard<std::mutex> lk(sv->mu);
                         sv->steps += (uint64_t)e.round;

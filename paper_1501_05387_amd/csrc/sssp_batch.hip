@@ -692,7 +692,7 @@ struct BsSession final : LaneSession {
         GFR_LAUNCH_CHECK();
     }
     void release(unsigned long long) override {}   // a finished lane has no queued pairs left
-    void step() override
+    void enqueue_step() override
     {
         hipLaunchKernelGGL(bsssp_relax<1024>, dim3(G), dim3(GFR_BLOCK), 0, stream, a);
         hipLaunchKernelGGL(compact_kernel<BsMarks>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, stream, a.R, a.n, nwords,
@@ -700,7 +700,6 @@ struct BsSession final : LaneSession {
                            &a.ctl->err);
         GFR_LAUNCH_CHECK();
         GFR_HIP(hipMemcpyAsync(pin, a.ctl, sizeof(BsCtl), hipMemcpyDeviceToHost, stream));
-        GFR_HIP(hipEventRecord(done, stream));
     }
     unsigned long long active() const override { return pin->mode == BS_DONE ? 0ull : pin->active; }
     gfr_status failed(std::string &msg) const override

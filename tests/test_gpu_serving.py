@@ -202,3 +202,41 @@ def test_graph_free_waits_for_its_queries(env):
         assert np.array_equal(out.cpu().numpy().view(np.uint32), oracle.sssp(row, col, w, i))
     if not freed:
         g.free()
+
+
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_session_rounds_with_and_without_hipgraph(env, graphs):
+    """Session rounds replayed from captured hipGraphs (many replays, with
+    eager work and synchronisations between them) give the same results as
+    plain launches and the oracle."""
+    import torch
+    gfr, ctx, graphs_ = env
+    ctx.set_option("serve.hipgraph", graphs)
+    ctx.set_option("batch.min_bfs", 1)
+    ctx.set_option("batch.min_sssp", 1)
+    try:
+        rng = np.random.default_rng(20 + graphs)
+        checks, tickets = [], []
+        for wave in range(4):
+            qs = []
+            for i in range(12):
+                name = ("rmat12", "grid64")[i % 2]
+                row, col, w, g = graphs_[name]
+                kind = (gfr.GFR_Q_BFS, gfr.GFR_Q_SSSP)[(i // 2) % 2]
+                src = int(rng.integers(0, row.size - 1))
+                out = torch.empty(row.size - 1, dtype=torch.int32, device="cuda:0")
+                qs.append((kind, g, src, out))
+                checks.append((name, kind, src, out))
+            tickets += ctx.submit_queries(qs)
+            torch.cuda.synchronize()                 # eager work between the replays
+            _ = ctx.bfs(graphs_["rmat12"][3], wave)
+        got = _drain(ctx, tickets)
+        assert all(st == gfr.GFR_OK for st in got.values())
+        for name, kind, src, out in checks:
+            row, col, w, g = graphs_[name]
+            want = oracle.bfs(row, col, src) if kind == gfr.GFR_Q_BFS else oracle.sssp(row, col, w, src)
+            assert np.array_equal(out.cpu().numpy().view(want.dtype), want), (graphs, name, kind, src)
+    finally:
+        ctx.set_option("serve.hipgraph", 1)
+        ctx.set_option("batch.min_bfs", 8)
+        ctx.set_option("batch.min_sssp", 24)
