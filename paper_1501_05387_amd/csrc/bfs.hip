@@ -252,7 +252,7 @@ void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s)
     const uint32_t chunk = (uint32_t)c.opt.advance_chunk;
     const uint32_t nwords = (uint32_t)(((int64_t)n + 63) / 64) * 2u;
     const size_t nparts = (size_t)(g.m / chunk) + 2;
-    const int G = grid_blocks(c, 4);
+    const int G = grid_blocks(c, 8);   // eight work-groups per CU fit at the default chunk
     const CompactGeom cg = compact_geom(nwords, c.num_cu);
     size_t need = 2 * al256(nwords * 4ull) + al256(nwords * 32ull) + 3 * al256(4ull * n) + al256(4 * nparts) +
                   al256(4ull * G) + al256(16ull * cg.blocks) + al256(sizeof(BfsCtl));

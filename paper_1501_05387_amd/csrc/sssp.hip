@@ -83,31 +83,43 @@ __global__ __launch_bounds__(GFR_BLOCK) void sssp_relax(SsspArgs a)
             s_du[i] = a.dist[q.v[s + i]];
         }
         __syncthreads();
-#pragma unroll 2
-        for (uint32_t k = 0; k < (uint32_t)CH; k += GFR_BLOCK) {
-            const uint32_t e = e0 + k + threadIdx.x;
-            if (e < e1) {
-                const int i = upper_index(s_off, 0, cnt - 1, e);
-                const int32_t idx = s_row[i] + (int32_t)(e - s_off[i]);
-                const int32_t v = a.C[idx];
-                const unsigned long long nd64 = (unsigned long long)s_du[i] + a.W[idx];
-                if (nd64 >= 0xFFFFFFFFull) {
-                    ovf = true;
+        // each thread takes every GFR_BLOCK-th edge of the chunk: all its
+        // column and weight loads are issued first, then all distance probes,
+        // and the tests are computed for every edge so that no load is moved
+        // into a branch and waited for there (an edge past the chunk end
+        // repeats the chunk's first edge and is masked)
+        constexpr int PER = CH / GFR_BLOCK;
+        int32_t vv[PER];
+        uint32_t nd[PER], dv[PER];
+        bool ok[PER], fits[PER];
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const uint32_t e = e0 + p * GFR_BLOCK + threadIdx.x;
+            ok[p] = e < e1;
+            const uint32_t ec = ok[p] ? e : e0;
+            const int i = upper_index(s_off, 0, cnt - 1, ec);
+            const int32_t idx = s_row[i] + (int32_t)(ec - s_off[i]);
+            vv[p] = a.C[idx];
+            const unsigned long long nd64 = (unsigned long long)s_du[i] + a.W[idx];
+            fits[p] = nd64 < 0xFFFFFFFFull;
+            nd[p] = (uint32_t)nd64;
+        }
+#pragma unroll
+        for (int p = 0; p < PER; ++p) dv[p] = a.dist[vv[p]];
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            ovf |= ok[p] & !fits[p];
+            // non-returning atomicMin; marking on the pre-check marks a
+            // superset of the true improvements, which only re-relaxes such
+            // a vertex with its current distance
+            if (ok[p] & fits[p] & (nd[p] < dv[p])) {
+                atomicMin(a.dist + vv[p], nd[p]);
+                ++nimp;
+                if (nd[p] < hi) {
+                    a.near[vv[p]] = 1;
                 } else {
-                    const uint32_t nd = (uint32_t)nd64;
-                    // non-returning atomicMin; marking on the pre-check marks a
-                    // superset of the true improvements, which only re-relaxes
-                    // such a vertex with its current distance
-                    if (nd < a.dist[v]) {
-                        atomicMin(a.dist + v, nd);
-                        ++nimp;
-                        if (nd < hi) {
-                            a.near[v] = 1;
-                        } else {
-                            a.far[v] = 1;
-                            ++nfar;
-                        }
-                    }
+                    a.far[vv[p]] = 1;
+                    ++nfar;
                 }
             }
         }
@@ -311,7 +323,7 @@ void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s)
     const uint32_t nwords = (uint32_t)(((int64_t)n + 63) / 64) * 2u;
     const size_t nparts = (size_t)(g.m / chunk) + 2;
     const uint32_t delta = c.opt.sssp_delta > 0 ? (uint32_t)c.opt.sssp_delta : sssp_auto_delta(g, c.opt.sssp_delta_factor);
-    const int G = grid_blocks(c, 4);
+    const int G = grid_blocks(c, 8);   // eight work-groups per CU fit at the default chunk
     const CompactGeom cg = compact_geom(nwords, c.num_cu);
     size_t need = 2 * al256(nwords * 32ull) + 3 * al256(4ull * n) + al256(4 * nparts) + al256(8ull * G) +
                   al256(16ull * cg.blocks) + al256(sizeof(SsspCtl));
