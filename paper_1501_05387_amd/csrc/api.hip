@@ -274,6 +274,7 @@ static const OptKey kOptKeys[] = {
     {"sssp.delta_factor", 1e-3, 1e6, true}, {"batch.delta_factor", 0, 1e6, true},
     {"msbfs.alpha", 1e-6, 1e9, true},    {"batch.delta", 0, 4.0e9, true},
     {"batch.min_bfs", 1, 1e9, true},     {"batch.min_sssp", 1, 1e9, true},
+    {"batch.pull_alpha", 0, 1e6, true},
     {"serve.budget_bytes", 0, 1e15, false}, {"serve.max_batch", 1, 64, false},
     {"profile.kernels", 0, 1, false}, {"serve.hipgraph", 0, 1, false},
 };
@@ -300,6 +301,7 @@ void option_set(Options &o, const std::string &key, double v)
     else if (key == "batch.delta") o.batch_delta = v;
     else if (key == "batch.min_bfs") o.batch_min_bfs = (int)v;
     else if (key == "batch.min_sssp") o.batch_min_sssp = (int)v;
+    else if (key == "batch.pull_alpha") o.batch_pull_alpha = v;
     else if (key == "serve.budget_bytes") o.serve_budget = v;
     else if (key == "serve.max_batch") o.serve_max_batch = (int)v;
     else if (key == "profile.kernels") o.profile_kernels = (int)v;
@@ -327,6 +329,7 @@ static double option_get(const Options &o, const std::string &key)
     if (key == "batch.delta") return o.batch_delta;
     if (key == "batch.min_bfs") return o.batch_min_bfs;
     if (key == "batch.min_sssp") return o.batch_min_sssp;
+    if (key == "batch.pull_alpha") return o.batch_pull_alpha;
     if (key == "serve.budget_bytes") return o.serve_budget;
     if (key == "serve.max_batch") return o.serve_max_batch;
     if (key == "serve.hipgraph") return o.serve_graphs;

@@ -122,6 +122,7 @@ struct Options {
     double msbfs_alpha = 4.0;   // batched BFS: pull when frontier edges > m / alpha
     double batch_delta = 0.0;   // batched SSSP bucket width; 0 -> batch_delta_factor
     double batch_delta_factor = 0.0;   // x mean edge weight; 0 -> one bucket (frontier order)
+    double batch_pull_alpha = 0.0;     // batched SSSP: pull sweep when frontier edges > m / alpha (0: never)
     int serve_max_batch = 64;
     int serve_graphs = 1;       // serving sessions replay their rounds from captured hipGraphs
     int batch_min_bfs = 8;      // fewer sources than this: sequential single-source BFS

@@ -33,6 +33,7 @@
 namespace gfr {
 
 enum : uint32_t { BS_RELAX = 0, BS_SPLIT = 1, BS_DONE = 2 };
+enum : uint32_t { BS_PUSH = 0, BS_PULL = 1 };
 
 struct BsCtl {
     uint32_t mode;
@@ -44,6 +45,10 @@ struct BsCtl {
     uint32_t overflow, parity, err, splits;
     unsigned long long relaxed, improvements, pair_entries;
     unsigned long long active;   // queries with a (vertex, query) pair in the next near queue
+    uint32_t dir;                // BS_PUSH / BS_PULL for the next relaxation
+    float pull_alpha;            // pull when the frontier's edges exceed m / pull_alpha (0: never)
+    unsigned long long m;
+    uint32_t pull_iters, pad2;
 };
 
 struct BsArgs {
@@ -59,6 +64,9 @@ struct BsArgs {
     FrontierQ q;
     uint32_t *part;              // per work-group [improvements, far marks written]
     unsigned long long *actp;    // per compaction group: OR of the query masks it queued
+    uint32_t *fbits;             // [nwords] frontier bitmap of the next relaxation (qm valid where set)
+    FrontierQ full;              // every vertex with edges (pull sweeps)
+    uint32_t full_nf, full_mf;
     BsCtl *ctl;
 };
 
@@ -70,7 +78,7 @@ template <int CH>
 __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
 {
     BsCtl *ctl = a.ctl;
-    if (ctl->mode != BS_RELAX) return;
+    if (ctl->mode != BS_RELAX || ctl->dir != BS_PUSH) return;
     const uint32_t hi = ctl->hi, nf = ctl->nf, mf = ctl->mf;
     const FrontierQ q = a.q;
     __shared__ uint32_t s_off[CH + 1];
@@ -204,6 +212,148 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
     }
 }
 
+// Pull relaxation for frontiers that carry most of the edges: a
+// load-balanced sweep over every vertex's list (the whole-graph queue).  An
+// edge u->v with u in the frontier contributes dist[u][q] + w to a running
+// minimum of v, per query q active at u; each wave flushes the minimum of an
+// owner v once (one pre-checked atomicMin and mark per query) instead of once
+// per improving edge.  Sources outside the frontier cost one bitmap probe.
+constexpr int BP_UNROLL = 8;
+
+template <int CH>
+__global__ __launch_bounds__(GFR_BLOCK) void bsssp_pull(BsArgs a)
+{
+    BsCtl *ctl = a.ctl;
+    if (ctl->mode != BS_RELAX || ctl->dir != BS_PULL) return;
+    const uint32_t hi = ctl->hi;
+    const FrontierQ q = a.full;
+    const uint32_t nf = a.full_nf, mf = a.full_mf;
+    __shared__ uint32_t s_off[CH + 1];
+    __shared__ int32_t s_row[CH + 1];
+    __shared__ int32_t s_v[CH + 1];
+    const int lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    constexpr uint32_t QW = CH / GFR_WAVES;
+    const uint32_t nchunks = (mf + CH - 1) / CH;
+    uint32_t nimp = 0, nfar = 0;
+    bool ovf = false;
+    int32_t cur = -1;                 // owner whose minimum is being formed (wave-uniform)
+    uint32_t acc = 0xFFFFFFFFu;       // its minimum for this lane's query
+    uint32_t old = 0;                 // the owner's distance, loaded when the owner starts
+    auto flush = [&]() {
+        if (cur >= 0) {
+            const bool imp = acc < old;
+            const bool near_imp = imp & (acc < hi), far_imp = imp & (acc >= hi);
+            if (imp) {
+                atomicMin(a.D + (size_t)cur * 64 + lane, acc);
+                ++nimp;
+                (near_imp ? a.nmark : a.fmark)[(size_t)cur * 64 + lane] = 1;
+            }
+            const uint64_t bn = ballot(near_imp), bf = ballot(far_imp);
+            if (lane == 0) {
+                if (bn) a.nany[cur] = 1;
+                if (bf) {
+                    a.fany[cur] = 1;
+                    ++nfar;
+                }
+            }
+        }
+        acc = 0xFFFFFFFFu;
+    };
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const uint32_t e0 = c * CH;
+        const uint32_t e1 = min(e0 + (uint32_t)CH, mf);
+        const int s = q.part[c];
+        const int t = (c + 1 < nchunks) ? q.part[c + 1] : (int)nf - 1;
+        const int cnt = t - s + 1;
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += GFR_BLOCK) {
+            s_off[i] = q.off[s + i];
+            s_row[i] = q.row[s + i];
+            s_v[i] = q.v[s + i];
+        }
+        __syncthreads();
+        const uint32_t eb = e0 + wave * QW, ee = min(eb + QW, e1);
+        if (eb >= ee) continue;
+        int ilo = upper_index(s_off, 0, cnt - 1, eb);
+        for (uint32_t e = eb; e < ee; e += 64) {
+            // lane l: edge e + l, its source u (the neighbour), owner v and,
+            // if u is in the frontier, u's query mask (entry bounds as in
+            // bsssp_relax)
+            const int nb = (int)min(64u, ee - e);
+            int32_t ul = 0, vl = 0, wl = 0, il = ilo;
+            unsigned long long ql = 0;
+            if (lane < nb) {
+                const uint32_t el = e + lane;
+                il = upper_index(s_off, ilo, min(cnt - 1, ilo + lane + 1), el);
+                const int32_t idx = s_row[il] + (int32_t)(el - s_off[il]);
+                ul = a.C[idx];
+                wl = (int32_t)a.W[idx];
+                vl = s_v[il];
+                if ((a.fbits[ul >> 5] >> (ul & 31)) & 1u) ql = a.qm[ul];
+            }
+            ilo = lane_bcast(il, nb - 1);
+            unsigned long long act = ballot(ql != 0ull);
+            const int32_t qlo = (int32_t)(uint32_t)ql, qhi = (int32_t)(uint32_t)(ql >> 32);
+            while (act) {
+                // the next BP_UNROLL edges with a frontier source, in order;
+                // their source rows are loaded together
+                int jj[BP_UNROLL];
+#pragma unroll
+                for (int k = 0; k < BP_UNROLL; ++k) {
+                    jj[k] = act ? __ffsll(act) - 1 : -1;
+                    act &= act - 1;
+                }
+                uint32_t du[BP_UNROLL], ww[BP_UNROLL], qw[BP_UNROLL];
+                int32_t vv[BP_UNROLL];
+#pragma unroll
+                for (int k = 0; k < BP_UNROLL; ++k) {
+                    const int j = jj[k] < 0 ? jj[0] : jj[k];
+                    const int32_t u = lane_bcast(ul, j);
+                    vv[k] = lane_bcast(vl, j);
+                    ww[k] = (uint32_t)lane_bcast(wl, j);
+                    const uint32_t q0 = (uint32_t)lane_bcast(qlo, j), q1 = (uint32_t)lane_bcast(qhi, j);
+                    qw[k] = lane < 32 ? q0 : q1;
+                    du[k] = a.D[(size_t)u * 64 + lane];
+                }
+#pragma unroll
+                for (int k = 0; k < BP_UNROLL; ++k) {
+                    if (jj[k] < 0) break;
+                    if (vv[k] != cur) {
+                        flush();
+                        cur = vv[k];
+                        old = a.D[(size_t)cur * 64 + lane];   // read by the owner's flush
+                    }
+                    const bool on = ((qw[k] >> (lane & 31)) & 1u) != 0;
+                    const unsigned long long nd64 = (unsigned long long)du[k] + ww[k];
+                    const bool fits = nd64 < 0xFFFFFFFFull;
+                    ovf |= on & !fits;
+                    const uint32_t nd = (uint32_t)nd64;
+                    acc = (on & fits & (nd < acc)) ? nd : acc;
+                }
+            }
+        }
+        flush();
+        cur = -1;
+    }
+    if (ovf) ctl->overflow = 1u;
+    __shared__ uint32_t s_a[GFR_WAVES], s_b[GFR_WAVES];
+    nimp = wave_sum_u32(nimp);
+    if (lane == 0) {
+        s_a[wave] = nimp;
+        s_b[wave] = nfar;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t x = 0, y = 0;
+        for (int k = 0; k < GFR_WAVES; ++k) {
+            x += s_a[k];
+            y += s_b[k];
+        }
+        a.part[2 * blockIdx.x] = x;
+        a.part[2 * blockIdx.x + 1] = y;
+    }
+}
+
 // 64 mark bytes (0/1) of one vertex -> query mask; clears them when `clear`
 __device__ __forceinline__ unsigned long long row_mask(uint8_t *p, bool clear)
 {
@@ -231,6 +381,7 @@ struct BsMarks {
         BsCtl *ctl = a.ctl;
         if (ctl->mode == BS_RELAX) {
             const uint32_t m = marks_to_mask(a.nany + 32ull * w);
+            a.fbits[w] = m;
             if (!m) return 0u;
             clear_marks(a.nany + 32ull * w);
             uint32_t bits = m;
@@ -245,7 +396,10 @@ struct BsMarks {
             return m;
         }
         const uint32_t f = marks_to_mask(a.fany + 32ull * w);
-        if (!f) return 0u;
+        if (!f) {
+            a.fbits[w] = 0u;
+            return 0u;
+        }
         const uint32_t lo = ctl->lo, hi = ctl->hi;
         uint32_t out = 0, bits = f;
         while (bits) {
@@ -272,6 +426,7 @@ struct BsMarks {
                 out |= 1u << bi;
             }
         }
+        a.fbits[w] = out;
         return out;
     }
 
@@ -361,7 +516,8 @@ struct BsMarks {
         const uint32_t D = ctl->delta, hi = ctl->hi;
         uint32_t split_min = 0xFFFFFFFFu;
         if (mode == BS_RELAX) {
-            ctl->relaxed += ctl->mf;
+            ctl->relaxed += ctl->dir == BS_PULL ? ctl->m : ctl->mf;
+            ctl->pull_iters += ctl->dir == BS_PULL ? 1u : 0u;
             ctl->improvements += imp;
             if (far) ctl->far_any = 1u;
         } else {
@@ -393,10 +549,12 @@ struct BsMarks {
         ctl->iter += 1u;
         ctl->parity ^= 1u;
         ctl->mode = nm;
+        // a frontier carrying most of the edges is relaxed by a pull sweep
+        ctl->dir = (ctl->pull_alpha > 0.f && (double)mf2 * ctl->pull_alpha > (double)ctl->m) ? BS_PULL : BS_PUSH;
     }
 };
 
-__global__ void bsssp_init(BsArgs a, const int32_t *src, int32_t k, uint32_t delta)
+__global__ void bsssp_init(BsArgs a, const int32_t *src, int32_t k, uint32_t delta, float pull_alpha)
 {
     if (threadIdx.x == 0) {
         for (int32_t q = 0; q < k; ++q) {
@@ -417,6 +575,11 @@ __global__ void bsssp_init(BsArgs a, const int32_t *src, int32_t k, uint32_t del
         ctl->split_min = 0xFFFFFFFFu;
         ctl->overflow = ctl->parity = ctl->err = ctl->splits = 0;
         ctl->relaxed = ctl->improvements = ctl->pair_entries = 0ull;
+        ctl->active = 0ull;
+        ctl->dir = BS_PUSH;
+        ctl->pull_alpha = pull_alpha;
+        ctl->m = (unsigned long long)a.R[a.n];
+        ctl->pull_iters = 0;
     }
 }
 
@@ -464,7 +627,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     else if (c.opt.batch_delta_factor > 0) delta = sssp_auto_delta(g, c.opt.batch_delta_factor);
     c.arena.reserve(al256(256ull * n) + al256(8ull * n) + 2 * al256(64ull * n) + 2 * al256(32ull * nwords) +
                     3 * al256(4ull * n) + al256(4 * nparts) + al256(8ull * G) + al256(16ull * cg.blocks) +
-                    al256(sizeof(BsCtl)) + al256(4 * 64) + al256(8ull * cg.blocks));
+                    al256(sizeof(BsCtl)) + al256(4 * 64) + al256(8ull * cg.blocks) + al256(4ull * nwords));
     BsArgs a;
     a.R = g.R.as<int32_t>();
     a.C = g.C.as<int32_t>();
@@ -486,7 +649,11 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     a.ctl = c.arena.take<BsCtl>(1);
     int32_t *dsrc = c.arena.take<int32_t>(64);
     a.actp = c.arena.take<unsigned long long>(cg.blocks);
-    double iters = 0, relaxed = 0, imps = 0;
+    a.fbits = c.arena.take<uint32_t>(nwords);
+    a.full = g.full;
+    a.full_nf = (uint32_t)g.full_nf;
+    a.full_mf = (uint32_t)g.m;
+    double iters = 0, relaxed = 0, imps = 0, pulls = 0;
     for (int32_t g0 = 0; g0 < k; g0 += 64) {
         const int32_t kk = std::min<int32_t>(64, k - g0);
         fill_u32(a.D, 0xFFFFFFFFu, 64ull * n, s);
@@ -497,7 +664,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
         fill_u32(a.part, 0u, 2ull * G, s);
         fill_u32(status, 0u, 4ull * cg.blocks, s);
         GFR_HIP(hipMemcpyAsync(dsrc, sources + g0, 4ull * kk, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(bsssp_init, dim3(1), dim3(64), 0, s, a, dsrc, kk, delta);
+        hipLaunchKernelGGL(bsssp_init, dim3(1), dim3(64), 0, s, a, dsrc, kk, delta, (float)c.opt.batch_pull_alpha);
         BsMarks marks{a, (uint32_t)G, cg.blocks};
         auto compact = [&]() {
             c.ktimer.run("bsssp_compact", s, [&]() {
@@ -510,6 +677,9 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
         auto launch = [&]() {
             c.ktimer.run("bsssp_relax", s, [&]() {
                 hipLaunchKernelGGL(bsssp_relax<1024>, dim3(G), dim3(GFR_BLOCK), 0, s, a);
+            });
+            c.ktimer.run("bsssp_pull", s, [&]() {
+                hipLaunchKernelGGL(bsssp_pull<1024>, dim3(G), dim3(GFR_BLOCK), 0, s, a);
             });
             compact();
         };
@@ -526,10 +696,12 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
         iters += h.iter;
         relaxed += (double)h.relaxed;
         imps += (double)h.improvements;
+        pulls += h.pull_iters;
     }
     c.stats.v["iterations"] += iters;
     c.stats.v["relaxations"] += relaxed;   // edge visits, each serving up to 64 queries
     c.stats.v["improvements"] += imps;
+    c.stats.v["pull_iterations"] += pulls;
     c.stats.v["solves"] += k;
 }
 
@@ -564,7 +736,7 @@ __global__ void bs_admit(BsArgs a, const int32_t *pairs, int32_t count)
     }
 }
 
-__global__ void bs_session_init(BsArgs a)
+__global__ void bs_session_init(BsArgs a, float pull_alpha)
 {
     if (threadIdx.x != 0) return;
     BsCtl *ctl = a.ctl;
@@ -579,6 +751,10 @@ __global__ void bs_session_init(BsArgs a)
     ctl->overflow = ctl->parity = ctl->err = ctl->splits = 0;
     ctl->relaxed = ctl->improvements = ctl->pair_entries = 0ull;
     ctl->active = 0ull;
+    ctl->dir = BS_PUSH;
+    ctl->pull_alpha = pull_alpha;
+    ctl->m = (unsigned long long)a.R[a.n];
+    ctl->pull_iters = 0;
 }
 
 namespace {
@@ -588,7 +764,7 @@ struct BsLayout {
     {
         return al256(256 * n) + al256(8 * n) + 2 * al256(64 * n) + 2 * al256(32 * nwords) + 3 * al256(4 * n) +
                al256(4 * nparts) + al256(8 * G) + al256(16 * blocks) + al256(sizeof(BsCtl)) + al256(8 * blocks) +
-               al256(4 * 128) + al256(4 * 64 * n);
+               al256(4 * 128) + al256(4 * 64 * n) + al256(4 * nwords);
     }
 };
 BsLayout bs_layout(int64_t n, int64_t m, int num_cu)
@@ -617,7 +793,7 @@ struct BsSession final : LaneSession {
     int32_t *pairs = nullptr, *pin_pairs = nullptr;
     BsCtl *pin = nullptr;
 
-    BsSession(Ctx &cc, Graph &gg, const Options &) : c(cc), g(gg)
+    BsSession(Ctx &cc, Graph &gg, const Options &o) : c(cc), g(gg)
     {
         if (!g.weighted) fail(GFR_E_INVALID, "sssp query: graph was loaded without weights");
         n = g.n;
@@ -658,6 +834,10 @@ struct BsSession final : LaneSession {
         a.actp = (unsigned long long *)take(8 * L.blocks);
         pairs = (int32_t *)take(4 * 128);
         stage = take(4 * 64 * L.n);
+        a.fbits = (uint32_t *)take(4 * L.nwords);
+        a.full = g.full;
+        a.full_nf = (uint32_t)g.full_nf;
+        a.full_mf = (uint32_t)g.m;
         fill_u32(a.D, 0xFFFFFFFFu, 64 * L.n, stream);
         fill_u32(a.nmark, 0u, 16 * L.n, stream);
         fill_u32(a.fmark, 0u, 16 * L.n, stream);
@@ -665,7 +845,7 @@ struct BsSession final : LaneSession {
         fill_u32(a.fany, 0u, 8 * L.nwords, stream);
         fill_u32(a.part, 0u, 2 * L.G, stream);
         fill_u32(status, 0u, 4 * L.blocks, stream);
-        hipLaunchKernelGGL(bs_session_init, dim3(1), dim3(64), 0, stream, a);
+        hipLaunchKernelGGL(bs_session_init, dim3(1), dim3(64), 0, stream, a, (float)o.batch_pull_alpha);
         GFR_LAUNCH_CHECK();
     }
     ~BsSession() override
@@ -695,6 +875,7 @@ struct BsSession final : LaneSession {
     void enqueue_step() override
     {
         hipLaunchKernelGGL(bsssp_relax<1024>, dim3(G), dim3(GFR_BLOCK), 0, stream, a);
+        hipLaunchKernelGGL(bsssp_pull<1024>, dim3(G), dim3(GFR_BLOCK), 0, stream, a);
         hipLaunchKernelGGL(compact_kernel<BsMarks>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, stream, a.R, a.n, nwords,
                            cg.wpt, BsMarks{a, (uint32_t)G, cg.blocks}, a.q, 1024u, status, &a.ctl->parity,
                            &a.ctl->err);

@@ -457,3 +457,33 @@ def test_output_reuse_is_ordered_with_the_default_stream(ctx):
     finally:
         ctx.set_option("batch.min_bfs", 8)
         g.free()
+
+
+@pytest.mark.parametrize("name", ["rmat16", "grid96", "star5000", "forest"])
+@pytest.mark.parametrize("alpha", [0.5, 1e6])
+def test_sssp_batch_pull_sweeps(ctx, name, alpha):
+    """Batched SSSP with pull sweeps (alpha 1e6: every iteration pulls; 0.5:
+    only frontiers carrying more than twice the edges, i.e. none after the
+    first few) equals the oracle; duplicated and isolated sources included."""
+    row, col, w = graph(name)
+    n = row.size - 1
+    rng = np.random.default_rng(3)
+    src = rng.integers(0, n, size=40).astype(np.int32)
+    src[1] = src[2]
+    iso = np.nonzero(np.diff(row) == 0)[0]
+    if iso.size:
+        src[-1] = iso[0]
+    g = _load(ctx, row, col, w)
+    ctx.set_option("batch.pull_alpha", alpha)
+    ctx.set_option("batch.min_sssp", 1)
+    try:
+        _say("sssp_batch pull", name, alpha)
+        s = _host(ctx.sssp_batch(g, src)).view(np.uint32).reshape(src.size, n)
+        if alpha > 1:
+            assert ctx.stat("pull_iterations") > 0
+        for i in (0, 1, 2, 17, src.size - 1):
+            assert np.array_equal(s[i], oracle.sssp(row, col, w, src[i])), (name, alpha, i)
+    finally:
+        ctx.set_option("batch.pull_alpha", 0)
+        ctx.set_option("batch.min_sssp", 24)
+        g.free()
