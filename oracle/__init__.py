@@ -13,8 +13,11 @@ Every function follows a textbook definition named in the paper:
 * ``bc``        Brandes' two-pass betweenness (Sec. 5.3), FP64.
 * ``cc``        component labels (Sec. 5.4), union-find, label = min vertex id.
 * ``pagerank``  FP64 power iteration (Sec. 5.5), uniform dangling redistribution.
+* ``pagerank_filtered``  the same iteration with per-vertex convergence
+  filtering (Sec. 5.5): a vertex leaves the frontier once its rank changes by
+  less than a tolerance and keeps that rank from then on.
 
-All five are pinned against brute force, closed forms, library routines and
+All six are pinned against brute force, closed forms, library routines and
 invariants in ``tests/test_oracle_pins.py``.
 """
 from __future__ import annotations
@@ -57,6 +60,8 @@ class Oracle:
         lib.or_cc.argtypes = [i32, vp, vp, vp]
         lib.or_pagerank.restype = i32
         lib.or_pagerank.argtypes = [i32, vp, vp, f64, f64, i32, vp, vp, vp]
+        lib.or_pagerank_filtered.restype = i32
+        lib.or_pagerank_filtered.argtypes = [i32, vp, vp, f64, f64, i32, vp, vp, vp, vp]
         self.lib = lib
         self.path = libpath
 
@@ -113,6 +118,20 @@ class Oracle:
             raise ValueError("oracle.pagerank: bad input")
         return x, int(it.value), float(l1.value)
 
+    def pagerank_filtered(self, row, col, damping: float, vertex_tol: float, max_iter: int = 1000):
+        """(FP64 ranks, iterations run, last summed change, final frontier membership)
+        of PageRank with per-vertex convergence filtering."""
+        row, col = _c(row, np.int32), _c(col, np.int32)
+        n = row.size - 1
+        x = np.empty(n, np.float64)
+        act = np.empty(n, np.uint8)
+        it = ctypes.c_int32(0)
+        l1 = ctypes.c_double(0.0)
+        if self.lib.or_pagerank_filtered(n, _p(row), _p(col), float(damping), float(vertex_tol), int(max_iter),
+                                         _p(x), ctypes.addressof(it), ctypes.addressof(l1), _p(act)) != 0:
+            raise ValueError("oracle.pagerank_filtered: bad input")
+        return x, int(it.value), float(l1.value), act.astype(bool)
+
 
 _default = None
 
@@ -150,3 +169,7 @@ def cc(row, col):
 
 def pagerank(row, col, damping: float = 0.85, tol: float = 1e-6, max_iter: int = 1000):
     return default().pagerank(row, col, damping, tol, max_iter)
+
+
+def pagerank_filtered(row, col, damping: float, vertex_tol: float, max_iter: int = 1000):
+    return default().pagerank_filtered(row, col, damping, vertex_tol, max_iter)

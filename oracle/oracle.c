@@ -229,6 +229,33 @@ OR_EXPORT int32_t or_cc(int32_t n, const int32_t *R, const int32_t *C, int32_t *
 }
 
 /* --------------------------------------------------------- PageRank ---- */
+/* PageRank pieces shared by both PageRank functions (Sec. 5.5): the rank
+ * mass on vertices without edges, a vertex's sum of neighbour contributions
+ * x(u)/deg(u), and the damped update with uniform teleport and dangling
+ * redistribution. */
+static double pr_dangling_mass(int32_t n, const int32_t *R, const double *x)
+{
+    double dangling = 0.0;
+    for (int32_t u = 0; u < n; ++u)
+        if (R[u + 1] == R[u]) dangling += x[u];
+    return dangling;
+}
+
+static double pr_neighbour_sum(const int32_t *R, const int32_t *C, const double *x, int32_t v)
+{
+    double s = 0.0;
+    for (int32_t e = R[v]; e < R[v + 1]; ++e) {
+        int32_t u = C[e];
+        s += x[u] / (double)(R[u + 1] - R[u]);
+    }
+    return s;
+}
+
+static double pr_update(double damping, double N, double s, double dangling)
+{
+    return (1.0 - damping) / N + damping * (s + dangling / N);
+}
+
 /*
  * Power iteration (Sec. 5.5: start every vertex with a value and update from
  * neighbours until convergence), in FP64:
@@ -251,17 +278,8 @@ OR_EXPORT int32_t or_pagerank(int32_t n, const int32_t *R, const int32_t *C, dou
     int32_t k = 0;
     double l1 = 0.0;
     while (k < max_iter) {
-        double dangling = 0.0;
-        for (int32_t u = 0; u < n; ++u)
-            if (R[u + 1] == R[u]) dangling += x[u];
-        for (int32_t v = 0; v < n; ++v) {
-            double s = 0.0;
-            for (int32_t e = R[v]; e < R[v + 1]; ++e) {
-                int32_t u = C[e];
-                s += x[u] / (double)(R[u + 1] - R[u]);
-            }
-            y[v] = (1.0 - damping) / N + damping * (s + dangling / N);
-        }
+        const double dangling = pr_dangling_mass(n, R, x);
+        for (int32_t v = 0; v < n; ++v) y[v] = pr_update(damping, N, pr_neighbour_sum(R, C, x, v), dangling);
         l1 = 0.0;
         for (int32_t v = 0; v < n; ++v) {
             l1 += fabs(y[v] - x[v]);
@@ -271,6 +289,63 @@ OR_EXPORT int32_t or_pagerank(int32_t n, const int32_t *R, const int32_t *C, dou
         if (tol > 0.0 && l1 < tol) break;
     }
     free(y);
+    if (iters) *iters = k;
+    if (last_l1) *last_l1 = l1;
+    return 0;
+}
+
+/*
+ * PageRank with per-vertex convergence filtering (Sec. 5.5): the frontier
+ * starts with every vertex; each iteration recomputes the rank of the
+ * frontier's vertices from the current ranks of all vertices (those outside
+ * the frontier keep their last value), then the filter keeps in the frontier
+ * only the vertices whose rank changed by at least `vertex_tol`.  Stops when
+ * the frontier is empty or after max_iter iterations.  An approximation: a
+ * vertex leaves the frontier with a residual change below vertex_tol.
+ * `active` (n bytes, may be NULL) receives the final frontier membership;
+ * `last_l1` the summed change of the last iteration.
+ */
+OR_EXPORT int32_t or_pagerank_filtered(int32_t n, const int32_t *R, const int32_t *C, double damping,
+                                       double vertex_tol, int32_t max_iter, double *x, int32_t *iters,
+                                       double *last_l1, uint8_t *active_out)
+{
+    if (n <= 0 || max_iter < 0 || vertex_tol < 0.0 || !(damping > 0.0 && damping < 1.0)) return -1;
+    double *y = (double *)malloc((size_t)n * sizeof(double));
+    uint8_t *active = (uint8_t *)malloc((size_t)n);
+    if (!y || !active) {
+        free(y);
+        free(active);
+        return -1;
+    }
+    const double N = (double)n;
+    int32_t in_frontier = n;
+    for (int32_t v = 0; v < n; ++v) {
+        x[v] = 1.0 / N;
+        active[v] = 1;
+    }
+    int32_t k = 0;
+    double l1 = 0.0;
+    while (k < max_iter && in_frontier > 0) {
+        /* advance: new ranks of the frontier, from the ranks of this iterate */
+        const double dangling = pr_dangling_mass(n, R, x);
+        for (int32_t v = 0; v < n; ++v)
+            if (active[v]) y[v] = pr_update(damping, N, pr_neighbour_sum(R, C, x, v), dangling);
+        /* filter: drop the vertices that moved less than vertex_tol */
+        l1 = 0.0;
+        in_frontier = 0;
+        for (int32_t v = 0; v < n; ++v) {
+            if (!active[v]) continue;
+            double dx = fabs(y[v] - x[v]);
+            l1 += dx;
+            x[v] = y[v];
+            if (dx >= vertex_tol) ++in_frontier;
+            else active[v] = 0;
+        }
+        ++k;
+    }
+    if (active_out) memcpy(active_out, active, (size_t)n);
+    free(y);
+    free(active);
     if (iters) *iters = k;
     if (last_l1) *last_l1 = l1;
     return 0;

@@ -38,6 +38,12 @@ MUTANTS = [
      "if (a < b) label[a] = b;\n            else if (b < a) label[b] = a;"),
     ("cc_no_final_find", "label[v] = uf_find(label, v);\n        if", "(void)0;\n        if"),
     ("pr_drops_dangling", "damping * (s + dangling / N)", "damping * (s)"),
+    ("prf_never_filters", "if (dx >= vertex_tol) ++in_frontier;\n            else active[v] = 0;",
+     "++in_frontier;"),
+    ("prf_strict_threshold", "if (dx >= vertex_tol) ++in_frontier;", "if (dx > vertex_tol) ++in_frontier;"),
+    ("prf_frozen_keep_old_value", "x[v] = y[v];\n            if (dx >= vertex_tol) ++in_frontier;\n            else active[v] = 0;",
+     "if (dx >= vertex_tol) { ++in_frontier; x[v] = y[v]; }\n            else active[v] = 0;"),
+    ("prf_gauss_seidel", "if (active[v]) y[v] = pr_update(", "if (active[v]) x[v] = y[v] = pr_update("),
     ("pr_teleport_not_divided", "(1.0 - damping) / N + damping", "(1.0 - damping) + damping"),
     ("pr_divides_by_own_degree", "s += x[u] / (double)(R[u + 1] - R[u]);",
      "s += x[u] / (double)(R[v + 1] - R[v]);"),
@@ -60,6 +66,7 @@ def _all_pins(O):
     pins.pin_closed_forms(O)
     pins.pin_scipy(O)
     pins.pin_invariants(O)
+    pins.pin_pagerank_filtered(O)
 
 
 @pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])

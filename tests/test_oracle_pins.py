@@ -217,6 +217,95 @@ def test_invariants_rmat(orc):
     pin_invariants(orc)
 
 
+# ------------------------------- PageRank with convergence filtering ----
+def _star_iso_classes(k, n_iso, d, eps, max_iter):
+    """Filtered PageRank on a star K_{1,k} plus n_iso isolated vertices,
+    reduced by symmetry to three classes (centre, leaves, isolated): every
+    member of a class has the same value and leaves the frontier in the same
+    iteration.  Returns (values, iterations, last change, still active, the
+    smallest distance between a change and eps over all decisions)."""
+    N = 1 + k + n_iso
+    val = {"c": 1.0 / N, "l": 1.0 / N, "i": 1.0 / N}
+    cnt = {"c": 1, "l": k, "i": n_iso}
+    act = {"c": True, "l": True, "i": n_iso > 0}
+    if n_iso == 0:
+        del val["i"], cnt["i"], act["i"]
+    it, l1, margin = 0, 0.0, np.inf
+    while it < max_iter and any(act.values()):
+        D = n_iso * val.get("i", 0.0)
+        new = {"c": (1 - d) / N + d * (k * val["l"] + D / N),
+               "l": (1 - d) / N + d * (val["c"] / k + D / N),
+               "i": (1 - d) / N + d * (D / N)}
+        l1 = 0.0
+        for cl in val:
+            if act[cl]:
+                dx = abs(new[cl] - val[cl])
+                l1 += cnt[cl] * dx
+                val[cl] = new[cl]
+                margin = min(margin, abs(dx - eps))
+                act[cl] = dx >= eps
+        it += 1
+    return val, it, l1, act, margin
+
+
+def pin_pagerank_filtered(O):
+    # tolerance 0 never shrinks the frontier: identical to plain power iteration
+    for row, col in (graphgen.rmat(10, 8, seed=3), graphgen.from_edges(7, [0, 1, 2], [1, 2, 0])):
+        for iters in (1, 6, 25):
+            x, it, l1, act = O.pagerank_filtered(row, col, 0.85, 0.0, iters)
+            xp, itp, l1p = O.pagerank(row, col, 0.85, 0.0, iters)
+            assert it == iters == itp and np.array_equal(x, xp) and l1 == l1p and act.all()
+    # a change of exactly zero stays in the frontier at tolerance 0: K_2 with
+    # d = 1/2 is at its fixed point (1/2, 1/2) from the start, exactly
+    row, col = _complete(2)
+    x, it, l1, act = O.pagerank_filtered(row, col, 0.5, 0.0, 7)
+    assert it == 7 and act.all() and l1 == 0.0 and np.all(x == 0.5)
+    x, it, l1, act = O.pagerank_filtered(row, col, 0.5, 1e-300, 7)
+    assert it == 1 and not act.any()
+    # a tolerance above any possible change: one iteration, empty frontier
+    row, col = graphgen.rmat(10, 8, seed=3)
+    x, it, l1, act = O.pagerank_filtered(row, col, 0.85, 2.0, 50)
+    x1, _, l11 = O.pagerank(row, col, 0.85, 0.0, 1)
+    assert it == 1 and not act.any() and np.array_equal(x, x1) and l1 == l11
+    # a regular graph is at its fixed point: everything leaves at once
+    row, col = _complete(9)
+    x, it, _, act = O.pagerank_filtered(row, col, 0.85, 1e-12, 50)
+    assert it == 1 and not act.any() and np.allclose(x, 1.0 / 9, atol=1e-16)
+    # star + isolated vertices against the three-class recurrence; the
+    # tolerances make the classes leave the frontier in different iterations
+    staggered = False
+    for k, n_iso in ((5, 3), (12, 0), (2, 1)):
+        g = graphgen.from_edges(1 + k + n_iso, np.zeros(k, np.int32), np.arange(1, k + 1))
+        for eps in (1e-3, 3e-5, 1e-7, 1e-10, 1e-13):
+            val, it_w, l1_w, act_w, margin = _star_iso_classes(k, n_iso, 0.85, eps, 400)
+            assert margin > 1e-6 * eps, "decision too close to eps for a robust pin"
+            x, it, l1, act = O.pagerank_filtered(g[0], g[1], 0.85, eps, 400)
+            assert it == it_w, (k, n_iso, eps, it, it_w)
+            assert abs(x[0] - val["c"]) <= 1e-15 and np.allclose(x[1:k + 1], val["l"], rtol=0, atol=1e-15)
+            if n_iso:
+                assert np.allclose(x[k + 1:], val["i"], rtol=0, atol=1e-15)
+            assert abs(l1 - l1_w) <= 1e-12 * max(l1_w, 1e-300) + 1e-18
+            assert act[0] == act_w["c"] and np.all(act[1:k + 1] == act_w["l"])
+            if n_iso:
+                assert np.all(act[k + 1:] == act_w["i"])
+            # the capped run reproduces the classes' state after fewer iterations
+            cap = max(1, it_w // 2)
+            val2, it2, _, act2, _ = _star_iso_classes(k, n_iso, 0.85, eps, cap)
+            x2, it2g, _, a2 = O.pagerank_filtered(g[0], g[1], 0.85, eps, cap)
+            assert it2g == it2 and abs(x2[0] - val2["c"]) <= 1e-15 and a2[0] == act2["c"]
+            staggered |= n_iso > 0 and len({act2["c"], act2["l"], act2["i"]}) > 1
+    assert staggered
+    # shrinking the tolerance approaches the fixed point
+    row, col = graphgen.rmat(12)
+    xs, _, _ = O.pagerank(row, col, 0.85, 1e-15, 10000)
+    errs = [np.abs(O.pagerank_filtered(row, col, 0.85, e, 10000)[0] - xs).sum() for e in (1e-6, 1e-9, 1e-13)]
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-7
+
+
+def test_pagerank_filtered(orc):
+    pin_pagerank_filtered(orc)
+
+
 def test_input_validation(orc):
     row, col = _path(5)
     with pytest.raises(ValueError):
