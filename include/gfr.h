@@ -205,6 +205,27 @@ gfr_status gfr_pagerank(gfr_ctx *ctx, gfr_graph g, float damping, double l1_tol,
                         int32_t max_iter, float *rank_out, int32_t *iters_out,
                         double *final_l1_out, gfr_stream stream);
 
+/*
+ * PageRank with per-vertex convergence filtering (Sec. 5.5, the frontier
+ * form): the frontier starts with every vertex; each iteration recomputes
+ * the rank of the frontier's vertices by the update above, from the ranks of
+ * the previous iterate (vertices outside the frontier keep their last rank),
+ * then keeps in the frontier only the vertices whose rank changed by at least
+ * vertex_tol.  Stops when the frontier is empty or after max_iter iterations
+ * (GFR_OK in both cases).  An approximation of the fixed point whose error
+ * grows with vertex_tol; vertex_tol = 0 reproduces plain power iteration.
+ * Everything is FP64, including the filter decision.
+ *   rank_out      n doubles (device or host memory)
+ *   active_out    n bytes, 1 = still in the frontier at the end; may be NULL
+ *   iters_out     iterations run; final_l1_out: summed change of the last
+ *                 iteration over the vertices it updated (host, may be NULL)
+ * GFR_E_INVALID if damping is not in (0,1), vertex_tol < 0 or max_iter < 1.
+ * Statistics: iterations, l1, vertex_updates, edges_gathered, final_frontier.
+ */
+gfr_status gfr_pagerank_filtered(gfr_ctx *ctx, gfr_graph g, double damping, double vertex_tol,
+                                 int32_t max_iter, double *rank_out, uint8_t *active_out,
+                                 int32_t *iters_out, double *final_l1_out, gfr_stream stream);
+
 /* ---------------------------------------------------------------- batching */
 /*
  * k BFS (or SSSP) solves from `sources` (host memory, k >= 1) on one graph,

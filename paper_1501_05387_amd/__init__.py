@@ -65,6 +65,8 @@ SIGNATURES = {
     "gfr_cc": (_i32, [_vp, _i64, _vp, ctypes.POINTER(_i32), _vp]),
     "gfr_pagerank": (_i32, [_vp, _i64, _f32, _f64, _i32, _vp, ctypes.POINTER(_i32),
                             ctypes.POINTER(_f64), _vp]),
+    "gfr_pagerank_filtered": (_i32, [_vp, _i64, _f64, _f64, _i32, _vp, _vp, ctypes.POINTER(_i32),
+                                     ctypes.POINTER(_f64), _vp]),
     "gfr_bfs_batch": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp]),
     "gfr_sssp_batch": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp]),
     "gfr_submit_queries": (_i32, [_vp, ctypes.POINTER(Query), _i32, ctypes.POINTER(_i64)]),
@@ -162,7 +164,8 @@ class Context:
         """(pointer, object to return) for an output of `count` elements."""
         if out is None:
             torch = _torch()
-            tdt = {np.int32: torch.int32, np.uint32: torch.int32, np.float32: torch.float32}[dtype]
+            tdt = {np.int32: torch.int32, np.uint32: torch.int32, np.float32: torch.float32,
+                   np.float64: torch.float64, np.uint8: torch.uint8}[dtype]
             t = torch.empty(count, dtype=tdt, device="cuda:%d" % self.device)
             return t.data_ptr(), t
         if isinstance(out, np.ndarray):
@@ -170,8 +173,9 @@ class Context:
                 raise ValueError("out must be a contiguous %s array of %d elements" % (np.dtype(dtype), count))
             return out.ctypes.data, out
         # torch tensor
-        if out.numel() != count or not out.is_contiguous() or out.element_size() != 4:
-            raise ValueError("out must be a contiguous 4-byte tensor of %d elements" % count)
+        size = np.dtype(dtype).itemsize
+        if out.numel() != count or not out.is_contiguous() or out.element_size() != size:
+            raise ValueError("out must be a contiguous %d-byte tensor of %d elements" % (size, count))
         return out.data_ptr(), out
 
     def set_option(self, key: str, value: float):
@@ -234,6 +238,17 @@ class Context:
         self._check(lib().gfr_pagerank(self.ptr, g.handle, float(damping), float(tol), int(max_iter), p,
                                        ctypes.byref(it), ctypes.byref(l1), self._stream()))
         return ret, it.value, l1.value
+
+    def pagerank_filtered(self, g: Graph, damping: float = 0.85, vertex_tol: float = 1e-9,
+                          max_iter: int = 1000, out=None, active=None):
+        """(FP64 ranks, final frontier bytes, iterations, last summed change)."""
+        p, ret = self._out(out, g.n, np.float64)
+        pa, act = self._out(active, g.n, np.uint8)
+        it, l1 = _i32(), _f64()
+        self._check(lib().gfr_pagerank_filtered(self.ptr, g.handle, float(damping), float(vertex_tol),
+                                                int(max_iter), p, pa, ctypes.byref(it), ctypes.byref(l1),
+                                                self._stream()))
+        return ret, act, it.value, l1.value
 
     def bfs_batch(self, g: Graph, sources, out=None):
         src = _np(sources, np.int32)

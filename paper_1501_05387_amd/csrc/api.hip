@@ -722,6 +722,35 @@ gfr_status gfr_pagerank(gfr_ctx *ctx, gfr_graph gh, float damping, double l1_tol
     });
 }
 
+gfr_status gfr_pagerank_filtered(gfr_ctx *ctx, gfr_graph gh, double damping, double vertex_tol,
+                                 int32_t max_iter, double *rank_out, uint8_t *active_out, int32_t *iters_out,
+                                 double *final_l1_out, gfr_stream stream)
+{
+    return guard(ctx, [&](Ctx &c) {
+        Graph &g = get_graph(c, gh);
+        OptScope os(c, g);
+        if (!(damping > 0.0 && damping < 1.0)) fail(GFR_E_INVALID, "pagerank_filtered: damping must be in (0,1)");
+        if (max_iter < 1) fail(GFR_E_INVALID, "pagerank_filtered: max_iter must be >= 1");
+        if (!(vertex_tol >= 0.0)) fail(GFR_E_INVALID, "pagerank_filtered: vertex_tol must be >= 0");
+        hipStream_t s = pick_stream(c, stream);
+        OutBuf o(c, rank_out, 8ull * g.n);
+        int32_t it = 0;
+        double l1 = 0.0;
+        timed_begin(c, s);
+        const uint8_t *act = run_pagerank_filtered(c, g, damping, vertex_tol, max_iter, (double *)o.dev, &it, &l1, s);
+        timed_end(c, s);
+        if (active_out) {
+            if (is_device_ptr(active_out))
+                GFR_HIP(hipMemcpyAsync(active_out, act, (size_t)g.n, hipMemcpyDeviceToDevice, s));
+            else
+                copy_to_host(c.bounce, active_out, act, (size_t)g.n, s);
+        }
+        o.finish(c, s);
+        if (iters_out) *iters_out = it;
+        if (final_l1_out) *final_l1_out = l1;
+    });
+}
+
 gfr_status gfr_bfs_batch(gfr_ctx *ctx, gfr_graph gh, const int32_t *sources, int32_t k,
                          int32_t *depth_out, gfr_stream stream)
 {

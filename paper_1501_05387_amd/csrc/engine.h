@@ -271,6 +271,10 @@ uint32_t sssp_auto_delta(const Graph &g, double factor);
 void run_cc(Ctx &c, Graph &g, int32_t *label, int32_t *ncomp, hipStream_t s);
 void run_pagerank(Ctx &c, Graph &g, float damping, double tol, int32_t max_iter, float *rank,
                   int32_t *iters, double *l1, hipStream_t s);
+// Per-vertex convergence filtering; returns the final frontier membership
+// (n bytes in the context's arena, valid until the next solver call).
+const uint8_t *run_pagerank_filtered(Ctx &c, Graph &g, double damping, double vertex_tol, int32_t max_iter,
+                                     double *rank, int32_t *iters, double *l1, hipStream_t s);
 void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipStream_t s);
 void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t *depth,
                    hipStream_t s);
