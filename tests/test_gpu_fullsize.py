@@ -10,7 +10,9 @@ size for every output the oracle does not recompute:
   CC against the oracle.
 * R-MAT s23: BC from 4 sources against the oracle; BC from 32 sources
   against the identity sum_v BC(v) = sum_s sum_t (d(s,t) - 1); PageRank
-  against the FP64 oracle run for the GPU's iteration count.
+  against the FP64 oracle run for the GPU's iteration count; filtered
+  PageRank against the oracle of the same method (iterations and final
+  frontier exact).
 """
 from __future__ import annotations
 
@@ -136,4 +138,21 @@ def test_rmat23_pagerank(ctx, rmat23):
     _say("rmat23 pagerank iterations", it, "L1 vs FP64 oracle", err)
     assert err <= 1e-6
     assert abs(float(rank.sum()) - 1.0) <= 1e-5
+    g.free()
+
+
+def test_rmat23_pagerank_filtered(ctx, rmat23):
+    row, col = rmat23
+    n = row.size - 1
+    g = ctx.graph_load_csr(row, col)
+    eps = 1e-4 / n
+    _say("rmat23 pagerank_filtered, vertex_tol 1e-4/N")
+    x, act, it, l1 = ctx.pagerank_filtered(g, 0.85, eps, 1000)
+    xo, ito, l1o, acto = oracle.pagerank_filtered(row, col, 0.85, eps, 1000)
+    assert it == ito
+    assert np.array_equal(act.cpu().numpy().astype(bool), acto)
+    err = float(np.abs(x.cpu().numpy() - xo).sum())
+    _say("rmat23 pagerank_filtered iterations", it, "L1 vs oracle", err)
+    assert err <= 1e-11
+    assert abs(l1 - l1o) <= 1e-12 + 1e-9 * l1o
     g.free()
