@@ -92,6 +92,12 @@ const char *gfr_last_error(const gfr_ctx *ctx);
  *   "msbfs.alpha"     batched BFS: pull when the frontier's edges exceed m / alpha
  *   "batch.delta"     batched SSSP bucket width; 0 = "batch.delta_factor" times the
  *                     mean edge weight, where factor 0 (default) = a single bucket
+ *   "batch.pull_alpha" batched SSSP: relax by a pull sweep (one owner-side minimum per
+ *                     vertex and query) when the frontier's edges exceed m / alpha;
+ *                     0 (default) = always push
+ *   "bc.direction"    BC forward discovery (Sec. 5.3 with the push/pull choice of
+ *                     Sec. 4.5): 0 auto, 1 push only, 2 pull only; results do not change
+ *   "bc.alpha", "bc.beta"  the same ratios as bfs.alpha / bfs.beta for BC's levels
  *   "serve.max_batch" largest number of queries the serving runtime runs together (1..64)
  *   "serve.hipgraph"  1 (default): serving sessions replay their rounds of steps from
  *                     hipGraphs captured once per session; 0: plain launches

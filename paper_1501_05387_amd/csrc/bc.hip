@@ -1,8 +1,12 @@
 // bc.hip -- betweenness centrality from a set of sources, Brandes'
 // two-pass formulation as the paper maps it (Sec. 5.3):
 //   forward   an advance identical to BFS discovers level L+1 from level L,
-//             then a compute step gathers sigma(v) = sum of sigma(u) over the
-//             neighbours u one level up (shortest-path counts, FP64);
+//             pushing from the level's lists or, when the level is large,
+//             pulling: every unvisited vertex scans its own list for a vertex
+//             of level L (the direction choice of Sec. 4.5, which the paper
+//             names as the missing piece of its BC); then a compute step
+//             gathers sigma(v) = sum of sigma(u) over the neighbours u one
+//             level up (shortest-path counts, FP64);
 //   backward  walks the levels in reverse and gathers
 //             delta(v) = sigma(v) * sum over neighbours w one level down of
 //                        (1 + delta(w)) / sigma(w),
@@ -61,10 +65,48 @@ __global__ __launch_bounds__(GFR_BLOCK) void bc_discover(BcArgs a, FrontierQ qin
     }
 }
 
-// compaction of one BFS level into its slice of the BFS order (vertex order)
+// pull discovery of level L+1: every unvisited vertex (lane = vertex) scans
+// its list four neighbours at a time until one is in the level-L bitmap
+__global__ __launch_bounds__(GFR_BLOCK) void bc_pull_discover(BcArgs a, int32_t n, const uint32_t *fb, int32_t L,
+                                                              uint8_t *mark)
+{
+    const uint32_t waves = gridDim.x * GFR_WAVES;
+    const int lane = lane_id();
+    for (uint32_t grp = blockIdx.x * GFR_WAVES + threadIdx.x / 64; grp * 64u < (uint32_t)n; grp += waves) {
+        const int32_t v = (int32_t)(grp * 64u) + lane;
+        const uint32_t visw = a.vis[grp * 2u + (uint32_t)(lane >> 5)];
+        bool found = false;
+        if (v < n && !(visw & (1u << (v & 31)))) {
+            int32_t e = a.R[v];
+            const int32_t re = a.R[v + 1];
+            while (e < re) {
+                const int32_t k = min(4, re - e);
+                int32_t u[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) u[j] = a.C[j < k ? e + j : e];
+                uint32_t hit = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) hit |= (j < k) ? (fb[u[j] >> 5] >> (u[j] & 31)) & 1u : 0u;
+                if (hit) {
+                    found = true;
+                    break;
+                }
+                e += 4;
+            }
+        }
+        if (found) {
+            a.depth[v] = L + 1;
+            mark[v] = 1;
+        }
+    }
+}
+
+// compaction of one BFS level into its slice of the BFS order (vertex order);
+// also writes the level's bitmap for a following pull discovery
 struct BcMarks {
     uint8_t *mark;
     uint32_t *vis;
+    uint32_t *fb;
     unsigned long long *out;   // packed (entries << 32 | edges) of the new level
     uint32_t *parity;
     __device__ bool skip() const { return false; }
@@ -75,6 +117,7 @@ struct BcMarks {
             clear_marks(mark + 32ull * w);
             vis[w] |= m;
         }
+        fb[w] = m;
         return m;
     }
     __device__ void partial(uint32_t) {}
@@ -87,12 +130,14 @@ struct BcMarks {
     }
 };
 
-__global__ void bc_source_init(BcArgs a, int32_t src, FrontierQ q0, double *sigma, unsigned long long *ctr0)
+__global__ void bc_source_init(BcArgs a, int32_t src, FrontierQ q0, double *sigma, unsigned long long *ctr0,
+                               uint32_t *fb)
 {
     const int32_t rs = a.R[src], deg = a.R[src + 1] - rs;
     if (threadIdx.x == 0) {
         a.depth[src] = 0;
         a.vis[src >> 5] |= 1u << (src & 31);
+        fb[src >> 5] |= 1u << (src & 31);
         sigma[src] = 1.0;
         q0.v[0] = src;
         q0.off[0] = 0;
@@ -160,7 +205,8 @@ void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipS
     const size_t nlev = (size_t)n + 2;
     c.arena.reserve(al256(4ull * n) + al256(4ull * nwords) + al256(32ull * nwords) + 3 * al256(8ull * n) + 3 * al256(4ull * n) +
                     al256(4 * nparts) + 2 * al256(8 * nch) + al256(8 * nlev) +
-                    al256(16ull * (uint64_t)compact_geom(nwords, c.num_cu).blocks) + al256(256));
+                    al256(16ull * (uint64_t)compact_geom(nwords, c.num_cu).blocks) + al256(256) +
+                    al256(4ull * nwords));
     BcArgs a;
     a.R = g.R.as<int32_t>();
     a.C = g.C.as<int32_t>();
@@ -180,6 +226,7 @@ void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipS
     uint8_t *mark = c.arena.take<uint8_t>(32ull * nwords);
     unsigned long long *status = c.arena.take<unsigned long long>(2ull * cg.blocks);
     uint32_t *cw = c.arena.take<uint32_t>(64);   // [0] compaction parity, [1] look-back error
+    uint32_t *fb = c.arena.take<uint32_t>(nwords);
     fill_u32(mark, 0u, 8ull * nwords, s);
     fill_u32(status, 0u, 4ull * cg.blocks, s);
     fill_u32(cw, 0u, 64, s);
@@ -189,35 +236,53 @@ void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipS
         return FrontierQ{order + l.start, off + l.start, row + l.start, part + l.pbase};
     };
     std::vector<Level> lv;
-    double levels_total = 0;
+    double levels_total = 0, push_levels = 0, pull_levels = 0;
+    const int force = c.opt.bc_direction;
+    const double alpha = c.opt.bc_alpha, beta = c.opt.bc_beta;
     for (int32_t si = 0; si < k; ++si) {
         const int32_t src = sources[si];
         fill_u32(a.depth, 0xFFFFFFFFu, n, s);
         fill_u32(a.vis, 0u, nwords, s);
+        fill_u32(fb, 0u, nwords, s);
         lv.clear();
         lv.push_back(Level{0, 1, 0, 0});
-        hipLaunchKernelGGL(bc_source_init, dim3(1), dim3(GFR_BLOCK), 0, s, a, src, qat(lv[0]), sigma, ctr);
+        hipLaunchKernelGGL(bc_source_init, dim3(1), dim3(GFR_BLOCK), 0, s, a, src, qat(lv[0]), sigma, ctr, fb);
         GFR_LAUNCH_CHECK();
         GFR_HIP(hipMemcpyAsync(c.pinned, ctr, 8, hipMemcpyDeviceToHost, s));
         GFR_HIP(hipStreamSynchronize(s));
         lv[0].mf = c.pinned[0];
+        // unvisited vertices and their edges, for the direction choice
+        double mu = (double)g.m - (double)lv[0].mf, prev_nf = 0.0;
+        bool pull = false;
         // forward
         for (;;) {
             const Level cur = lv.back();
             const int32_t L = (int32_t)lv.size() - 1;
             if (cur.mf == 0) break;
+            if (force == 1) pull = false;
+            else if (force == 2) pull = true;
+            else if (!pull) pull = (double)cur.mf > mu / alpha && (double)cur.nf > prev_nf;
+            else pull = !((double)cur.nf < (double)n / beta && (double)cur.nf < prev_nf);
+            prev_nf = (double)cur.nf;
             Level nx{cur.start + cur.nf, 0, 0, cur.pbase + (cur.mf + GATHER_CH - 1) / GATHER_CH + 1};
             unsigned long long *cn = ctr + lv.size();
-            hipLaunchKernelGGL(bc_discover<GATHER_CH>, dim3(G), dim3(GFR_BLOCK), 0, s, a, qat(cur), cur.nf, cur.mf,
-                               L, mark);
+            if (pull) {
+                hipLaunchKernelGGL(bc_pull_discover, dim3(G), dim3(GFR_BLOCK), 0, s, a, n, fb, L, mark);
+                pull_levels += 1;
+            } else {
+                hipLaunchKernelGGL(bc_discover<GATHER_CH>, dim3(G), dim3(GFR_BLOCK), 0, s, a, qat(cur), cur.nf,
+                                   cur.mf, L, mark);
+                push_levels += 1;
+            }
             hipLaunchKernelGGL(compact_kernel<BcMarks>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R, n, nwords, cg.wpt,
-                               BcMarks{mark, a.vis, cn, cw}, qat(nx), GATHER_CH, status, cw, cw + 1);
+                               BcMarks{mark, a.vis, fb, cn, cw}, qat(nx), GATHER_CH, status, cw, cw + 1);
             GFR_LAUNCH_CHECK();
             GFR_HIP(hipMemcpyAsync(c.pinned, cn, 8, hipMemcpyDeviceToHost, s));
             GFR_HIP(hipStreamSynchronize(s));
             nx.mf = c.pinned[0];
             nx.nf = c.pinned[1];
             if (nx.nf == 0) break;
+            mu -= (double)nx.mf;
             lv.push_back(nx);
             const uint32_t *cw = (const uint32_t *)cn;
             hipLaunchKernelGGL((gather_chunks<GATHER_CH, SigmaOp, SigmaFin>), dim3(G), dim3(GFR_BLOCK), 0, s,
@@ -252,6 +317,8 @@ void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipS
     GFR_HIP(hipStreamSynchronize(s));
     if (c.pinned[0]) fail(GFR_E_DEVICE, "bc: frontier compaction look-back timed out");
     c.stats.v["levels"] = levels_total;
+    c.stats.v["push_levels"] = push_levels;
+    c.stats.v["pull_levels"] = pull_levels;
 }
 
 }  // namespace gfr

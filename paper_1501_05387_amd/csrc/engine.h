@@ -127,6 +127,9 @@ struct Options {
     int serve_graphs = 1;       // serving sessions replay their rounds from captured hipGraphs
     int batch_min_bfs = 8;      // fewer sources than this: sequential single-source BFS
     int batch_min_sssp = 24;    // fewer queries than this: sequential single-source SSSP
+    int bc_direction = 0;       // BC forward discovery: 0 auto, 1 push, 2 pull
+    double bc_alpha = 15.0;     // push -> pull when level edges > unvisited edges / alpha (growing)
+    double bc_beta = 18.0;      // pull -> push when level size < n / beta (shrinking)
 };
 
 // Options from a tuning file: context-wide values and per-graph-class values.

@@ -220,18 +220,42 @@ def test_pagerank_max_iter(ctx):
 
 # --------------------------------------------------------------------- BC
 @pytest.mark.parametrize("name", ["rmat12", "grid96", "star5000", "path3000", "forest"])
-def test_bc_matches_oracle(ctx, name):
+@pytest.mark.parametrize("direction", [0, 1, 2])
+def test_bc_matches_oracle(ctx, name, direction):
     row, col, _ = graph(name)
     n = row.size - 1
     src = np.array(_sources(row, col, 4)[:6], np.int32)
     g = _load(ctx, row, col)
-    _say("bc", name, "sources", src.tolist())
-    got = _host(ctx.bc(g, src)).astype(np.float64)
+    _say("bc", name, "direction", direction, "sources", src.tolist())
+    ctx.set_option("bc.direction", direction)
+    try:
+        got = _host(ctx.bc(g, src)).astype(np.float64)
+    finally:
+        ctx.set_option("bc.direction", 0)
     want = oracle.bc(row, col, src)
     nz = want != 0
     rel = np.abs(got[nz] - want[nz]) / np.abs(want[nz])
     assert np.all(got[~nz] == 0)
     assert rel.size == 0 or rel.max() <= 1e-5, rel.max()
+    g.free()
+
+
+def test_bc_directions_agree_bitwise(ctx):
+    """The forward discovery direction changes neither a level nor the order of
+    any sum, so push-only, pull-only and automatic runs agree bit for bit."""
+    row, col, _ = graph("rmat16")
+    src = np.array(_sources(row, col, 4)[:5], np.int32)
+    g = _load(ctx, row, col)
+    out = {}
+    try:
+        for d in (1, 2, 0):
+            ctx.set_option("bc.direction", d)
+            out[d] = _host(ctx.bc(g, src)).copy()
+            if d == 0:
+                assert ctx.stat("pull_levels") > 0 and ctx.stat("push_levels") > 0
+    finally:
+        ctx.set_option("bc.direction", 0)
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
     g.free()
 
 
