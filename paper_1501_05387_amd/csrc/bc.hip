@@ -12,7 +12,11 @@
 //                        (1 + delta(w)) / sigma(w),
 //             stored in FP32; bc(v) accumulates delta(v) over sources.
 // Both gathers are pull-style: no floating-point atomics, fixed order per
-// list (see gather.h).  Every level is kept as a contiguous slice of one BFS
+// list (see gather.h).  Depths are kept as one byte per vertex, depth mod
+// 128 (0xFF = unvisited): the neighbours a gather inspects are within one
+// level of the gathering vertex (or not yet discovered), so the byte
+// identifies the level exactly, and the array is a quarter of an int32 one,
+// which keeps the random probes of the gathers in cache.  Every level is kept as a contiguous slice of one BFS
 // order array so the backward pass can revisit it.
 #include <vector>
 
@@ -22,15 +26,20 @@
 
 namespace gfr {
 
+constexpr uint8_t BC_UNSEEN = 0xFF;   // never a level code
+
+__host__ __device__ __forceinline__ uint8_t level_code(int32_t L) { return (uint8_t)(L & 127); }
+static_assert(BC_UNSEEN > 127, "unvisited must differ from every level code");
+
 struct BcArgs {
     const int32_t *R;
     const int32_t *C;
-    int32_t *depth;
+    uint8_t *dc;     // depth code per vertex
     uint32_t *vis;
 };
 
 // push advance of one level (load-balanced edge chunks): an unvisited
-// neighbour gets its depth and a mark byte (plain stores; duplicates write
+// neighbour gets its depth code and a mark byte (plain stores; duplicates write
 // the same values and collapse in the compaction)
 template <int CH>
 __global__ __launch_bounds__(GFR_BLOCK) void bc_discover(BcArgs a, FrontierQ qin, uint32_t nf, uint32_t mf,
@@ -57,7 +66,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bc_discover(BcArgs a, FrontierQ qin
                 const int i = upper_index(s_off, 0, cnt - 1, e);
                 const int32_t v = a.C[s_row[i] + (int32_t)(e - s_off[i])];
                 if (!((a.vis[v >> 5] >> (v & 31)) & 1u) && !mark[v]) {
-                    a.depth[v] = L + 1;
+                    a.dc[v] = level_code(L + 1);
                     mark[v] = 1;
                 }
             }
@@ -95,7 +104,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bc_pull_discover(BcArgs a, int32_t 
             }
         }
         if (found) {
-            a.depth[v] = L + 1;
+            a.dc[v] = level_code(L + 1);
             mark[v] = 1;
         }
     }
@@ -135,7 +144,7 @@ __global__ void bc_source_init(BcArgs a, int32_t src, FrontierQ q0, double *sigm
 {
     const int32_t rs = a.R[src], deg = a.R[src + 1] - rs;
     if (threadIdx.x == 0) {
-        a.depth[src] = 0;
+        a.dc[src] = level_code(0);
         a.vis[src >> 5] |= 1u << (src & 31);
         fb[src >> 5] |= 1u << (src & 31);
         sigma[src] = 1.0;
@@ -148,10 +157,10 @@ __global__ void bc_source_init(BcArgs a, int32_t src, FrontierQ q0, double *sigm
 }
 
 struct SigmaOp {
-    const int32_t *depth;
+    const uint8_t *dc;
     const double *sigma;
-    int32_t L;   // level of the predecessors
-    __device__ double operator()(int32_t u, int32_t) const { return depth[u] == L ? sigma[u] : 0.0; }
+    uint8_t code;   // level of the predecessors
+    __device__ double operator()(int32_t u, int32_t) const { return dc[u] == code ? sigma[u] : 0.0; }
 };
 
 struct SigmaFin {
@@ -160,10 +169,10 @@ struct SigmaFin {
 };
 
 struct DeltaOp {
-    const int32_t *depth;
+    const uint8_t *dc;
     const double *coef;
-    int32_t L;   // level of the successors
-    __device__ double operator()(int32_t w, int32_t) const { return depth[w] == L ? coef[w] : 0.0; }
+    uint8_t code;   // level of the successors
+    __device__ double operator()(int32_t w, int32_t) const { return dc[w] == code ? coef[w] : 0.0; }
 };
 
 struct DeltaFin {
@@ -210,7 +219,7 @@ void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipS
     BcArgs a;
     a.R = g.R.as<int32_t>();
     a.C = g.C.as<int32_t>();
-    a.depth = c.arena.take<int32_t>(n);
+    a.dc = c.arena.take<uint8_t>(4ull * ((n + 3) / 4));
     a.vis = c.arena.take<uint32_t>(nwords);
     double *sigma = c.arena.take<double>(n);
     double *coef = c.arena.take<double>(n);
@@ -241,7 +250,7 @@ void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipS
     const double alpha = c.opt.bc_alpha, beta = c.opt.bc_beta;
     for (int32_t si = 0; si < k; ++si) {
         const int32_t src = sources[si];
-        fill_u32(a.depth, 0xFFFFFFFFu, n, s);
+        fill_u32(a.dc, 0xFFFFFFFFu, (n + 3) / 4, s);   // BC_UNSEEN
         fill_u32(a.vis, 0u, nwords, s);
         fill_u32(fb, 0u, nwords, s);
         lv.clear();
@@ -286,7 +295,7 @@ void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipS
             lv.push_back(nx);
             const uint32_t *cw = (const uint32_t *)cn;
             hipLaunchKernelGGL((gather_chunks<GATHER_CH, SigmaOp, SigmaFin>), dim3(G), dim3(GFR_BLOCK), 0, s,
-                               qat(nx), cw + 1, cw, a.C, SigmaOp{a.depth, sigma, L}, SigmaFin{sigma}, gs,
+                               qat(nx), cw + 1, cw, a.C, SigmaOp{a.dc, sigma, level_code(L)}, SigmaFin{sigma}, gs,
                                c.zero_word.as<uint32_t>());
             hipLaunchKernelGGL((gather_fixup<GATHER_CH, SigmaFin>), dim3(G), dim3(GFR_BLOCK), 0, s, qat(nx), cw + 1,
                                cw, SigmaFin{sigma}, gs, c.zero_word.as<uint32_t>());
@@ -304,7 +313,7 @@ void run_bc(Ctx &c, Graph &g, const int32_t *sources, int32_t k, float *bc, hipS
             const Level &l = lv[L];
             const uint32_t *cw = (const uint32_t *)(ctr + L);
             hipLaunchKernelGGL((gather_chunks<GATHER_CH, DeltaOp, DeltaFin>), dim3(G), dim3(GFR_BLOCK), 0, s, qat(l),
-                               cw + 1, cw, a.C, DeltaOp{a.depth, coef, L + 1}, DeltaFin{sigma, coef, acc}, gs,
+                               cw + 1, cw, a.C, DeltaOp{a.dc, coef, level_code(L + 1)}, DeltaFin{sigma, coef, acc}, gs,
                                c.zero_word.as<uint32_t>());
             hipLaunchKernelGGL((gather_fixup<GATHER_CH, DeltaFin>), dim3(G), dim3(GFR_BLOCK), 0, s, qat(l), cw + 1, cw,
                                DeltaFin{sigma, coef, acc}, gs, c.zero_word.as<uint32_t>());

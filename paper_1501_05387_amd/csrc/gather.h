@@ -56,11 +56,30 @@ __global__ __launch_bounds__(GFR_BLOCK) void gather_chunks(FrontierQ q, const ui
         }
         if (threadIdx.x == 0) s_off[cnt] = (t + 1 < (int)nf) ? q.off[t + 1] : mf;
         __syncthreads();
-        for (uint32_t k = threadIdx.x; k < e1 - e0; k += GFR_BLOCK) {
-            const uint32_t e = e0 + k;
-            const int i = upper_index(s_off, 0, cnt - 1, e);
-            const int32_t u = C[s_row[i] + (int32_t)(e - s_off[i])];
-            s_val[k] = op(u, s_v[i]);
+        {
+            // every lane takes CH / GFR_BLOCK edges and issues all their column
+            // loads, then all their value loads, before storing any value: the
+            // loads of one lane overlap instead of waiting one after another.
+            // Lanes past the chunk's end repeat its last edge (in bounds) and
+            // store nothing.
+            constexpr int EPT = CH / GFR_BLOCK;
+            static_assert(CH % GFR_BLOCK == 0, "chunk must be a multiple of the work-group size");
+            int ii[EPT];
+            int32_t u[EPT];
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) {
+                const uint32_t e = min(e0 + (uint32_t)(j * GFR_BLOCK) + threadIdx.x, e1 - 1u);
+                ii[j] = upper_index(s_off, 0, cnt - 1, e);
+                u[j] = C[s_row[ii[j]] + (int32_t)(e - s_off[ii[j]])];
+            }
+            double val[EPT];
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) val[j] = op(u[j], s_v[ii[j]]);
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) {
+                const uint32_t k = (uint32_t)(j * GFR_BLOCK) + threadIdx.x;
+                if (k < e1 - e0) s_val[k] = val[j];
+            }
         }
         __syncthreads();
         // short segments: one lane each; long ones are queued for the waves
