@@ -13,6 +13,8 @@ mesh-like rgg_n_24 / roadnet_CA):
   no noise and no permutation, symmetrised, self loops and duplicates removed.
 * Grid: side x side lattice, each lattice edge dropped with p = 0.03, plus
   0.1 % (of the lattice edge count) uniformly random long edges.
+* Bipartite R-MAT (for the bipartite rankings): the same draws, edge (u, v)
+  joining left vertex u to right vertex 2^scale + v.
 * Weights: uniform integers in [1, maxw], a function of the unordered pair, so
   the weighted graph stays symmetric (the paper draws SSSP weights in 1..64).
 """
@@ -53,6 +55,8 @@ def _L():
                                        ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double)
         lib.gg_rmat.restype = vp
         lib.gg_rmat.argtypes = [i32, i32, f64, f64, f64, u64]
+        lib.gg_bipartite_rmat.restype = vp
+        lib.gg_bipartite_rmat.argtypes = [i32, i32, f64, f64, f64, u64]
         lib.gg_grid.restype = vp
         lib.gg_grid.argtypes = [i32, f64, i64, u64]
         lib.gg_from_edges.restype = vp
@@ -98,6 +102,13 @@ def rmat(scale: int, edge_factor: int = 16, abcd=RMAT_ABCD, seed: int = SEED_GRA
     """R-MAT graph as symmetric simple CSR ``(row_offsets int32[n+1], col int32[m])``."""
     a, b, c, _d = abcd
     return _take(_L().gg_rmat(scale, edge_factor, a, b, c, seed))
+
+
+def bipartite_rmat(scale: int, edge_factor: int = 16, abcd=RMAT_ABCD, seed: int = SEED_GRAPH):
+    """Bipartite R-MAT: left vertices [0, 2^scale), right [2^scale, 2^(scale+1)); symmetric
+    simple CSR whose every edge joins the two sides."""
+    a, b, c, _d = abcd
+    return _take(_L().gg_bipartite_rmat(scale, edge_factor, a, b, c, seed))
 
 
 def grid(side: int = 4096, p_drop: float = 0.03, long_frac: float = 0.001,

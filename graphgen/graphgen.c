@@ -171,6 +171,30 @@ static gg_graph *build_csr(int32_t n, int64_t ne, const int32_t *eu, const int32
  * otherwise, setting bit (scale-1-l) of u and/or v.  No noise, no vertex
  * permutation: vertex 0 is the densest corner.
  */
+/* endpoints of R-MAT edge i: one quadrant draw per level, counter (i, level) */
+static void rmat_edge(int32_t scale, double a, double b, double c, uint64_t s0, int64_t i, int32_t *pu,
+                      int32_t *pv)
+{
+    const double ab = a + b, abc = a + b + c;
+    uint64_t hi = gg_mix(s0 ^ (uint64_t)i);
+    int32_t u = 0, v = 0;
+    for (int32_t l = 0; l < scale; ++l) {
+        double r = gg_unit(gg_mix(hi ^ ((uint64_t)(l + 1) * 0xD1B54A32D192ED03ull)));
+        int32_t bit = (int32_t)1 << (scale - 1 - l);
+        if (r < a) {
+        } else if (r < ab) {
+            v |= bit;
+        } else if (r < abc) {
+            u |= bit;
+        } else {
+            u |= bit;
+            v |= bit;
+        }
+    }
+    *pu = u;
+    *pv = v;
+}
+
 GG_EXPORT gg_graph *gg_rmat(int32_t scale, int32_t edge_factor, double a, double b, double c,
                             uint64_t seed)
 {
@@ -180,29 +204,37 @@ GG_EXPORT gg_graph *gg_rmat(int32_t scale, int32_t edge_factor, double a, double
     int32_t *eu = (int32_t *)malloc((size_t)ne * sizeof(int32_t));
     int32_t *ev = (int32_t *)malloc((size_t)ne * sizeof(int32_t));
     if (!eu || !ev) { free(eu); free(ev); return NULL; }
-    const double ab = a + b, abc = a + b + c;
+    const uint64_t s0 = gg_mix(seed);
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < ne; ++i) rmat_edge(scale, a, b, c, s0, i, eu + i, ev + i);
+    gg_graph *g = build_csr(n, ne, eu, ev);
+    free(eu);
+    free(ev);
+    return g;
+}
+
+/*
+ * Bipartite R-MAT: 2^scale vertices on each side; R-MAT edge (u, v) joins
+ * left vertex u to right vertex 2^scale + v (a "who follows whom" graph:
+ * users on the left, the accounts they follow on the right).  Symmetric
+ * simple CSR over n = 2^(scale+1) vertices; duplicates removed.
+ */
+GG_EXPORT gg_graph *gg_bipartite_rmat(int32_t scale, int32_t edge_factor, double a, double b, double c,
+                                      uint64_t seed)
+{
+    if (scale < 1 || scale > 29 || edge_factor < 1) return NULL;
+    const int32_t half = (int32_t)1 << scale;
+    const int64_t ne = (int64_t)edge_factor << scale;
+    int32_t *eu = (int32_t *)malloc((size_t)ne * sizeof(int32_t));
+    int32_t *ev = (int32_t *)malloc((size_t)ne * sizeof(int32_t));
+    if (!eu || !ev) { free(eu); free(ev); return NULL; }
     const uint64_t s0 = gg_mix(seed);
     #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < ne; ++i) {
-        uint64_t hi = gg_mix(s0 ^ (uint64_t)i);
-        int32_t u = 0, v = 0;
-        for (int32_t l = 0; l < scale; ++l) {
-            double r = gg_unit(gg_mix(hi ^ ((uint64_t)(l + 1) * 0xD1B54A32D192ED03ull)));
-            int32_t bit = (int32_t)1 << (scale - 1 - l);
-            if (r < a) {
-            } else if (r < ab) {
-                v |= bit;
-            } else if (r < abc) {
-                u |= bit;
-            } else {
-                u |= bit;
-                v |= bit;
-            }
-        }
-        eu[i] = u;
-        ev[i] = v;
+        rmat_edge(scale, a, b, c, s0, i, eu + i, ev + i);
+        ev[i] += half;
     }
-    gg_graph *g = build_csr(n, ne, eu, ev);
+    gg_graph *g = build_csr(2 * half, ne, eu, ev);
     free(eu);
     free(ev);
     return g;

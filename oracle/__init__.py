@@ -16,8 +16,12 @@ Every function follows a textbook definition named in the paper:
 * ``pagerank_filtered``  the same iteration with per-vertex convergence
   filtering (Sec. 5.5): a vertex leaves the frontier once its rank changes by
   less than a tolerance and keeps that rank from then on.
+* ``two_hop``   walks of length two from a seed set (the 2-hop advance, Sec. 4.1).
+* ``ppr``       personalized PageRank, teleport and dangling mass to the seeds.
+* ``salsa``, ``hits``  bipartite node rankings (hubs left, authorities right),
+  the rankings Sec. 5.5 lists as built on the same advance.
 
-All six are pinned against brute force, closed forms, library routines and
+All ten are pinned against brute force, closed forms, library routines and
 invariants in ``tests/test_oracle_pins.py``.
 """
 from __future__ import annotations
@@ -62,6 +66,14 @@ class Oracle:
         lib.or_pagerank.argtypes = [i32, vp, vp, f64, f64, i32, vp, vp, vp]
         lib.or_pagerank_filtered.restype = i32
         lib.or_pagerank_filtered.argtypes = [i32, vp, vp, f64, f64, i32, vp, vp, vp, vp]
+        lib.or_two_hop.restype = i32
+        lib.or_two_hop.argtypes = [i32, vp, vp, vp, i32, vp]
+        lib.or_ppr.restype = i32
+        lib.or_ppr.argtypes = [i32, vp, vp, vp, i32, f64, f64, i32, vp, vp, vp]
+        lib.or_salsa.restype = i32
+        lib.or_salsa.argtypes = [i32, vp, vp, i32, i32, vp, vp]
+        lib.or_hits.restype = i32
+        lib.or_hits.argtypes = [i32, vp, vp, i32, i32, vp, vp]
         self.lib = lib
         self.path = libpath
 
@@ -132,6 +144,46 @@ class Oracle:
             raise ValueError("oracle.pagerank_filtered: bad input")
         return x, int(it.value), float(l1.value), act.astype(bool)
 
+    def two_hop(self, row, col, seeds) -> np.ndarray:
+        """uint64 number of walks s - u - v of length two from the seed set, per end vertex v."""
+        row, col = _c(row, np.int32), _c(col, np.int32)
+        sd = _c(seeds, np.int32)
+        n = row.size - 1
+        out = np.empty(n, np.uint64)
+        if self.lib.or_two_hop(n, _p(row), _p(col), _p(sd), sd.size, _p(out)) != 0:
+            raise ValueError("oracle.two_hop: bad input (seeds empty, out of range or duplicated)")
+        return out
+
+    def ppr(self, row, col, seeds, damping: float = 0.85, tol: float = 1e-9, max_iter: int = 1000):
+        """(FP64 personalized PageRank, iterations, last L1 change); teleport uniform over the seeds."""
+        row, col = _c(row, np.int32), _c(col, np.int32)
+        sd = _c(seeds, np.int32)
+        n = row.size - 1
+        x = np.empty(n, np.float64)
+        it = ctypes.c_int32(0)
+        l1 = ctypes.c_double(0.0)
+        if self.lib.or_ppr(n, _p(row), _p(col), _p(sd), sd.size, float(damping), float(tol), int(max_iter), _p(x),
+                           ctypes.addressof(it), ctypes.addressof(l1)) != 0:
+            raise ValueError("oracle.ppr: bad input")
+        return x, int(it.value), float(l1.value)
+
+    def _bip(self, fn, name, row, col, n_left: int, iters: int):
+        row, col = _c(row, np.int32), _c(col, np.int32)
+        n = row.size - 1
+        hub = np.empty(max(n_left, 0), np.float64)
+        auth = np.empty(max(n - n_left, 0), np.float64)
+        if fn(n, _p(row), _p(col), int(n_left), int(iters), _p(hub), _p(auth)) != 0:
+            raise ValueError("oracle.%s: bad input (not bipartite across n_left, or bad sizes)" % name)
+        return hub, auth
+
+    def salsa(self, row, col, n_left: int, iters: int):
+        """(hub scores of [0, n_left), authority scores of [n_left, n)) after `iters` SALSA iterations."""
+        return self._bip(self.lib.or_salsa, "salsa", row, col, n_left, iters)
+
+    def hits(self, row, col, n_left: int, iters: int):
+        """(unit-L2 hub scores, unit-L2 authority scores) after `iters` HITS iterations."""
+        return self._bip(self.lib.or_hits, "hits", row, col, n_left, iters)
+
 
 _default = None
 
@@ -173,3 +225,19 @@ def pagerank(row, col, damping: float = 0.85, tol: float = 1e-6, max_iter: int =
 
 def pagerank_filtered(row, col, damping: float, vertex_tol: float, max_iter: int = 1000):
     return default().pagerank_filtered(row, col, damping, vertex_tol, max_iter)
+
+
+def two_hop(row, col, seeds):
+    return default().two_hop(row, col, seeds)
+
+
+def ppr(row, col, seeds, damping: float = 0.85, tol: float = 1e-9, max_iter: int = 1000):
+    return default().ppr(row, col, seeds, damping, tol, max_iter)
+
+
+def salsa(row, col, n_left: int, iters: int):
+    return default().salsa(row, col, n_left, iters)
+
+
+def hits(row, col, n_left: int, iters: int):
+    return default().hits(row, col, n_left, iters)

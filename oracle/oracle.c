@@ -1,5 +1,5 @@
 /*
- * oracle.c -- plain, slow, obviously-correct CPU reference for the five graph
+ * oracle.c -- plain, slow, obviously-correct CPU reference for the graph
  * primitives of the frontier engine.  TEST INFRASTRUCTURE ONLY: it is used by
  * the test-suite, by the smoke check and by the benchmark's CPU-baseline leg,
  * never by the product path.  It shares no code with the GPU engine.
@@ -14,6 +14,9 @@
  *   BC    unnormalised sum over ordered pairs (s in S, t in V), no halving.
  *   CC    label = smallest vertex id of the component.
  *   PR    uniform teleport (1-d)/N, dangling mass spread uniformly, L1 stop.
+ *   2-hop uint64 walk counts per end vertex.
+ *   PPR   teleport and dangling mass uniform over the seeds, x_0 on the seeds.
+ *   SALSA / HITS  hubs = [0, nl), authorities = [nl, n), every edge across.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -348,5 +351,169 @@ OR_EXPORT int32_t or_pagerank_filtered(int32_t n, const int32_t *R, const int32_
     free(active);
     if (iters) *iters = k;
     if (last_l1) *last_l1 = l1;
+    return 0;
+}
+
+/* ------------------------------------------------- 2-hop and ranking ---- */
+static int32_t distinct_in_range(int32_t n, const int32_t *v, int32_t k)
+{
+    if (k < 1) return 0;
+    for (int32_t i = 0; i < k; ++i) {
+        if (v[i] < 0 || v[i] >= n) return 0;
+        for (int32_t j = 0; j < i; ++j) if (v[j] == v[i]) return 0;
+    }
+    return 1;
+}
+
+/*
+ * Walks of length two from a vertex set (Sec. 4.1, the fourth use of advance:
+ * from the seeds' edges to their neighbouring edges, returning the far-end
+ * vertices): count[v] = number of walks s - u - v with s a seed, u a
+ * neighbour of s and v a neighbour of u.  Seeds distinct and in range.
+ */
+OR_EXPORT int32_t or_two_hop(int32_t n, const int32_t *R, const int32_t *C, const int32_t *seeds, int32_t k,
+                             uint64_t *count)
+{
+    if (n <= 0 || !distinct_in_range(n, seeds, k)) return -1;
+    for (int32_t v = 0; v < n; ++v) count[v] = 0;
+    for (int32_t i = 0; i < k; ++i) {
+        const int32_t s = seeds[i];
+        for (int32_t e = R[s]; e < R[s + 1]; ++e) {
+            const int32_t u = C[e];
+            for (int32_t f = R[u]; f < R[u + 1]; ++f) count[C[f]] += 1;
+        }
+    }
+    return 0;
+}
+
+/*
+ * Personalized PageRank (one of the bipartite node rankings built on
+ * advance, Sec. 5.5's list of further uses): the teleport vector p is uniform
+ * over the seeds and also receives the rank of zero-degree vertices,
+ *   x_0     = p
+ *   x_{k+1}(v) = (1-d) p(v) + d * ( sum_{u in N(v)} x_k(u)/deg(u) + D_k p(v) )
+ * with D_k the rank on zero-degree vertices.  Stops like or_pagerank: after
+ * the first iteration whose L1 change is below tol, or after max_iter.
+ */
+OR_EXPORT int32_t or_ppr(int32_t n, const int32_t *R, const int32_t *C, const int32_t *seeds, int32_t k,
+                         double damping, double tol, int32_t max_iter, double *x, int32_t *iters,
+                         double *last_l1)
+{
+    if (n <= 0 || max_iter < 0 || !(damping > 0.0 && damping < 1.0) || !distinct_in_range(n, seeds, k))
+        return -1;
+    double *p = (double *)calloc((size_t)n, sizeof(double));
+    double *y = (double *)malloc((size_t)n * sizeof(double));
+    if (!p || !y) {
+        free(p);
+        free(y);
+        return -1;
+    }
+    for (int32_t i = 0; i < k; ++i) p[seeds[i]] = 1.0 / (double)k;
+    for (int32_t v = 0; v < n; ++v) x[v] = p[v];
+    int32_t it = 0;
+    double l1 = 0.0;
+    while (it < max_iter) {
+        const double dangling = pr_dangling_mass(n, R, x);
+        for (int32_t v = 0; v < n; ++v)
+            y[v] = (1.0 - damping) * p[v] + damping * (pr_neighbour_sum(R, C, x, v) + dangling * p[v]);
+        l1 = 0.0;
+        for (int32_t v = 0; v < n; ++v) {
+            l1 += fabs(y[v] - x[v]);
+            x[v] = y[v];
+        }
+        ++it;
+        if (l1 < tol && tol > 0.0) break;
+    }
+    free(p);
+    free(y);
+    if (iters) *iters = it;
+    if (last_l1) *last_l1 = l1;
+    return 0;
+}
+
+/* every edge must join the two sides [0, nl) and [nl, n) */
+static int32_t is_bipartite_split(int32_t n, const int32_t *R, const int32_t *C, int32_t nl)
+{
+    if (nl < 1 || nl >= n) return 0;
+    for (int32_t v = 0; v < n; ++v)
+        for (int32_t e = R[v]; e < R[v + 1]; ++e)
+            if ((v < nl) == (C[e] < nl)) return 0;
+    return 1;
+}
+
+/*
+ * SALSA on a bipartite graph (hubs on the left [0, nl), authorities on the
+ * right [nl, n)): random-walk scores, starting from h_0 = 1/nl on every hub;
+ * each iteration
+ *   a(r) = sum_{l in N(r)} h(l) / deg(l)     then
+ *   h(l) = sum_{r in N(l)} a(r) / deg(r)     (with the new a).
+ * hub[nl] and auth[n - nl] receive the scores after `iters` iterations.
+ */
+OR_EXPORT int32_t or_salsa(int32_t n, const int32_t *R, const int32_t *C, int32_t nl, int32_t iters,
+                           double *hub, double *auth)
+{
+    if (n <= 1 || iters < 0 || !is_bipartite_split(n, R, C, nl)) return -1;
+    const int32_t nr = n - nl;
+    for (int32_t l = 0; l < nl; ++l) hub[l] = 1.0 / (double)nl;
+    for (int32_t r = 0; r < nr; ++r) auth[r] = 0.0;
+    for (int32_t it = 0; it < iters; ++it) {
+        for (int32_t r = 0; r < nr; ++r) {
+            const int32_t v = nl + r;
+            double s = 0.0;
+            for (int32_t e = R[v]; e < R[v + 1]; ++e) {
+                const int32_t l = C[e];
+                s += hub[l] / (double)(R[l + 1] - R[l]);
+            }
+            auth[r] = s;
+        }
+        for (int32_t l = 0; l < nl; ++l) {
+            double s = 0.0;
+            for (int32_t e = R[l]; e < R[l + 1]; ++e) {
+                const int32_t v = C[e];
+                s += auth[v - nl] / (double)(R[v + 1] - R[v]);
+            }
+            hub[l] = s;
+        }
+    }
+    return 0;
+}
+
+static void scale_to_unit_l2(double *a, int32_t len)
+{
+    double ss = 0.0;
+    for (int32_t i = 0; i < len; ++i) ss += a[i] * a[i];
+    if (ss > 0.0) {
+        const double inv = 1.0 / sqrt(ss);
+        for (int32_t i = 0; i < len; ++i) a[i] *= inv;
+    }
+}
+
+/*
+ * HITS on a bipartite graph (hubs left, authorities right): h_0 = 1/sqrt(nl);
+ * each iteration a = B^T h, scaled to unit L2 norm, then h = B a, scaled to
+ * unit L2 norm (a zero vector stays zero), B the biadjacency matrix.
+ */
+OR_EXPORT int32_t or_hits(int32_t n, const int32_t *R, const int32_t *C, int32_t nl, int32_t iters, double *hub,
+                          double *auth)
+{
+    if (n <= 1 || iters < 0 || !is_bipartite_split(n, R, C, nl)) return -1;
+    const int32_t nr = n - nl;
+    for (int32_t l = 0; l < nl; ++l) hub[l] = 1.0 / sqrt((double)nl);
+    for (int32_t r = 0; r < nr; ++r) auth[r] = 0.0;
+    for (int32_t it = 0; it < iters; ++it) {
+        for (int32_t r = 0; r < nr; ++r) {
+            const int32_t v = nl + r;
+            double s = 0.0;
+            for (int32_t e = R[v]; e < R[v + 1]; ++e) s += hub[C[e]];
+            auth[r] = s;
+        }
+        scale_to_unit_l2(auth, nr);
+        for (int32_t l = 0; l < nl; ++l) {
+            double s = 0.0;
+            for (int32_t e = R[l]; e < R[l + 1]; ++e) s += auth[C[e] - nl];
+            hub[l] = s;
+        }
+        scale_to_unit_l2(hub, nl);
+    }
     return 0;
 }

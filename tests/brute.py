@@ -93,6 +93,22 @@ def pagerank_solve(A: np.ndarray, d: float) -> np.ndarray:
     return np.linalg.solve(np.eye(n) - d * M, np.full(n, (1.0 - d) / n))
 
 
+def ppr_solve(A: np.ndarray, d: float, seeds) -> np.ndarray:
+    """Fixed point of x = (1-d) p + d (A^T D^-1 x + (dangling . x) p), p uniform over the
+    seeds, by a dense solve."""
+    n = A.shape[0]
+    p = np.zeros(n)
+    p[list(seeds)] = 1.0 / len(seeds)
+    deg = A.sum(1).astype(float)
+    M = np.zeros((n, n))
+    for u in range(n):
+        if deg[u] > 0:
+            M[:, u] = A[u, :] / deg[u]
+        else:
+            M[:, u] = p
+    return np.linalg.solve(np.eye(n) - d * M, (1.0 - d) * p)
+
+
 def component_min_labels(D: np.ndarray) -> np.ndarray:
     """label[v] = smallest u reachable from v (finite distance)."""
     n = D.shape[0]

@@ -44,6 +44,17 @@ MUTANTS = [
     ("prf_frozen_keep_old_value", "x[v] = y[v];\n            if (dx >= vertex_tol) ++in_frontier;\n            else active[v] = 0;",
      "if (dx >= vertex_tol) { ++in_frontier; x[v] = y[v]; }\n            else active[v] = 0;"),
     ("prf_gauss_seidel", "if (active[v]) y[v] = pr_update(", "if (active[v]) x[v] = y[v] = pr_update("),
+    ("two_hop_counts_middle_vertex", "for (int32_t f = R[u]; f < R[u + 1]; ++f) count[C[f]] += 1;",
+     "for (int32_t f = R[u]; f < R[u + 1]; ++f) count[u] += 1;"),
+    ("two_hop_one_hop_only", "for (int32_t f = R[u]; f < R[u + 1]; ++f) count[C[f]] += 1;", "count[u] += 1;"),
+    ("ppr_dangling_spread_uniformly", "dangling * p[v]", "dangling / (double)n"),
+    ("ppr_teleport_uniform", "(1.0 - damping) * p[v]", "(1.0 - damping) / (double)n"),
+    ("salsa_divides_by_target_degree", "s += hub[l] / (double)(R[l + 1] - R[l]);",
+     "s += hub[l] / (double)(R[v + 1] - R[v]);"),
+    ("salsa_hub_from_unnormalised_auth", "s += auth[v - nl] / (double)(R[v + 1] - R[v]);", "s += auth[v - nl];"),
+    ("hits_skips_authority_scaling", "scale_to_unit_l2(auth, nr);", "(void)0;"),
+    ("hits_l1_scaling", "for (int32_t i = 0; i < len; ++i) ss += a[i] * a[i];",
+     "for (int32_t i = 0; i < len; ++i) ss += fabs(a[i]);"),
     ("pr_teleport_not_divided", "(1.0 - damping) / N + damping", "(1.0 - damping) + damping"),
     ("pr_divides_by_own_degree", "s += x[u] / (double)(R[u + 1] - R[u]);",
      "s += x[u] / (double)(R[v + 1] - R[v]);"),
@@ -67,6 +78,10 @@ def _all_pins(O):
     pins.pin_scipy(O)
     pins.pin_invariants(O)
     pins.pin_pagerank_filtered(O)
+    pins.pin_two_hop(O)
+    pins.pin_ppr(O)
+    pins.pin_salsa(O)
+    pins.pin_hits(O)
 
 
 @pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])

@@ -306,6 +306,142 @@ def test_pagerank_filtered(orc):
     pin_pagerank_filtered(orc)
 
 
+# --------------------------------------------- 2-hop and node ranking ----
+def _bipartite(rng, nl, nr, p, connect=True):
+    """Random bipartite graph, left [0, nl), right [nl, nl + nr); with `connect`
+    a spanning path alternating sides keeps it connected."""
+    B = rng.random((nl, nr)) < p
+    if connect:
+        for i in range(max(nl, nr)):
+            B[i % nl, i % nr] = True
+            B[(i + 1) % nl, i % nr] = True
+    l, r = np.nonzero(B)
+    row, col = graphgen.from_edges(nl + nr, l, nl + r)
+    return row, col, B
+
+
+def pin_two_hop(O, seed=4):
+    rng = np.random.default_rng(seed)
+    # every labelled graph on up to 4 vertices, every seed set, against A @ A
+    for n in range(1, 5):
+        for A in brute.all_simple_graphs(n):
+            row, col, _ = brute.csr_from_adj(A)
+            A2 = A.astype(np.int64) @ A.astype(np.int64)
+            for mask in range(1, 1 << n):
+                S = [i for i in range(n) if mask >> i & 1]
+                assert np.array_equal(O.two_hop(row, col, S), A2[S].sum(0)), (A.tolist(), S)
+    # scipy sparse products on larger graphs; the total is the degree sum of the seeds' neighbours
+    for row, col in (_random_graph(rng, 300, 0.02), graphgen.rmat(11), graphgen.grid(40)):
+        n = row.size - 1
+        M = _csr_matrix(row, col)
+        for k in (1, 5, 40):
+            S = rng.choice(n, size=k, replace=False)
+            want = np.asarray((M[S] @ M).sum(0)).ravel().astype(np.uint64)
+            got = O.two_hop(row, col, S)
+            assert np.array_equal(got, want)
+            deg = np.diff(row)
+            assert int(got.sum()) == int(sum(deg[col[row[s]:row[s + 1]]].sum() for s in S))
+    row, col = _star(6)
+    for bad in ([], [1, 1], [6]):
+        with pytest.raises(ValueError):
+            O.two_hop(row, col, bad)
+
+
+def pin_ppr(O, seed=5):
+    rng = np.random.default_rng(seed)
+    for n in range(1, 6):
+        for A in brute.all_simple_graphs(n):
+            row, col, _ = brute.csr_from_adj(A)
+            S = sorted(rng.choice(n, size=rng.integers(1, n + 1), replace=False).tolist())
+            x, it, l1 = O.ppr(row, col, S, 0.85, 1e-15, 10000)
+            assert np.allclose(x, brute.ppr_solve(A, 0.85, S), rtol=0, atol=1e-13), (A.tolist(), S)
+    row, col = graphgen.rmat(11)
+    n = row.size - 1
+    # teleport to every vertex is plain PageRank
+    x, _, _ = O.ppr(row, col, np.arange(n), 0.85, 1e-14, 10000)
+    xp, _, _ = O.pagerank(row, col, 0.85, 1e-14, 10000)
+    assert np.abs(x - xp).sum() < 1e-12
+    # mass, positivity on the seeds' reach, and the contraction bound
+    S = graphgen.sample_sources(row, col, 3)
+    x, it, l1 = O.ppr(row, col, S, 0.85, 1e-8, 1000)
+    xs, _, _ = O.ppr(row, col, S, 0.85, 1e-15, 10000)
+    assert abs(x.sum() - 1.0) < 1e-12 and l1 < 1e-8
+    assert np.abs(x - xs).sum() <= 0.85 / 0.15 * l1 * (1 + 1e-9)
+    reach = O.bfs(row, col, int(S[0])) >= 0
+    assert np.all(xs[reach] > 0) and np.all(xs[~reach] == 0)
+
+
+def pin_salsa(O, seed=6):
+    rng = np.random.default_rng(seed)
+    # K_{a,b}: uniform after one iteration
+    for a, b in ((1, 1), (3, 5), (7, 2)):
+        l, r = np.divmod(np.arange(a * b), b)
+        row, col = graphgen.from_edges(a + b, l, a + r)
+        h, au = O.salsa(row, col, a, 1)
+        assert np.allclose(h, 1.0 / a, atol=1e-16) and np.allclose(au, 1.0 / b, atol=1e-16)
+    # connected, no isolated vertex: the scores converge to degree / |E|
+    row, col, B = _bipartite(rng, 40, 60, 0.08)
+    E = col.size // 2
+    deg = np.diff(row).astype(float)
+    h, au = O.salsa(row, col, 40, 400)
+    assert np.allclose(h, deg[:40] / E, rtol=0, atol=1e-12) and np.allclose(au, deg[40:] / E, rtol=0, atol=1e-12)
+    for it in (1, 2, 7):   # the walk keeps its mass
+        h, au = O.salsa(row, col, 40, it)
+        assert abs(h.sum() - 1) < 1e-12 and abs(au.sum() - 1) < 1e-12
+    # two components: each keeps the share of hubs it started with, spread by degree
+    r1, c1, _ = _bipartite(rng, 10, 15, 0.2)
+    r2, c2, _ = _bipartite(rng, 30, 20, 0.1)
+    s1 = np.repeat(np.arange(25), np.diff(r1))
+    s2 = np.repeat(np.arange(50), np.diff(r2))
+    relabel1 = np.where(np.arange(25) < 10, np.arange(25), 40 + (np.arange(25) - 10))
+    relabel2 = np.where(np.arange(50) < 30, 10 + np.arange(50), 40 + 15 + (np.arange(50) - 30))
+    eu = np.concatenate([relabel1[s1], relabel2[s2]])
+    ev = np.concatenate([relabel1[c1], relabel2[c2]])
+    row, col = graphgen.from_edges(75, eu, ev)
+    deg = np.diff(row).astype(float)
+    h, au = O.salsa(row, col, 40, 600)
+    E1, E2 = c1.size // 2, c2.size // 2
+    want_h = np.concatenate([10 / 40 * deg[:10] / E1, 30 / 40 * deg[10:40] / E2])
+    want_a = np.concatenate([10 / 40 * deg[40:55] / E1, 30 / 40 * deg[55:] / E2])
+    assert np.allclose(h, want_h, rtol=0, atol=1e-12) and np.allclose(au, want_a, rtol=0, atol=1e-12)
+    with pytest.raises(ValueError):
+        O.salsa(*_path(4), 1, 3)      # edge 1-2 stays inside the right side
+
+
+def pin_hits(O, seed=7):
+    rng = np.random.default_rng(seed)
+    for a, b in ((1, 1), (3, 5), (7, 2)):
+        l, r = np.divmod(np.arange(a * b), b)
+        row, col = graphgen.from_edges(a + b, l, a + r)
+        h, au = O.hits(row, col, a, 1)
+        assert np.allclose(h, 1 / np.sqrt(a), atol=1e-15) and np.allclose(au, 1 / np.sqrt(b), atol=1e-15)
+    row, col, B = _bipartite(rng, 50, 35, 0.1)
+    U, sv, Vt = np.linalg.svd(B.astype(float))
+    u1, v1 = np.abs(U[:, 0]), np.abs(Vt[0])
+    assert sv[0] - sv[1] > 0.1 * sv[0]           # a clear gap, so the iteration converges fast
+    h, au = O.hits(row, col, 50, 300)
+    assert np.allclose(h, u1, rtol=0, atol=1e-10) and np.allclose(au, v1, rtol=0, atol=1e-10)
+    for it in (1, 3):
+        h, au = O.hits(row, col, 50, it)
+        assert abs(np.linalg.norm(h) - 1) < 1e-14 and abs(np.linalg.norm(au) - 1) < 1e-14
+
+
+def test_two_hop(orc):
+    pin_two_hop(orc)
+
+
+def test_ppr(orc):
+    pin_ppr(orc)
+
+
+def test_salsa(orc):
+    pin_salsa(orc)
+
+
+def test_hits(orc):
+    pin_hits(orc)
+
+
 def test_input_validation(orc):
     row, col = _path(5)
     with pytest.raises(ValueError):
