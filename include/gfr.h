@@ -98,6 +98,7 @@ const char *gfr_last_error(const gfr_ctx *ctx);
  *   "bc.direction"    BC forward discovery (Sec. 5.3 with the push/pull choice of
  *                     Sec. 4.5): 0 auto, 1 push only, 2 pull only; results do not change
  *   "bc.alpha", "bc.beta"  the same ratios as bfs.alpha / bfs.beta for BC's levels
+ *   "twohop.direction" second advance of gfr_two_hop: 0 auto, 1 push, 2 pull
  *   "serve.max_batch" largest number of queries the serving runtime runs together (1..64)
  *   "serve.hipgraph"  1 (default): serving sessions replay their rounds of steps from
  *                     hipGraphs captured once per session; 0: plain launches
@@ -231,6 +232,51 @@ gfr_status gfr_pagerank(gfr_ctx *ctx, gfr_graph g, float damping, double l1_tol,
 gfr_status gfr_pagerank_filtered(gfr_ctx *ctx, gfr_graph g, double damping, double vertex_tol,
                                  int32_t max_iter, double *rank_out, uint8_t *active_out,
                                  int32_t *iters_out, double *final_l1_out, gfr_stream stream);
+
+/* --------------------------------------------- 2-hop and node rankings */
+/*
+ * Walks of length two from a seed set (Sec. 4.1: advance from the seeds'
+ * edges to their neighbouring edges, returning the far-end vertices):
+ *   count_out[v] = number of walks s - u - v, s in seeds, u in N(s), v in N(u)
+ * seeds: host array of k >= 1 distinct vertices.  count_out: n uint64 (device
+ * or host memory).  The second advance pushes with 64-bit atomics, or pulls
+ * over every list when the middle vertices hold more than a quarter of all
+ * edges (option "twohop.direction": 0 auto, 1 push, 2 pull; same result).
+ * GFR_E_INVALID for an empty, out-of-range or duplicated seed set.
+ */
+gfr_status gfr_two_hop(gfr_ctx *ctx, gfr_graph g, const int32_t *seeds, int32_t k,
+                       uint64_t *count_out, gfr_stream stream);
+
+/*
+ * Personalized PageRank (one of the rankings Sec. 5.5 lists as built on
+ * advance): teleport vector p uniform over the seed set, which also receives
+ * the rank held by zero-degree vertices:
+ *   x_0 = p,  x_{k+1}(v) = (1-d) p(v) + d * (sum_{u in N(v)} x_k(u)/deg(u) + D_k p(v))
+ * Stops after the first iteration whose L1 change is below l1_tol, or after
+ * max_iter iterations.  FP64 throughout.  seeds: host, k >= 1 distinct.
+ * rank_out: n doubles.  GFR_E_INVALID on bad seeds, damping outside (0,1),
+ * l1_tol < 0 or max_iter < 1.
+ */
+gfr_status gfr_ppr(gfr_ctx *ctx, gfr_graph g, const int32_t *seeds, int32_t k, double damping,
+                   double l1_tol, int32_t max_iter, double *rank_out, int32_t *iters_out,
+                   double *final_l1_out, gfr_stream stream);
+
+/*
+ * Bipartite node rankings (Sec. 5.5): the graph's vertices [0, n_left) are
+ * hubs and [n_left, n) authorities, and every edge must join the two sides
+ * (checked on the device once per graph and split; GFR_E_INVALID otherwise).
+ * SALSA (random walk): h_0 = 1/n_left on every hub; per iteration
+ *   a(r) = sum_{l in N(r)} h(l)/deg(l),  then  h(l) = sum_{r in N(l)} a(r)/deg(r).
+ * HITS: h_0 = 1/sqrt(n_left); per iteration a = B^T h scaled to unit L2 norm,
+ * then h = B a scaled to unit L2 norm (B the biadjacency matrix; a zero
+ * vector stays zero).  hub_out: n_left doubles, auth_out: n - n_left doubles
+ * (device or host memory), the scores after `iters` iterations (iters >= 0).
+ * FP64, fixed summation order.
+ */
+gfr_status gfr_salsa(gfr_ctx *ctx, gfr_graph g, int32_t n_left, int32_t iters, double *hub_out,
+                     double *auth_out, gfr_stream stream);
+gfr_status gfr_hits(gfr_ctx *ctx, gfr_graph g, int32_t n_left, int32_t iters, double *hub_out,
+                    double *auth_out, gfr_stream stream);
 
 /* ---------------------------------------------------------------- batching */
 /*

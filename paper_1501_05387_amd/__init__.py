@@ -67,6 +67,11 @@ SIGNATURES = {
                             ctypes.POINTER(_f64), _vp]),
     "gfr_pagerank_filtered": (_i32, [_vp, _i64, _f64, _f64, _i32, _vp, _vp, ctypes.POINTER(_i32),
                                      ctypes.POINTER(_f64), _vp]),
+    "gfr_two_hop": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp]),
+    "gfr_ppr": (_i32, [_vp, _i64, _vp, _i32, _f64, _f64, _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_f64),
+                       _vp]),
+    "gfr_salsa": (_i32, [_vp, _i64, _i32, _i32, _vp, _vp, _vp]),
+    "gfr_hits": (_i32, [_vp, _i64, _i32, _i32, _vp, _vp, _vp]),
     "gfr_bfs_batch": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp]),
     "gfr_sssp_batch": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp]),
     "gfr_submit_queries": (_i32, [_vp, ctypes.POINTER(Query), _i32, ctypes.POINTER(_i64)]),
@@ -165,7 +170,7 @@ class Context:
         if out is None:
             torch = _torch()
             tdt = {np.int32: torch.int32, np.uint32: torch.int32, np.float32: torch.float32,
-                   np.float64: torch.float64, np.uint8: torch.uint8}[dtype]
+                   np.float64: torch.float64, np.uint8: torch.uint8, np.uint64: torch.int64}[dtype]
             t = torch.empty(count, dtype=tdt, device="cuda:%d" % self.device)
             return t.data_ptr(), t
         if isinstance(out, np.ndarray):
@@ -249,6 +254,36 @@ class Context:
                                                 int(max_iter), p, pa, ctypes.byref(it), ctypes.byref(l1),
                                                 self._stream()))
         return ret, act, it.value, l1.value
+
+    def two_hop(self, g: Graph, seeds, out=None):
+        """Walks of length two from the seed set, per end vertex (int64 tensor or uint64 array)."""
+        sd = _np(seeds, np.int32)
+        p, ret = self._out(out, g.n, np.uint64)
+        self._check(lib().gfr_two_hop(self.ptr, g.handle, sd.ctypes.data, sd.size, p, self._stream()))
+        return ret
+
+    def ppr(self, g: Graph, seeds, damping: float = 0.85, tol: float = 1e-9, max_iter: int = 1000, out=None):
+        """(FP64 personalized PageRank, iterations, last L1 change)."""
+        sd = _np(seeds, np.int32)
+        p, ret = self._out(out, g.n, np.float64)
+        it, l1 = _i32(), _f64()
+        self._check(lib().gfr_ppr(self.ptr, g.handle, sd.ctypes.data, sd.size, float(damping), float(tol),
+                                  int(max_iter), p, ctypes.byref(it), ctypes.byref(l1), self._stream()))
+        return ret, it.value, l1.value
+
+    def _bipartite(self, fn, g: Graph, n_left: int, iters: int, hub, auth):
+        ph, rh = self._out(hub, n_left, np.float64)
+        pa, ra = self._out(auth, g.n - n_left, np.float64)
+        self._check(fn(self.ptr, g.handle, int(n_left), int(iters), ph, pa, self._stream()))
+        return rh, ra
+
+    def salsa(self, g: Graph, n_left: int, iters: int, hub=None, auth=None):
+        """(hub scores of [0, n_left), authority scores of [n_left, n)) after `iters` SALSA iterations."""
+        return self._bipartite(lib().gfr_salsa, g, n_left, iters, hub, auth)
+
+    def hits(self, g: Graph, n_left: int, iters: int, hub=None, auth=None):
+        """(unit-L2 hub scores, unit-L2 authority scores) after `iters` HITS iterations."""
+        return self._bipartite(lib().gfr_hits, g, n_left, iters, hub, auth)
 
     def bfs_batch(self, g: Graph, sources, out=None):
         src = _np(sources, np.int32)

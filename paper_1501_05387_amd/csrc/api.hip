@@ -220,6 +220,25 @@ struct OutBuf {
 
 static hipStream_t pick_stream(Ctx &c, gfr_stream s) { return s ? (hipStream_t)s : c.stream; }
 
+void deliver(Ctx &c, void *user, const void *dev, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return;
+    if (is_device_ptr(user)) GFR_HIP(hipMemcpyAsync(user, dev, bytes, hipMemcpyDeviceToDevice, s));
+    else copy_to_host(c.bounce, user, dev, bytes, s);
+    GFR_HIP(hipStreamSynchronize(s));
+}
+
+// seeds: host array of k distinct in-range vertices
+static void check_seeds(const Graph &g, const int32_t *seeds, int32_t k, const char *who)
+{
+    if (k < 1 || !seeds) fail(GFR_E_INVALID, std::string(who) + ": need k >= 1 seeds");
+    std::vector<uint8_t> seen((size_t)g.n, 0);
+    for (int32_t i = 0; i < k; ++i) {
+        if (seeds[i] < 0 || seeds[i] >= g.n) fail(GFR_E_INVALID, std::string(who) + ": seed out of range");
+        if (seen[(size_t)seeds[i]]++) fail(GFR_E_INVALID, std::string(who) + ": duplicated seed");
+    }
+}
+
 template <class F>
 static gfr_status guard(gfr_ctx *ctx, F f)
 {
@@ -276,6 +295,7 @@ static const OptKey kOptKeys[] = {
     {"batch.min_bfs", 1, 1e9, true},     {"batch.min_sssp", 1, 1e9, true},
     {"batch.pull_alpha", 0, 1e6, true},  {"bc.direction", 0, 2, true},
     {"bc.alpha", 1e-6, 1e9, true},       {"bc.beta", 1e-6, 1e9, true},
+    {"twohop.direction", 0, 2, true},
     {"serve.budget_bytes", 0, 1e15, false}, {"serve.max_batch", 1, 64, false},
     {"profile.kernels", 0, 1, false}, {"serve.hipgraph", 0, 1, false},
 };
@@ -306,6 +326,7 @@ void option_set(Options &o, const std::string &key, double v)
     else if (key == "bc.direction") o.bc_direction = (int)v;
     else if (key == "bc.alpha") o.bc_alpha = v;
     else if (key == "bc.beta") o.bc_beta = v;
+    else if (key == "twohop.direction") o.twohop_direction = (int)v;
     else if (key == "serve.budget_bytes") o.serve_budget = v;
     else if (key == "serve.max_batch") o.serve_max_batch = (int)v;
     else if (key == "profile.kernels") o.profile_kernels = (int)v;
@@ -337,6 +358,7 @@ static double option_get(const Options &o, const std::string &key)
     if (key == "bc.direction") return o.bc_direction;
     if (key == "bc.alpha") return o.bc_alpha;
     if (key == "bc.beta") return o.bc_beta;
+    if (key == "twohop.direction") return o.twohop_direction;
     if (key == "serve.budget_bytes") return o.serve_budget;
     if (key == "serve.max_batch") return o.serve_max_batch;
     if (key == "serve.hipgraph") return o.serve_graphs;
@@ -756,6 +778,74 @@ gfr_status gfr_pagerank_filtered(gfr_ctx *ctx, gfr_graph gh, double damping, dou
         if (iters_out) *iters_out = it;
         if (final_l1_out) *final_l1_out = l1;
     });
+}
+
+gfr_status gfr_two_hop(gfr_ctx *ctx, gfr_graph gh, const int32_t *seeds, int32_t k, uint64_t *count_out,
+                       gfr_stream stream)
+{
+    return guard(ctx, [&](Ctx &c) {
+        Graph &g = get_graph(c, gh);
+        OptScope os(c, g);
+        check_seeds(g, seeds, k, "two_hop");
+        hipStream_t s = pick_stream(c, stream);
+        OutBuf o(c, count_out, 8ull * g.n);
+        timed_begin(c, s);
+        run_two_hop(c, g, seeds, k, (uint64_t *)o.dev, s);
+        timed_end(c, s);
+        o.finish(c, s);
+    });
+}
+
+gfr_status gfr_ppr(gfr_ctx *ctx, gfr_graph gh, const int32_t *seeds, int32_t k, double damping, double l1_tol,
+                   int32_t max_iter, double *rank_out, int32_t *iters_out, double *final_l1_out, gfr_stream stream)
+{
+    return guard(ctx, [&](Ctx &c) {
+        Graph &g = get_graph(c, gh);
+        OptScope os(c, g);
+        check_seeds(g, seeds, k, "ppr");
+        if (!(damping > 0.0 && damping < 1.0)) fail(GFR_E_INVALID, "ppr: damping must be in (0,1)");
+        if (max_iter < 1) fail(GFR_E_INVALID, "ppr: max_iter must be >= 1");
+        if (!(l1_tol >= 0.0)) fail(GFR_E_INVALID, "ppr: l1_tol must be >= 0");
+        hipStream_t s = pick_stream(c, stream);
+        OutBuf o(c, rank_out, 8ull * g.n);
+        int32_t it = 0;
+        double l1 = 0.0;
+        timed_begin(c, s);
+        run_ppr(c, g, seeds, k, damping, l1_tol, max_iter, (double *)o.dev, &it, &l1, s);
+        timed_end(c, s);
+        o.finish(c, s);
+        if (iters_out) *iters_out = it;
+        if (final_l1_out) *final_l1_out = l1;
+    });
+}
+
+static gfr_status bipartite_rank(gfr_ctx *ctx, gfr_graph gh, int32_t n_left, int32_t iters, double *hub_out,
+                                 double *auth_out, gfr_stream stream, bool walk)
+{
+    return guard(ctx, [&](Ctx &c) {
+        Graph &g = get_graph(c, gh);
+        OptScope os(c, g);
+        const char *who = walk ? "salsa" : "hits";
+        if (n_left < 1 || n_left >= g.n) fail(GFR_E_INVALID, std::string(who) + ": need 0 < n_left < n");
+        if (iters < 0) fail(GFR_E_INVALID, std::string(who) + ": iters must be >= 0");
+        if (!hub_out || !auth_out) fail(GFR_E_INVALID, std::string(who) + ": null output buffer");
+        hipStream_t s = pick_stream(c, stream);
+        timed_begin(c, s);
+        run_bipartite_rank(c, g, n_left, iters, walk, hub_out, auth_out, s);
+        timed_end(c, s);
+    });
+}
+
+gfr_status gfr_salsa(gfr_ctx *ctx, gfr_graph g, int32_t n_left, int32_t iters, double *hub_out, double *auth_out,
+                     gfr_stream stream)
+{
+    return bipartite_rank(ctx, g, n_left, iters, hub_out, auth_out, stream, true);
+}
+
+gfr_status gfr_hits(gfr_ctx *ctx, gfr_graph g, int32_t n_left, int32_t iters, double *hub_out, double *auth_out,
+                    gfr_stream stream)
+{
+    return bipartite_rank(ctx, g, n_left, iters, hub_out, auth_out, stream, false);
 }
 
 gfr_status gfr_bfs_batch(gfr_ctx *ctx, gfr_graph gh, const int32_t *sources, int32_t k,

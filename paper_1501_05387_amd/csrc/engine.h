@@ -104,6 +104,7 @@ struct Graph {
     uint32_t *full_counts = nullptr;   // device [nf, mf, 0, 0]
     int32_t full_nf = 0;
     int32_t n_isolated = 0;
+    int32_t bip_checked_nl = -1;   // last side split verified for the bipartite rankings
     // hints for the speculative level loop
     int32_t bfs_levels_hint = 8;
     int32_t sssp_iter_hint = 16;
@@ -130,6 +131,7 @@ struct Options {
     int bc_direction = 0;       // BC forward discovery: 0 auto, 1 push, 2 pull
     double bc_alpha = 15.0;     // push -> pull when level edges > unvisited edges / alpha (growing)
     double bc_beta = 18.0;      // pull -> push when level size < n / beta (shrinking)
+    int twohop_direction = 0;   // 2-hop second advance: 0 auto, 1 push, 2 pull
 };
 
 // Options from a tuning file: context-wide values and per-graph-class values.
@@ -274,6 +276,14 @@ uint32_t sssp_auto_delta(const Graph &g, double factor);
 void run_cc(Ctx &c, Graph &g, int32_t *label, int32_t *ncomp, hipStream_t s);
 void run_pagerank(Ctx &c, Graph &g, float damping, double tol, int32_t max_iter, float *rank,
                   int32_t *iters, double *l1, hipStream_t s);
+void run_ppr(Ctx &c, Graph &g, const int32_t *seeds, int32_t k, double damping, double tol, int32_t max_iter,
+             double *rank, int32_t *iters, double *l1, hipStream_t s);
+void run_two_hop(Ctx &c, Graph &g, const int32_t *seeds, int32_t k, uint64_t *count, hipStream_t s);
+// SALSA (walk = true) or HITS; hub / auth are the caller's buffers (device or host)
+void run_bipartite_rank(Ctx &c, Graph &g, int32_t nl, int32_t iters, bool walk, double *hub, double *auth,
+                        hipStream_t s);
+// Copy `bytes` of device data to a caller's buffer (device or host memory) and wait.
+void deliver(Ctx &c, void *user, const void *dev, size_t bytes, hipStream_t s);
 // Per-vertex convergence filtering; returns the final frontier membership
 // (n bytes in the context's arena, valid until the next solver call).
 const uint8_t *run_pagerank_filtered(Ctx &c, Graph &g, double damping, double vertex_tol, int32_t max_iter,

@@ -37,6 +37,13 @@ struct PrFin {
     __device__ void operator()(int32_t v, double s) const { sum[v] = s; }
 };
 
+// byte[list[i]] = 1 for i < k
+__global__ void set_bytes(const int32_t *list, int32_t k, uint8_t *byte)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k) byte[list[i]] = 1;
+}
+
 // Fixed-order block reduction of two FP64 values (wave butterfly, then the
 // four wave results in wave order).
 __device__ __forceinline__ void block_sum2(double &a, double &b)
@@ -393,6 +400,119 @@ const uint8_t *run_pagerank_filtered(Ctx &c, Graph &g, double damping, double ve
     c.stats.v["edges_gathered"] = h.edges;
     c.stats.v["final_frontier"] = (double)h.nf + (h.iso_active ? h.n_iso : 0.0);
     return active;
+}
+
+// ---------------------------------------------------------------------------
+// Personalized PageRank: the teleport vector p is uniform over a seed set and
+// also receives the rank of zero-degree vertices,
+//   x_0 = p,  x_{k+1}(v) = (1-d) p(v) + d (S(v) + D_k p(v)),
+// the ranking that seeds the bipartite who-to-follow pipeline.  Same launch
+// structure as run_pagerank (full-queue gather, finalize, one-group reduce,
+// speculative iterations), with FP64 ranks and contributions.
+
+struct PpOp {
+    const double *contrib;
+    __device__ double operator()(int32_t u, int32_t) const { return contrib[u]; }
+};
+
+__global__ __launch_bounds__(GFR_BLOCK) void ppr_init(const int32_t *R, int32_t n, const uint8_t *seed, double invk,
+                                                       double *x0, double *contrib, double *part)
+{
+    double dang = 0.0, zero = 0.0;
+    for (int32_t v = blockIdx.x * GFR_BLOCK + threadIdx.x; v < n; v += gridDim.x * GFR_BLOCK) {
+        const int32_t deg = R[v + 1] - R[v];
+        const double xv = seed[v] ? invk : 0.0;
+        x0[v] = xv;
+        if (deg > 0) contrib[v] = xv / (double)deg;
+        else dang += xv;
+    }
+    block_sum2(dang, zero);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = 0.0;
+        part[2 * blockIdx.x + 1] = dang;
+    }
+}
+
+__global__ __launch_bounds__(GFR_BLOCK) void ppr_finalize(const int32_t *R, int32_t n, const uint8_t *seed,
+                                                           double invk, double *xa, double *xb, double *contrib,
+                                                           const double *sum, double *part, PrCtl *ctl)
+{
+    if (ctl->done) return;
+    const uint32_t k = ctl->iters;
+    const double *xo = (k & 1) ? xb : xa;
+    double *xn = (k & 1) ? xa : xb;
+    const double d = ctl->damping, D = ctl->D;
+    double l1 = 0.0, dang = 0.0;
+    for (int32_t v = blockIdx.x * GFR_BLOCK + threadIdx.x; v < n; v += gridDim.x * GFR_BLOCK) {
+        const int32_t deg = R[v + 1] - R[v];
+        const double s = deg > 0 ? sum[v] : 0.0;
+        const double p = seed[v] ? invk : 0.0;
+        const double x = (1.0 - d) * p + d * (s + D * p);
+        l1 += fabs(x - xo[v]);
+        xn[v] = x;
+        if (deg > 0) contrib[v] = x / (double)deg;
+        else dang += x;
+    }
+    block_sum2(l1, dang);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = l1;
+        part[2 * blockIdx.x + 1] = dang;
+    }
+}
+
+void run_ppr(Ctx &c, Graph &g, const int32_t *seeds, int32_t k, double damping, double tol, int32_t max_iter,
+             double *rank, int32_t *iters, double *l1, hipStream_t s)
+{
+    const int32_t n = g.n;
+    const int G = grid_blocks(c, 4);
+    const size_t nch = (size_t)(g.m + GATHER_CH - 1) / GATHER_CH + 1;
+    c.arena.reserve(4 * al256(8ull * n) + al256(4ull * ((n + 3) / 4)) + al256(4ull * k) + 2 * al256(8 * nch) +
+                    al256(16ull * G) + al256(sizeof(PrCtl)));
+    double *xa = c.arena.take<double>(n);
+    double *xb = c.arena.take<double>(n);
+    double *contrib = c.arena.take<double>(n);
+    double *sum = c.arena.take<double>(n);
+    uint8_t *seed = c.arena.take<uint8_t>(4ull * ((n + 3) / 4));
+    int32_t *dseeds = c.arena.take<int32_t>(k);
+    GatherScratch gs{c.arena.take<double>(nch), c.arena.take<double>(nch)};
+    double *part = c.arena.take<double>(2 * (size_t)G);
+    PrCtl *ctl = c.arena.take<PrCtl>(1);
+    const double invk = 1.0 / (double)k;
+
+    PrCtl h{};
+    h.max_iter = (uint32_t)max_iter;
+    h.tol = tol;
+    h.damping = damping;
+    GFR_HIP(hipMemcpyAsync(ctl, &h, sizeof h, hipMemcpyHostToDevice, s));
+    GFR_HIP(hipMemcpyAsync(dseeds, seeds, 4ull * k, hipMemcpyHostToDevice, s));
+    fill_u32(seed, 0u, (n + 3) / 4, s);
+    hipLaunchKernelGGL(set_bytes, dim3((k + GFR_BLOCK - 1) / GFR_BLOCK), dim3(GFR_BLOCK), 0, s, dseeds, k, seed);
+    hipLaunchKernelGGL(ppr_init, dim3(G), dim3(GFR_BLOCK), 0, s, g.R.as<int32_t>(), n, seed, invk, xa, contrib, part);
+    hipLaunchKernelGGL(pr_reduce, dim3(1), dim3(GFR_BLOCK), 0, s, part, (uint32_t)G, ctl, 1u);
+    GFR_LAUNCH_CHECK();
+
+    PpOp op{contrib};
+    PrFin fin{sum};
+    const int32_t *C = g.C.as<int32_t>();
+    auto launch = [&]() {
+        hipLaunchKernelGGL((gather_chunks<GATHER_CH, PpOp, PrFin>), dim3(G), dim3(GFR_BLOCK), 0, s, g.full,
+                           g.full_counts, g.full_counts + 1, C, op, fin, gs, &ctl->done);
+        hipLaunchKernelGGL((gather_fixup<GATHER_CH, PrFin>), dim3(G), dim3(GFR_BLOCK), 0, s, g.full,
+                           g.full_counts, g.full_counts + 1, fin, gs, &ctl->done);
+        hipLaunchKernelGGL(ppr_finalize, dim3(G), dim3(GFR_BLOCK), 0, s, g.R.as<int32_t>(), n, seed, invk, xa, xb,
+                           contrib, sum, part, ctl);
+        hipLaunchKernelGGL(pr_reduce, dim3(1), dim3(GFR_BLOCK), 0, s, part, (uint32_t)G, ctl, 0u);
+    };
+    const int32_t first = max_iter < 8 ? max_iter : 8;
+    run_until_done(c, &ctl->done, 1u, first, (int64_t)max_iter + 8, s, launch);
+    GFR_HIP(hipMemcpyAsync(&h, ctl, sizeof h, hipMemcpyDeviceToHost, s));
+    GFR_HIP(hipStreamSynchronize(s));
+    const double *xf = (h.iters & 1) ? xb : xa;
+    GFR_HIP(hipMemcpyAsync(rank, xf, 8ull * n, hipMemcpyDeviceToDevice, s));
+    *iters = (int32_t)h.iters;
+    *l1 = h.l1;
+    c.stats.v["iterations"] = h.iters;
+    c.stats.v["l1"] = h.l1;
 }
 
 }  // namespace gfr
