@@ -201,6 +201,60 @@ def prf_error_report(ctx, log, scale=20):
     return rep
 
 
+def rank_leg(ctx, log):
+    """2-hop walk counts on R-MAT s22 (1 and 64 seeds, both directions of the
+    second advance), personalized PageRank on R-MAT s22 from 1 and 64 seeds,
+    SALSA and HITS on a bipartite R-MAT with 2^21 vertices per side; each with
+    a parity sample against the oracle."""
+    import graphgen
+    import oracle
+    out = {}
+    row, col = graphgen.rmat(22)
+    n = row.size - 1
+    g = ctx.graph_load_csr(row, col)
+    seeds64 = graphgen.sample_sources(row, col, 64)
+    for k in (1, 64):
+        S = seeds64[:k]
+        for direction, name in ((1, "push"), (2, "pull"), (0, "auto")):
+            ctx.set_option("twohop.direction", direction)
+            ts = _timed(ctx, lambda: ctx.two_hop(g, S), 5)
+            e = ctx.stat("edges_inspected")
+            out["two_hop_%d_%s" % (k, name)] = {"ms_median": float(np.median(ts)), "edges_inspected": e,
+                                               "gteps": e / (float(np.median(ts)) * 1e-3) / 1e9}
+            log("d6 two_hop", k, name, out["two_hop_%d_%s" % (k, name)])
+        ctx.set_option("twohop.direction", 0)
+        got = ctx.two_hop(g, S).cpu().numpy().view(np.uint64)
+        out["two_hop_%d_bit_exact" % k] = bool(np.array_equal(got, oracle.two_hop(row, col, S)))
+    for k in (1, 64):
+        S = seeds64[:k]
+        ts = _timed(ctx, lambda: ctx.ppr(g, S, 0.85, 1e-9, 1000), 3, warm=1)
+        x, it, l1 = ctx.ppr(g, S, 0.85, 1e-9, 1000)
+        out["ppr_%d" % k] = {"ms_median": float(np.median(ts)), "iterations": it,
+                             "ms_per_iteration": float(np.median(ts)) / it}
+        log("d6 ppr", k, out["ppr_%d" % k])
+    xo, _, _ = oracle.ppr(row, col, seeds64[:1], 0.85, 0.0, out["ppr_1"]["iterations"])
+    x, _, _ = ctx.ppr(g, seeds64[:1], 0.85, 1e-9, 1000)
+    out["ppr_1_l1_vs_oracle"] = float(np.abs(x.cpu().numpy() - xo).sum())
+    g.free()
+    del row, col
+    row, col = graphgen.bipartite_rmat(21)
+    nl = 1 << 21
+    g = ctx.graph_load_csr(row, col)
+    for method in ("salsa", "hits"):
+        fn = getattr(ctx, method)
+        ts = _timed(ctx, lambda: fn(g, nl, 20), 3, warm=1)
+        out[method + "_20_iterations"] = {"ms_median": float(np.median(ts)),
+                                          "ms_per_iteration": float(np.median(ts)) / 20,
+                                          "edges_per_s": 20 * col.size / (float(np.median(ts)) * 1e-3)}
+        h, a = fn(g, nl, 5)
+        ho, ao = getattr(oracle, method)(row, col, nl, 5)
+        out[method + "_5_max_abs_err"] = float(max(np.abs(h.cpu().numpy() - ho).max(), np.abs(a.cpu().numpy() - ao).max()))
+        log("d6", method, out[method + "_20_iterations"], out[method + "_5_max_abs_err"])
+    out["bipartite_graph"] = {"n": int(row.size - 1), "m": int(col.size)}
+    g.free()
+    return out
+
+
 def suite(args, log):
     """The measurement rows of the design: R-MAT s16 BFS launch overhead; the
     R-MAT s22 modes (push BFS, direction-optimizing BFS, SSSP, 64-source
@@ -364,6 +418,10 @@ def suite(args, log):
         del row, col
         rep["d4_rmat20_pagerank_filtered_error"] = prf_error_report(ctx, log)
 
+    if "6" in args.suite_parts:
+        # d.6 the 2-hop advance and the node rankings
+        rep["d6_two_hop_and_ranking"] = rank_leg(ctx, log)
+
     if "5" in args.suite_parts:
         # d.5 serving ladder
         resident = {}
@@ -391,7 +449,7 @@ def main():
     ap.add_argument("--serve-queries", type=int, default=512, help="queries per serving point (0: skip)")
     ap.add_argument("--suite", default="", help="run the full measurement suite and write its JSON here")
     ap.add_argument("--suite-queries", type=int, default=10000, help="serving queries per point in the suite")
-    ap.add_argument("--suite-parts", default="12345", help="suite rows to run (digits of d.1 .. d.5)")
+    ap.add_argument("--suite-parts", default="123456", help="suite rows to run (digits of d.1 .. d.6)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="finish with one device copy of this many MiB (a known-size kernel that "
                          "calibrates the HBM byte counters of a profiler run)")

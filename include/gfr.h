@@ -99,6 +99,7 @@ const char *gfr_last_error(const gfr_ctx *ctx);
  *                     Sec. 4.5): 0 auto, 1 push only, 2 pull only; results do not change
  *   "bc.alpha", "bc.beta"  the same ratios as bfs.alpha / bfs.beta for BC's levels
  *   "twohop.direction" second advance of gfr_two_hop: 0 auto, 1 push, 2 pull
+ *   "twohop.alpha"    auto: pull when the middle vertices' edges exceed m / alpha
  *   "serve.max_batch" largest number of queries the serving runtime runs together (1..64)
  *   "serve.hipgraph"  1 (default): serving sessions replay their rounds of steps from
  *                     hipGraphs captured once per session; 0: plain launches
@@ -240,8 +241,9 @@ gfr_status gfr_pagerank_filtered(gfr_ctx *ctx, gfr_graph g, double damping, doub
  *   count_out[v] = number of walks s - u - v, s in seeds, u in N(s), v in N(u)
  * seeds: host array of k >= 1 distinct vertices.  count_out: n uint64 (device
  * or host memory).  The second advance pushes with 64-bit atomics, or pulls
- * over every list when the middle vertices hold more than a quarter of all
- * edges (option "twohop.direction": 0 auto, 1 push, 2 pull; same result).
+ * over every list when the middle vertices hold more than m / alpha edges
+ * (options "twohop.direction": 0 auto, 1 push, 2 pull, and "twohop.alpha",
+ * default 10; the result is the same).
  * GFR_E_INVALID for an empty, out-of-range or duplicated seed set.
  */
 gfr_status gfr_two_hop(gfr_ctx *ctx, gfr_graph g, const int32_t *seeds, int32_t k,

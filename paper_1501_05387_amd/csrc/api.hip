@@ -295,7 +295,7 @@ static const OptKey kOptKeys[] = {
     {"batch.min_bfs", 1, 1e9, true},     {"batch.min_sssp", 1, 1e9, true},
     {"batch.pull_alpha", 0, 1e6, true},  {"bc.direction", 0, 2, true},
     {"bc.alpha", 1e-6, 1e9, true},       {"bc.beta", 1e-6, 1e9, true},
-    {"twohop.direction", 0, 2, true},
+    {"twohop.direction", 0, 2, true},    {"twohop.alpha", 1e-6, 1e9, true},
     {"serve.budget_bytes", 0, 1e15, false}, {"serve.max_batch", 1, 64, false},
     {"profile.kernels", 0, 1, false}, {"serve.hipgraph", 0, 1, false},
 };
@@ -327,6 +327,7 @@ void option_set(Options &o, const std::string &key, double v)
     else if (key == "bc.alpha") o.bc_alpha = v;
     else if (key == "bc.beta") o.bc_beta = v;
     else if (key == "twohop.direction") o.twohop_direction = (int)v;
+    else if (key == "twohop.alpha") o.twohop_alpha = v;
     else if (key == "serve.budget_bytes") o.serve_budget = v;
     else if (key == "serve.max_batch") o.serve_max_batch = (int)v;
     else if (key == "profile.kernels") o.profile_kernels = (int)v;
@@ -359,6 +360,7 @@ static double option_get(const Options &o, const std::string &key)
     if (key == "bc.alpha") return o.bc_alpha;
     if (key == "bc.beta") return o.bc_beta;
     if (key == "twohop.direction") return o.twohop_direction;
+    if (key == "twohop.alpha") return o.twohop_alpha;
     if (key == "serve.budget_bytes") return o.serve_budget;
     if (key == "serve.max_batch") return o.serve_max_batch;
     if (key == "serve.hipgraph") return o.serve_graphs;

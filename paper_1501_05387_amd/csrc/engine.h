@@ -132,6 +132,7 @@ struct Options {
     double bc_alpha = 15.0;     // push -> pull when level edges > unvisited edges / alpha (growing)
     double bc_beta = 18.0;      // pull -> push when level size < n / beta (shrinking)
     int twohop_direction = 0;   // 2-hop second advance: 0 auto, 1 push, 2 pull
+    double twohop_alpha = 10.0; // auto: pull when the middle frontier's edges exceed m / alpha
 };
 
 // Options from a tuning file: context-wide values and per-graph-class values.

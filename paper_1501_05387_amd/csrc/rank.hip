@@ -10,10 +10,11 @@
 //      atomics), marking u;
 //   3. the marked vertices become the middle frontier (compaction);
 //   4. push: advance over the middle frontier's edges, count(v) += c1(u)
-//      (64-bit atomics); or pull, when the middle frontier holds more than a
-//      quarter of all edges: every vertex gathers the sum of c1 over its
-//      list with the segmented FP64 gather, exact because every partial sum
-//      is an integer below 2^53.
+//      (64-bit atomics, ~13 G/s on MI355X); or pull, when the middle
+//      frontier holds more than m / alpha edges (default alpha 10: a pull
+//      sweep of all m edges runs near 125 G edges/s): every vertex gathers
+//      the sum of c1 over its list with the segmented FP64 gather, exact
+//      because every partial sum is an integer below 2^53.
 //
 // SALSA / HITS on a bipartite graph (hubs [0, nl), authorities [nl, n)):
 // each side is a frontier queue built once; an iteration is a gather over
@@ -191,7 +192,7 @@ void run_two_hop(Ctx &c, Graph &g, const int32_t *seeds, int32_t k, uint64_t *co
     GFR_HIP(hipStreamSynchronize(s));
     const uint32_t mf1 = c.pinned[0], mf2 = c.pinned[2];
     const int force = c.opt.twohop_direction;
-    const bool pull = force == 2 || (force == 0 && (double)mf2 > (double)g.m / 4.0);
+    const bool pull = force == 2 || (force == 0 && (double)mf2 > (double)g.m / c.opt.twohop_alpha);
     unsigned long long *cnt = (unsigned long long *)count;
     if (pull) {
         hipLaunchKernelGGL((gather_chunks<GATHER_CH, Hop2PullOp, Hop2Fin>), dim3(G), dim3(GFR_BLOCK), 0, s, g.full,
