@@ -55,8 +55,9 @@ def bfs_bytes(st: dict, solves: int, n: int) -> float:
 def bsssp_bytes(st: dict, n: int) -> float:
     """Algorithmic bytes of bsssp_relax (64 queries per pass): per edge visit the
     column and weight (8 B) and the target's 256-byte distance row; per
-    improvement one 4-byte atomic and one mark byte."""
-    return (8 + 256) * st["relaxations"] + 5 * st["improvements"]
+    improvement one 4-byte atomic.  (The 8-byte query-mask atomicOr of an
+    improved edge visit is left out, so the figure is a lower bound.)"""
+    return (8 + 256) * st["relaxations"] + 4 * st["improvements"]
 
 
 def msbfs_bytes(st: dict, n: int) -> float:

@@ -10,8 +10,9 @@
 // single-source SSSP; the queries share the near/far bucket bound of the
 // priority queue (Sec. 4.5), which only changes the schedule, not the result.
 //
-// Marks are bytes: mark[v][q] for the (vertex, query) pairs improved in an
-// iteration plus any[v] for the vertex, written with plain stores.
+// Marks: per vertex a 64-bit mask of the queries improved in an iteration
+// (one atomicOr of the wave's ballot per improved edge, not one byte store
+// per improving lane) plus a byte any[v] for the compaction's scan.
 //
 // Every iteration is two launches:
 //   bsssp_relax   load-balanced edge chunks over the near queue; each wave
@@ -59,7 +60,7 @@ struct BsArgs {
     uint32_t nwords;
     uint32_t *D;                 // [n][64]
     unsigned long long *qm;      // query mask of every queued vertex
-    uint8_t *nmark, *fmark;      // [n][64]
+    unsigned long long *nq, *fq; // [n] queries improved into the near / far set
     uint8_t *nany, *fany;        // [n] (padded)
     FrontierQ q;
     uint32_t *part;              // per work-group [improvements, far marks written]
@@ -140,12 +141,15 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
                 if (imp) {
                     atomicMin(a.D + (size_t)v * 64 + lane, nd);
                     ++nimp;
-                    (near_imp ? a.nmark : a.fmark)[(size_t)v * 64 + lane] = 1;
                 }
                 const uint64_t bn = ballot(near_imp), bf = ballot(far_imp);
                 if (lane == 0) {
-                    if (bn) a.nany[v] = 1;
+                    if (bn) {
+                        atomicOr(a.nq + v, (unsigned long long)bn);
+                        a.nany[v] = 1;
+                    }
                     if (bf) {
+                        atomicOr(a.fq + v, (unsigned long long)bf);
                         a.fany[v] = 1;
                         ++nfar;
                     }
@@ -246,12 +250,15 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_pull(BsArgs a)
             if (imp) {
                 atomicMin(a.D + (size_t)cur * 64 + lane, acc);
                 ++nimp;
-                (near_imp ? a.nmark : a.fmark)[(size_t)cur * 64 + lane] = 1;
             }
             const uint64_t bn = ballot(near_imp), bf = ballot(far_imp);
             if (lane == 0) {
-                if (bn) a.nany[cur] = 1;
+                if (bn) {
+                    atomicOr(a.nq + cur, (unsigned long long)bn);
+                    a.nany[cur] = 1;
+                }
                 if (bf) {
+                    atomicOr(a.fq + cur, (unsigned long long)bf);
                     a.fany[cur] = 1;
                     ++nfar;
                 }
@@ -355,18 +362,6 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_pull(BsArgs a)
 }
 
 // 64 mark bytes (0/1) of one vertex -> query mask; clears them when `clear`
-__device__ __forceinline__ unsigned long long row_mask(uint8_t *p, bool clear)
-{
-    unsigned long long m = 0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const uint32_t part = marks_to_mask(p + 32 * h);
-        m |= (unsigned long long)part << (32 * h);
-        if (clear && part) clear_marks(p + 32 * h);
-    }
-    return m;
-}
-
 struct BsMarks {
     BsArgs a;
     uint32_t nparts;
@@ -389,7 +384,8 @@ struct BsMarks {
                 const int bi = __ffs(bits) - 1;
                 bits &= bits - 1;
                 const uint32_t v = w * 32u + bi;
-                const unsigned long long qv = row_mask(a.nmark + (size_t)v * 64, true);
+                const unsigned long long qv = a.nq[v];
+                a.nq[v] = 0ull;
                 a.qm[v] = qv;
                 actq |= qv;
             }
@@ -406,13 +402,12 @@ struct BsMarks {
             const int bi = __ffs(bits) - 1;
             bits &= bits - 1;
             const uint32_t v = w * 32u + bi;
-            unsigned long long fm = row_mask(a.fmark + (size_t)v * 64, false), nm = 0, left = 0;
+            unsigned long long fm = a.fq[v], nm = 0, left = 0;
             while (fm) {
                 const int qq = __ffsll(fm) - 1;
                 fm &= fm - 1;
                 const uint32_t d = a.D[(size_t)v * 64 + qq];
                 if (d < hi) {
-                    a.fmark[(size_t)v * 64 + qq] = 0;
                     if (d >= lo) nm |= 1ull << qq;
                 } else {
                     left |= 1ull << qq;
@@ -420,6 +415,7 @@ struct BsMarks {
                     kmin = min(kmin, d);
                 }
             }
+            a.fq[v] = left;
             if (!left) a.fany[v] = 0;
             if (nm) {
                 a.qm[v] = nm;
@@ -560,7 +556,7 @@ __global__ void bsssp_init(BsArgs a, const int32_t *src, int32_t k, uint32_t del
         for (int32_t q = 0; q < k; ++q) {
             const int32_t v = src[q];
             a.D[(size_t)v * 64 + q] = 0u;
-            a.nmark[(size_t)v * 64 + q] = 1;
+            a.nq[v] |= 1ull << q;
             a.nany[v] = 1;
         }
         BsCtl *ctl = a.ctl;
@@ -625,7 +621,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     uint32_t delta = 0xFFFFFFFFu;
     if (c.opt.batch_delta > 0) delta = (uint32_t)c.opt.batch_delta;
     else if (c.opt.batch_delta_factor > 0) delta = sssp_auto_delta(g, c.opt.batch_delta_factor);
-    c.arena.reserve(al256(256ull * n) + al256(8ull * n) + 2 * al256(64ull * n) + 2 * al256(32ull * nwords) +
+    c.arena.reserve(al256(256ull * n) + al256(8ull * n) + 2 * al256(8ull * n) + 2 * al256(32ull * nwords) +
                     3 * al256(4ull * n) + al256(4 * nparts) + al256(8ull * G) + al256(16ull * cg.blocks) +
                     al256(sizeof(BsCtl)) + al256(4 * 64) + al256(8ull * cg.blocks) + al256(4ull * nwords));
     BsArgs a;
@@ -636,8 +632,8 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     a.nwords = nwords;
     a.D = c.arena.take<uint32_t>(64ull * n);
     a.qm = c.arena.take<unsigned long long>(n);
-    a.nmark = c.arena.take<uint8_t>(64ull * n);
-    a.fmark = c.arena.take<uint8_t>(64ull * n);
+    a.nq = c.arena.take<unsigned long long>(n);
+    a.fq = c.arena.take<unsigned long long>(n);
     a.nany = c.arena.take<uint8_t>(32ull * nwords);
     a.fany = c.arena.take<uint8_t>(32ull * nwords);
     a.q.v = c.arena.take<int32_t>(n);
@@ -657,8 +653,8 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     for (int32_t g0 = 0; g0 < k; g0 += 64) {
         const int32_t kk = std::min<int32_t>(64, k - g0);
         fill_u32(a.D, 0xFFFFFFFFu, 64ull * n, s);
-        fill_u32(a.nmark, 0u, 16ull * n, s);
-        fill_u32(a.fmark, 0u, 16ull * n, s);
+        fill_u32(a.nq, 0u, 2ull * n, s);
+        fill_u32(a.fq, 0u, 2ull * n, s);
         fill_u32(a.nany, 0u, 8ull * nwords, s);
         fill_u32(a.fany, 0u, 8ull * nwords, s);
         fill_u32(a.part, 0u, 2ull * G, s);
@@ -726,7 +722,7 @@ __global__ void bs_admit(BsArgs a, const int32_t *pairs, int32_t count)
     for (int32_t i = 0; i < count; ++i) {
         const int32_t q = pairs[2 * i], src = pairs[2 * i + 1];
         a.D[(size_t)src * 64 + q] = 0u;
-        a.nmark[(size_t)src * 64 + q] = 1;
+        a.nq[src] |= 1ull << q;
         a.nany[src] = 1;
     }
     BsCtl *ctl = a.ctl;
@@ -762,7 +758,7 @@ struct BsLayout {
     size_t n, nwords, nparts, G, blocks;
     size_t total() const
     {
-        return al256(256 * n) + al256(8 * n) + 2 * al256(64 * n) + 2 * al256(32 * nwords) + 3 * al256(4 * n) +
+        return al256(256 * n) + al256(8 * n) + 2 * al256(8 * n) + 2 * al256(32 * nwords) + 3 * al256(4 * n) +
                al256(4 * nparts) + al256(8 * G) + al256(16 * blocks) + al256(sizeof(BsCtl)) + al256(8 * blocks) +
                al256(4 * 128) + al256(4 * 64 * n) + al256(4 * nwords);
     }
@@ -820,8 +816,8 @@ struct BsSession final : LaneSession {
         a.nwords = nwords;
         a.D = (uint32_t *)take(256 * L.n);
         a.qm = (unsigned long long *)take(8 * L.n);
-        a.nmark = (uint8_t *)take(64 * L.n);
-        a.fmark = (uint8_t *)take(64 * L.n);
+        a.nq = (unsigned long long *)take(8 * L.n);
+        a.fq = (unsigned long long *)take(8 * L.n);
         a.nany = (uint8_t *)take(32 * L.nwords);
         a.fany = (uint8_t *)take(32 * L.nwords);
         a.q.v = (int32_t *)take(4 * L.n);
@@ -839,8 +835,8 @@ struct BsSession final : LaneSession {
         a.full_nf = (uint32_t)g.full_nf;
         a.full_mf = (uint32_t)g.m;
         fill_u32(a.D, 0xFFFFFFFFu, 64 * L.n, stream);
-        fill_u32(a.nmark, 0u, 16 * L.n, stream);
-        fill_u32(a.fmark, 0u, 16 * L.n, stream);
+        fill_u32(a.nq, 0u, 2 * L.n, stream);
+        fill_u32(a.fq, 0u, 2 * L.n, stream);
         fill_u32(a.nany, 0u, 8 * L.nwords, stream);
         fill_u32(a.fany, 0u, 8 * L.nwords, stream);
         fill_u32(a.part, 0u, 2 * L.G, stream);
