@@ -18,7 +18,8 @@
 //   bsssp_relax   load-balanced edge chunks over the near queue; each wave
 //                 takes a quarter of the chunk, 64 edges at a time: lane l
 //                 fetches edge l's target, weight, source and query mask
-//                 (coalesced), then the wave relaxes the 64 edges eight at a
+//                 (coalesced; the next group's fetch is issued before the
+//                 current group relaxes), then the wave relaxes the 64 edges eight at a
 //                 time with their sixteen distance rows in flight; a group
 //                 whose 64 edges all leave one vertex loads that vertex's
 //                 row once and relaxes sixteen edges at a time.
@@ -106,24 +107,30 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
         const uint32_t eb = e0 + wave * QW, ee = min(eb + QW, e1);
         if (eb >= ee) continue;
         int ilo = upper_index(s_off, 0, cnt - 1, eb);
+        // lane l of a group describes edge e + l (target, weight, source, query
+        // mask); the next group's loads are issued before this group relaxes
+        auto fetch = [&](uint32_t e, int nbx, int32_t &vx, int32_t &wx, int32_t &ux, unsigned long long &qx) {
+            const uint32_t el = e + (uint32_t)min(lane, nbx - 1);
+            const int il = upper_index(s_off, ilo, min(cnt - 1, ilo + lane + 1), el);
+            const int32_t idx = s_row[il] + (int32_t)(el - s_off[il]);
+            vx = a.C[idx];
+            wx = (int32_t)a.W[idx];
+            ux = s_v[il];
+            qx = a.qm[ux];
+            ilo = lane_bcast(il, nbx - 1);
+        };
+        int nbn = (int)min(64u, ee - eb);
+        int32_t vn, wn, un;
+        unsigned long long qn;
+        fetch(eb, nbn, vn, wn, un, qn);
         for (uint32_t e = eb; e < ee; e += 64) {
-            // lane l describes edge e + l: its target, weight, source and the
-            // source's query mask.  ilo holds edge e - 1 (or e), and every
-            // queued vertex has an edge, so edge e + l lies in entry
-            // ilo + l + 1 at the latest.
-            const int nb = (int)min(64u, ee - e);
-            int32_t vl = 0, wl = 0, ul = 0, il = ilo;
-            unsigned long long ql = 0;
-            if (lane < nb) {
-                const uint32_t el = e + lane;
-                il = upper_index(s_off, ilo, min(cnt - 1, ilo + lane + 1), el);
-                const int32_t idx = s_row[il] + (int32_t)(el - s_off[il]);
-                vl = a.C[idx];
-                wl = (int32_t)a.W[idx];
-                ul = s_v[il];
-                ql = a.qm[ul];
+            const int nb = nbn;
+            const int32_t vl = vn, wl = wn, ul = un;
+            const unsigned long long ql = qn;
+            if (e + 64 < ee) {
+                nbn = (int)min(64u, ee - (e + 64));
+                fetch(e + 64, nbn, vn, wn, un, qn);
             }
-            ilo = lane_bcast(il, nb - 1);
             const int32_t qlo = (int32_t)(uint32_t)ql, qhi = (int32_t)(uint32_t)(ql >> 32);
             // one relaxation of edge (u, v, w) for this lane's query; the test
             // is computed for every lane, so that no load is moved into a
