@@ -18,9 +18,16 @@
 //                   vertex rarely finds all of them early, so the sweep is
 //                   balanced over edges rather than cut short per vertex.
 //   msbfs_finalize  lane = vertex: new = nx[v]; vis |= new; fr = new; the
-//                   depths L+1 are written row by row of the [k][n] output,
-//                   64 consecutive vertices per store, and the vertex gets a
-//                   mark byte if its mask is non-empty.
+//                   new mask is kept as the per-level record lvl[L+1][v]
+//                   (one coalesced 8-byte store per vertex), and the vertex
+//                   gets a mark byte if its mask is non-empty.  Past the
+//                   record's capacity (and in serving sessions) the depths
+//                   L+1 are written straight into the [k][n] output instead.
+//   after the traversal, msbfs_output turns the level records into the
+//   depth rows: every output line is written once and whole (writing each
+//   level's depths into the rows left partial lines, level after level,
+//   which ran at a fifth of the write bandwidth), and -1 goes where a source
+//   never reached the vertex, so the output needs no fill.
 //   compact         queue of the new frontier + level control (compact.h).
 #include <algorithm>
 #include <vector>
@@ -55,6 +62,8 @@ struct MsArgs {
     uint8_t *mark;
     int32_t *depth;    // [k][n]
     int32_t k;
+    unsigned long long *lvl;        // [lvl_cap][n] new-vertex masks per depth (null: write depths directly)
+    int32_t lvl_cap;
     unsigned long long allq;
     const int32_t *base;            // [64] depth written = level + 1 - base[lane]
     unsigned long long *actp;       // [gridDim of finalize] per-group OR of the new frontier masks
@@ -164,8 +173,8 @@ __global__ __launch_bounds__(GFR_BLOCK) void msbfs_level(MsArgs a)
 }
 
 // lane = vertex: fold the next-frontier masks into visited / frontier, write
-// depths L+1 row by row (64 consecutive vertices per store), mark non-empty
-// vertices for the compaction.
+// the level record (or depths L+1 row by row, 64 consecutive vertices per
+// store), mark non-empty vertices for the compaction.
 __global__ __launch_bounds__(GFR_BLOCK) void msbfs_finalize(MsArgs a)
 {
     MsCtl *ctl = a.ctl;
@@ -195,6 +204,10 @@ __global__ __launch_bounds__(GFR_BLOCK) void msbfs_finalize(MsArgs a)
             any |= ((unsigned long long)hi << 32) | lo;
         }
         act |= any;
+        if (a.lvl && L + 1 < a.lvl_cap) {   // uniform: record the level, rows come later
+            if (v < a.n) a.lvl[(size_t)(L + 1) * a.n + v] = nw;
+            continue;
+        }
         while (any) {
             const int qq = __ffsll(any) - 1;
             any &= any - 1;
@@ -208,6 +221,50 @@ __global__ __launch_bounds__(GFR_BLOCK) void msbfs_finalize(MsArgs a)
         unsigned long long t = 0;
         for (int i = 0; i < GFR_WAVES; ++i) t |= s_act[i];
         a.actp[blockIdx.x] = t;
+    }
+}
+
+// Depth rows from the level records of depths 0 .. nlev-1, lane = vertex.
+// All records of the vertex are loaded first (clamped to the last valid one,
+// then masked), folded into five bit planes (plane b = OR of the records
+// whose depth has bit b set) and a found mask, so the depth of source q is
+// read off bit q of the planes.  Then 64 coalesced row stores: -1 where the
+// source never reached the vertex, the depth where a record holds it.
+// Entries reached deeper than the records were written during the traversal
+// and are left alone.
+constexpr int32_t MS_LVL_CAP = 24;   // depths kept as records (5 bit planes cover them)
+constexpr int32_t MS_DEEP = INT32_MIN;
+static_assert(MS_LVL_CAP <= 32, "five bit planes hold depths below 32");
+
+__global__ __launch_bounds__(GFR_BLOCK) void msbfs_output(MsArgs a, int32_t nlev)
+{
+    const int32_t kq = a.k;
+    const size_t n = (size_t)a.n;
+    for (size_t v = (size_t)blockIdx.x * GFR_BLOCK + threadIdx.x; v - threadIdx.x < n;
+         v += (size_t)gridDim.x * GFR_BLOCK) {
+        const bool ok = v < n;
+        const size_t vc = ok ? v : n - 1;
+        unsigned long long rec[MS_LVL_CAP];
+#pragma unroll
+        for (int d = 0; d < MS_LVL_CAP; ++d) rec[d] = a.lvl[(size_t)min(d, nlev - 1) * n + vc];
+        unsigned long long plane[5] = {0, 0, 0, 0, 0}, found = 0;
+#pragma unroll
+        for (int d = 0; d < MS_LVL_CAP; ++d) {
+            const unsigned long long r = d < nlev ? rec[d] : 0ull;
+            found |= r;
+#pragma unroll
+            for (int bit = 0; bit < 5; ++bit)
+                if ((d >> bit) & 1) plane[bit] |= r;
+        }
+        const unsigned long long vis = a.vis[vc];
+        for (int q = 0; q < kq; ++q) {
+            int32_t d = 0;
+#pragma unroll
+            for (int bit = 0; bit < 5; ++bit) d |= (int32_t)((plane[bit] >> q) & 1ull) << bit;
+            const bool rec_q = (found >> q) & 1ull, seen = (vis >> q) & 1ull;
+            const int32_t x = rec_q ? d - a.base[q] : (seen ? MS_DEEP : -1);
+            if (ok && x != MS_DEEP) a.depth[(size_t)q * n + v] = x;
+        }
     }
 }
 
@@ -288,8 +345,10 @@ void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t 
     const size_t nparts = (size_t)(g.m / chunk) + 2;
     const int G = grid_blocks(c, 5);   // the level kernel (28.7 KB of LDS) fits five work-groups per CU
     const CompactGeom cg = compact_geom(nwords, c.num_cu);
+    // level records: 8 bytes per vertex and depth, for the first MS_LVL_CAP depths
     c.arena.reserve(3 * al256(8ull * n) + al256(32ull * nwords) + 3 * al256(4ull * n) + al256(4 * nparts) +
-                    al256(16ull * cg.blocks) + al256(sizeof(MsCtl)) + 2 * al256(4 * 64) + al256(8ull * G));
+                    al256(16ull * cg.blocks) + al256(sizeof(MsCtl)) + 2 * al256(4 * 64) + al256(8ull * G) +
+                    al256(8ull * n * MS_LVL_CAP));
     MsArgs a;
     a.R = g.R.as<int32_t>();
     a.C = g.C.as<int32_t>();
@@ -313,6 +372,8 @@ void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t 
     a.base = base;
     a.actp = c.arena.take<unsigned long long>(G);
     a.nactp = (uint32_t)G;
+    a.lvl = c.arena.take<unsigned long long>((size_t)n * MS_LVL_CAP);
+    a.lvl_cap = MS_LVL_CAP;
     fill_u32(base, 0u, 64, s);
     double levels = 0, pull_levels = 0, push_edges = 0;
     for (int32_t g0 = 0; g0 < k; g0 += 64) {
@@ -325,7 +386,6 @@ void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t 
         fill_u32(a.nx, 0u, 2ull * n, s);
         fill_u32(a.mark, 0u, 8ull * nwords, s);
         fill_u32(status, 0u, 4ull * cg.blocks, s);
-        fill_u32(a.depth, 0xFFFFFFFFu, (size_t)kk * n, s);
         GFR_HIP(hipMemcpyAsync(dsrc, sources + g0, 4ull * kk, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(msbfs_init, dim3(1), dim3(64), 0, s, a, dsrc, (float)c.opt.msbfs_alpha);
         GFR_LAUNCH_CHECK();
@@ -347,6 +407,12 @@ void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t 
         GFR_HIP(hipStreamSynchronize(s));
         memcpy(&h, c.pinned, sizeof(MsCtl));
         if (h.err) fail(GFR_E_DEVICE, "bfs_batch: frontier compaction look-back timed out");
+        // depths 0 .. h.level were recorded (the last record is the empty frontier)
+        const int32_t nlev = std::min<int32_t>(MS_LVL_CAP, h.level + 1);
+        c.ktimer.run("msbfs_output", s, [&]() {
+            hipLaunchKernelGGL(msbfs_output, dim3(grid_blocks(c, 8)), dim3(GFR_BLOCK), 0, s, a, nlev);
+        });
+        GFR_LAUNCH_CHECK();
         levels += h.level;
         pull_levels += (double)h.pull_levels;
         push_edges += (double)h.push_edges;
