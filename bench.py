@@ -445,7 +445,7 @@ def main():
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--edge-factor", type=int, default=16)
     ap.add_argument("--sources", type=int, default=64)
-    ap.add_argument("--cpu-sources", type=int, default=4, help="oracle sample size (sources)")
+    ap.add_argument("--cpu-sources", type=int, default=5, help="oracle sample size (sources, about 12 s of CPU work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-queries", type=int, default=512, help="queries per serving point (0: skip)")
     ap.add_argument("--suite", default="", help="run the full measurement suite and write its JSON here")
