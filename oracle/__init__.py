@@ -10,6 +10,8 @@ Every function follows a textbook definition named in the paper:
 
 * ``bfs``       hop distance from a source (Sec. 5.1), FIFO-queue BFS.
 * ``sssp``      non-negative-weight shortest paths (Sec. 4.1, Sec. 5.2), Dijkstra.
+* ``bfs_pred``, ``sssp_pred``  the distances plus a predecessor per vertex (the
+  first neighbour in its row one step closer to the source).
 * ``bc``        Brandes' two-pass betweenness (Sec. 5.3), FP64.
 * ``cc``        component labels (Sec. 5.4), union-find, label = min vertex id.
 * ``pagerank``  FP64 power iteration (Sec. 5.5), uniform dangling redistribution.
@@ -21,7 +23,7 @@ Every function follows a textbook definition named in the paper:
 * ``salsa``, ``hits``  bipartite node rankings (hubs left, authorities right),
   the rankings Sec. 5.5 lists as built on the same advance.
 
-All ten are pinned against brute force, closed forms, library routines and
+All twelve are pinned against brute force, closed forms, library routines and
 invariants in ``tests/test_oracle_pins.py``.
 """
 from __future__ import annotations
@@ -66,6 +68,10 @@ class Oracle:
         lib.or_pagerank.argtypes = [i32, vp, vp, f64, f64, i32, vp, vp, vp]
         lib.or_pagerank_filtered.restype = i32
         lib.or_pagerank_filtered.argtypes = [i32, vp, vp, f64, f64, i32, vp, vp, vp, vp]
+        lib.or_bfs_pred.restype = i64
+        lib.or_bfs_pred.argtypes = [i32, vp, vp, i32, vp, vp]
+        lib.or_sssp_pred.restype = i64
+        lib.or_sssp_pred.argtypes = [i32, vp, vp, vp, i32, vp, vp]
         lib.or_two_hop.restype = i32
         lib.or_two_hop.argtypes = [i32, vp, vp, vp, i32, vp]
         lib.or_ppr.restype = i32
@@ -97,6 +103,29 @@ class Oracle:
         if rc < 0:
             raise ValueError("oracle.sssp: bad input")
         return dist
+
+    def bfs_pred(self, row, col, src: int):
+        """(int32 depths, int32 predecessors): pred[src] = src, -1 unreached, else the first
+        neighbour in the row one level up."""
+        row, col = _c(row, np.int32), _c(col, np.int32)
+        n = row.size - 1
+        depth, pred = np.empty(n, np.int32), np.empty(n, np.int32)
+        if self.lib.or_bfs_pred(n, _p(row), _p(col), int(src), _p(depth), _p(pred)) < 0:
+            raise ValueError("oracle.bfs_pred: bad input")
+        return depth, pred
+
+    def sssp_pred(self, row, col, w, src: int):
+        """(uint32 distances, int32 predecessors): the first neighbour u in the row with
+        dist[u] + w = dist[v]."""
+        row, col, w = _c(row, np.int32), _c(col, np.int32), _c(w, np.uint32)
+        n = row.size - 1
+        dist, pred = np.empty(n, np.uint32), np.empty(n, np.int32)
+        rc = self.lib.or_sssp_pred(n, _p(row), _p(col), _p(w), int(src), _p(dist), _p(pred))
+        if rc == -2:
+            raise OverflowError("oracle.sssp_pred: a distance does not fit in uint32")
+        if rc < 0:
+            raise ValueError("oracle.sssp_pred: bad input")
+        return dist, pred
 
     def bc(self, row, col, sources) -> np.ndarray:
         """FP64 betweenness summed over ``sources`` (unnormalised, ordered pairs)."""
@@ -225,6 +254,14 @@ def pagerank(row, col, damping: float = 0.85, tol: float = 1e-6, max_iter: int =
 
 def pagerank_filtered(row, col, damping: float, vertex_tol: float, max_iter: int = 1000):
     return default().pagerank_filtered(row, col, damping, vertex_tol, max_iter)
+
+
+def bfs_pred(row, col, src: int):
+    return default().bfs_pred(row, col, src)
+
+
+def sssp_pred(row, col, w, src: int):
+    return default().sssp_pred(row, col, w, src)
 
 
 def two_hop(row, col, seeds):

@@ -11,6 +11,7 @@
  * Output conventions (fixed here because the paper leaves them open):
  *   BFS   depth int32, source 0, unreached -1.
  *   SSSP  dist uint32, source 0, unreached 0xFFFFFFFF; sums formed in uint64.
+ *   pred  source -> itself, unreached -1, else the first neighbour one step closer.
  *   BC    unnormalised sum over ordered pairs (s in S, t in V), no halving.
  *   CC    label = smallest vertex id of the component.
  *   PR    uniform teleport (1-d)/N, dangling mass spread uniformly, L1 stop.
@@ -131,6 +132,60 @@ OR_EXPORT int64_t or_sssp(int32_t n, const int32_t *R, const int32_t *C, const u
         else dist[v] = (uint32_t)d[v];
     }
     free(d); free(done); free(heap);
+    return rc;
+}
+
+/* ----------------------------------------------------- predecessors ---- */
+/*
+ * Predecessors read off the distances (a BFS tree, Sec. 5.1, and a
+ * shortest-path tree, Sec. 5.2): pred[src] = src, -1 where unreached, and
+ * otherwise the first neighbour u in v's list that lies one step closer:
+ * depth[u] = depth[v] - 1 for BFS, dist[u] + w(v,u) = dist[v] for SSSP (the
+ * smallest such id when rows are sorted).  The distances come from or_bfs /
+ * or_sssp and are returned too.  Same return codes as those.
+ */
+OR_EXPORT int64_t or_bfs_pred(int32_t n, const int32_t *R, const int32_t *C, int32_t src, int32_t *depth,
+                              int32_t *pred)
+{
+    const int64_t rc = or_bfs(n, R, C, src, depth);
+    if (rc < 0) return rc;
+    for (int32_t v = 0; v < n; ++v) {
+        pred[v] = -1;
+        if (depth[v] < 0) continue;
+        if (v == src) {
+            pred[v] = src;
+            continue;
+        }
+        for (int32_t e = R[v]; e < R[v + 1]; ++e) {
+            if (depth[C[e]] == depth[v] - 1) {
+                pred[v] = C[e];
+                break;
+            }
+        }
+    }
+    return rc;
+}
+
+OR_EXPORT int64_t or_sssp_pred(int32_t n, const int32_t *R, const int32_t *C, const uint32_t *W, int32_t src,
+                               uint32_t *dist, int32_t *pred)
+{
+    const int64_t rc = or_sssp(n, R, C, W, src, dist);
+    if (rc < 0) return rc;
+    for (int32_t v = 0; v < n; ++v) {
+        pred[v] = -1;
+        if (dist[v] == 0xFFFFFFFFu) continue;
+        if (v == src) {
+            pred[v] = src;
+            continue;
+        }
+        for (int32_t e = R[v]; e < R[v + 1]; ++e) {
+            const int32_t u = C[e];
+            if (dist[u] != 0xFFFFFFFFu && (uint64_t)dist[u] + W[e] == (uint64_t)dist[v]) {
+                pred[v] = u;
+                break;
+            }
+        }
+    }
     return rc;
 }
 

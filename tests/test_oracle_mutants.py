@@ -44,6 +44,8 @@ MUTANTS = [
     ("prf_frozen_keep_old_value", "x[v] = y[v];\n            if (dx >= vertex_tol) ++in_frontier;\n            else active[v] = 0;",
      "if (dx >= vertex_tol) { ++in_frontier; x[v] = y[v]; }\n            else active[v] = 0;"),
     ("prf_gauss_seidel", "if (active[v]) y[v] = pr_update(", "if (active[v]) x[v] = y[v] = pr_update("),
+    ("bfs_pred_last_match", "pred[v] = C[e];\n                break;", "pred[v] = C[e];"),
+    ("sssp_pred_any_closer_neighbour", "(uint64_t)dist[u] + W[e] == (uint64_t)dist[v]", "(uint64_t)dist[u] < (uint64_t)dist[v]"),
     ("two_hop_counts_middle_vertex", "for (int32_t f = R[u]; f < R[u + 1]; ++f) count[C[f]] += 1;",
      "for (int32_t f = R[u]; f < R[u + 1]; ++f) count[u] += 1;"),
     ("two_hop_one_hop_only", "for (int32_t f = R[u]; f < R[u + 1]; ++f) count[C[f]] += 1;", "count[u] += 1;"),

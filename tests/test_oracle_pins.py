@@ -74,6 +74,21 @@ def pin_exhaustive(O, nmax=5, seed=0):
             for s in range(n):
                 want = np.where(np.isfinite(DW[s]), DW[s], 0xFFFFFFFF).astype(np.uint32)
                 assert np.array_equal(O.sssp(rowW, colW, wW, s), want), (n, Wm.tolist(), s)
+            # predecessors: the smallest neighbour one step closer (rows are sorted)
+            for s in range(n):
+                dep, pred = O.bfs_pred(row, col, s)
+                _, predw = O.sssp_pred(rowW, colW, wW, s)
+                for v in range(n):
+                    if not np.isfinite(D[s][v]):
+                        assert pred[v] == -1 and predw[v] == -1
+                        continue
+                    if v == s:
+                        assert pred[v] == s and predw[v] == s
+                        continue
+                    up = [u for u in range(n) if A[u, v] and D[s][u] == D[s][v] - 1]
+                    assert pred[v] == min(up), (A.tolist(), s, v)
+                    upw = [u for u in range(n) if Wm[u, v] and DW[s][u] + Wm[u, v] == DW[s][v]]
+                    assert predw[v] == min(upw), (Wm.tolist(), s, v)
             # CC labels = smallest reachable id
             lab, k = O.cc(row, col)
             want = brute.component_min_labels(D)
@@ -193,6 +208,18 @@ def pin_invariants(O):
         # unit weights turn SSSP into BFS
         assert np.array_equal(O.sssp(row, col, np.ones_like(w), s).astype(np.int64),
                               np.where(d >= 0, d.astype(np.int64), 0xFFFFFFFF))
+        # predecessor trees: a neighbour one step closer, and every chain ends at the source
+        dep, pred = O.bfs_pred(row, col, s)
+        dist2, predw = O.sssp_pred(row, col, w, s)
+        assert np.array_equal(dep, d) and np.array_equal(dist2, dist)
+        for p_, key in ((pred, d.astype(np.int64)), (predw, np.where(dist == 0xFFFFFFFF, -1, dist.astype(np.int64)))):
+            reached = key >= 0
+            assert np.array_equal(p_ >= 0, reached) and p_[s] == s
+            v = np.nonzero(reached & (np.arange(n) != s))[0]
+            u = p_[v]
+            assert np.all(key[u] < key[v])            # strictly closer (weights >= 1)
+            nb = set(zip(np.repeat(np.arange(n), np.diff(row)).tolist(), col.tolist()))
+            assert all((int(a), int(b)) in nb for a, b in zip(v[:2000], u[:2000]))
     lab, k = O.cc(row, col)
     assert inv.check_cc(row, col, lab) == k
     bcv = O.bc(row, col, srcs)
