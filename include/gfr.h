@@ -165,21 +165,27 @@ gfr_status gfr_graph_info(gfr_ctx *ctx, gfr_graph g, int32_t *n, int64_t *m,
  * Breadth-first search (Sec. 5.1): depth_out[v] = hop distance from `source`,
  * depth_out[source] = 0, unreached vertices -1.  n int32 elements.
  * Level-synchronous advance + filter with a per-level push/pull choice.
+ * pred_out (n int32, may be NULL): a BFS tree read off the depths --
+ * pred[source] = source, unreached -1, otherwise the first neighbour in v's
+ * row one level up (the smallest such id when rows are sorted).
  * GFR_E_INVALID if source is outside [0,n).
  */
 gfr_status gfr_bfs(gfr_ctx *ctx, gfr_graph g, int32_t source, int32_t *depth_out,
-                   gfr_stream stream);
+                   int32_t *pred_out, gfr_stream stream);
 
 /*
  * Single-source shortest paths with non-negative integer weights
  * (Sec. 4.1 Algorithm 1, Sec. 5.2): dist_out[v] = minimum path weight,
  * dist_out[source] = 0, unreached 0xFFFFFFFF.  n uint32 elements.
- * Near/far priority-queue split (Sec. 4.5).  GFR_E_INVALID if the graph has
- * no weights, the source is out of range, or a distance would not fit below
- * 0xFFFFFFFF.
+ * Near/far priority-queue split (Sec. 4.5).  pred_out (n int32, may be
+ * NULL): pred[source] = source, unreached -1, otherwise the first neighbour u
+ * in v's row with dist[u] + w(u,v) = dist[v] (with zero-weight edges the
+ * pointers may form cycles among equal distances; with positive weights they
+ * form a shortest-path tree).  GFR_E_INVALID if the graph has no weights, the
+ * source is out of range, or a distance would not fit below 0xFFFFFFFF.
  */
 gfr_status gfr_sssp(gfr_ctx *ctx, gfr_graph g, int32_t source, uint32_t *dist_out,
-                    gfr_stream stream);
+                    int32_t *pred_out, gfr_stream stream);
 
 /*
  * Betweenness centrality restricted to k sources (Sec. 5.3, Brandes'

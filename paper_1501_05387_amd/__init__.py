@@ -59,8 +59,8 @@ SIGNATURES = {
     "gfr_graph_load_csr": (_i32, [_vp, _i32, _i64, _vp, _vp, _vp, _u32, ctypes.POINTER(_i64)]),
     "gfr_graph_free": (_i32, [_vp, _i64]),
     "gfr_graph_info": (_i32, [_vp, _i64, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_u64)]),
-    "gfr_bfs": (_i32, [_vp, _i64, _i32, _vp, _vp]),
-    "gfr_sssp": (_i32, [_vp, _i64, _i32, _vp, _vp]),
+    "gfr_bfs": (_i32, [_vp, _i64, _i32, _vp, _vp, _vp]),
+    "gfr_sssp": (_i32, [_vp, _i64, _i32, _vp, _vp, _vp]),
     "gfr_bc": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp]),
     "gfr_cc": (_i32, [_vp, _i64, _vp, ctypes.POINTER(_i32), _vp]),
     "gfr_pagerank": (_i32, [_vp, _i64, _f32, _f64, _i32, _vp, ctypes.POINTER(_i32),
@@ -215,15 +215,25 @@ class Context:
         return n.value, m.value, b.value
 
     # ---------------------------------------------------------- primitives
-    def bfs(self, g: Graph, source: int, out=None):
-        p, ret = self._out(out, g.n, np.int32)
-        self._check(lib().gfr_bfs(self.ptr, g.handle, int(source), p, self._stream()))
-        return ret
+    def _pred(self, pred, n):
+        """(pointer or None, object to return or None) for an optional predecessor output."""
+        if pred is None or pred is False:
+            return None, None
+        return self._out(None if pred is True else pred, n, np.int32)
 
-    def sssp(self, g: Graph, source: int, out=None):
+    def bfs(self, g: Graph, source: int, out=None, pred=None):
+        """Depths; with pred=True (or a buffer) also the predecessors: (depth, pred)."""
+        p, ret = self._out(out, g.n, np.int32)
+        pp, pret = self._pred(pred, g.n)
+        self._check(lib().gfr_bfs(self.ptr, g.handle, int(source), p, pp, self._stream()))
+        return ret if pret is None else (ret, pret)
+
+    def sssp(self, g: Graph, source: int, out=None, pred=None):
+        """Distances; with pred=True (or a buffer) also the predecessors: (dist, pred)."""
         p, ret = self._out(out, g.n, np.uint32)
-        self._check(lib().gfr_sssp(self.ptr, g.handle, int(source), p, self._stream()))
-        return ret
+        pp, pret = self._pred(pred, g.n)
+        self._check(lib().gfr_sssp(self.ptr, g.handle, int(source), p, pp, self._stream()))
+        return ret if pret is None else (ret, pret)
 
     def bc(self, g: Graph, sources, out=None):
         src = _np(sources, np.int32)

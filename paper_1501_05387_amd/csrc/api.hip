@@ -475,6 +475,22 @@ OptScope::~OptScope() { c.opt = saved; }
 
 using namespace gfr;
 
+// Predecessor output of a single-source solve: written straight into a device
+// buffer, or staged in the arena and copied out for host memory.
+template <class Run>
+static void with_pred(Ctx &c, Graph &g, int32_t *pred_out, hipStream_t s, Run run)
+{
+    if (!pred_out) return;
+    int32_t *pd = pred_out;
+    const bool dev = is_device_ptr(pred_out);
+    if (!dev) {
+        c.arena.reserve(al256(4ull * g.n));
+        pd = c.arena.take<int32_t>(g.n);
+    }
+    run(pd);
+    if (!dev) deliver(c, pred_out, pd, 4ull * g.n, s);
+}
+
 extern "C" {
 
 gfr_status gfr_ctx_create(int32_t device, const char *tuning_json, gfr_ctx **out)
@@ -660,7 +676,8 @@ gfr_status gfr_graph_info(gfr_ctx *ctx, gfr_graph gh, int32_t *n, int64_t *m, ui
     });
 }
 
-gfr_status gfr_bfs(gfr_ctx *ctx, gfr_graph gh, int32_t source, int32_t *depth_out, gfr_stream stream)
+gfr_status gfr_bfs(gfr_ctx *ctx, gfr_graph gh, int32_t source, int32_t *depth_out, int32_t *pred_out,
+                   gfr_stream stream)
 {
     return guard(ctx, [&](Ctx &c) {
         Graph &g = get_graph(c, gh);
@@ -670,12 +687,14 @@ gfr_status gfr_bfs(gfr_ctx *ctx, gfr_graph gh, int32_t source, int32_t *depth_ou
         OutBuf o(c, depth_out, 4ull * g.n);
         timed_begin(c, s);
         run_bfs(c, g, source, (int32_t *)o.dev, s);
+        with_pred(c, g, pred_out, s, [&](int32_t *pd) { run_bfs_pred(c, g, source, (const int32_t *)o.dev, pd, s); });
         timed_end(c, s);
         o.finish(c, s);
     });
 }
 
-gfr_status gfr_sssp(gfr_ctx *ctx, gfr_graph gh, int32_t source, uint32_t *dist_out, gfr_stream stream)
+gfr_status gfr_sssp(gfr_ctx *ctx, gfr_graph gh, int32_t source, uint32_t *dist_out, int32_t *pred_out,
+                    gfr_stream stream)
 {
     return guard(ctx, [&](Ctx &c) {
         Graph &g = get_graph(c, gh);
@@ -686,6 +705,8 @@ gfr_status gfr_sssp(gfr_ctx *ctx, gfr_graph gh, int32_t source, uint32_t *dist_o
         OutBuf o(c, dist_out, 4ull * g.n);
         timed_begin(c, s);
         run_sssp(c, g, source, (uint32_t *)o.dev, s);
+        with_pred(c, g, pred_out, s,
+                  [&](int32_t *pd) { run_sssp_pred(c, g, source, (const uint32_t *)o.dev, pd, s); });
         timed_end(c, s);
         o.finish(c, s);
     });

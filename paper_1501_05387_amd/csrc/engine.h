@@ -272,6 +272,9 @@ int grid_blocks(const Ctx &c, int per_cu = 4);
 // Solvers (outputs are device pointers on the context's device).
 void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s);
 void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s);
+// Predecessors from finished distances (device pointers): the first neighbour one step closer.
+void run_bfs_pred(Ctx &c, Graph &g, int32_t src, const int32_t *depth, int32_t *pred, hipStream_t s);
+void run_sssp_pred(Ctx &c, Graph &g, int32_t src, const uint32_t *dist, int32_t *pred, hipStream_t s);
 // Bucket width factor x mean edge weight, clamped to [1, 1e9].
 uint32_t sssp_auto_delta(const Graph &g, double factor);
 void run_cc(Ctx &c, Graph &g, int32_t *label, int32_t *ncomp, hipStream_t s);

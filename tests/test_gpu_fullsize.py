@@ -86,6 +86,21 @@ def test_rmat22_bench_step(ctx):
     g.free()
 
 
+def test_rmat22_predecessors(ctx):
+    row, col = graphgen.rmat(22)
+    w = graphgen.weights(row, col, 64)
+    src = int(graphgen.sample_sources(row, col, 1)[0])
+    g = ctx.graph_load_csr(row, col, w)
+    _say("rmat22 bfs/sssp predecessors from", src)
+    d, p = ctx.bfs(g, src, pred=True)
+    do, po = oracle.bfs_pred(row, col, src)
+    assert np.array_equal(d.cpu().numpy(), do) and np.array_equal(p.cpu().numpy(), po)
+    d, p = ctx.sssp(g, src, pred=True)
+    do, po = oracle.sssp_pred(row, col, w, src)
+    assert np.array_equal(d.cpu().numpy().view(np.uint32), do) and np.array_equal(p.cpu().numpy(), po)
+    g.free()
+
+
 def test_grid4096_bfs_sssp_cc(ctx):
     row, col = graphgen.grid(4096)
     w = graphgen.weights(row, col, 1000)

@@ -176,6 +176,39 @@ def test_sssp_rejects_unweighted_and_overflow(ctx):
     g.free()
 
 
+# ----------------------------------------------------------- predecessors
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_predecessors_match_oracle(ctx, name):
+    row, col, w = graph(name)
+    g = _load(ctx, row, col, w)
+    for s in _sources(row, col, 3):
+        _say("pred", name, "source", s)
+        d, p = ctx.bfs(g, s, pred=True)
+        do, po = oracle.bfs_pred(row, col, s)
+        assert np.array_equal(_host(d), do) and np.array_equal(_host(p), po)
+        d, p = ctx.sssp(g, s, pred=True)
+        do, po = oracle.sssp_pred(row, col, w, s)
+        assert np.array_equal(_host(d).view(np.uint32), do) and np.array_equal(_host(p), po)
+    g.free()
+
+
+def test_predecessors_host_outputs_and_default(ctx):
+    row, col, w = graph("star5000")
+    n = row.size - 1
+    g = _load(ctx, row, col, w)
+    dh, ph = np.empty(n, np.int32), np.empty(n, np.int32)
+    d, p = ctx.bfs(g, 4321, out=dh, pred=ph)       # the centre's row (5000 entries) takes the wave path
+    assert d is dh and p is ph
+    do, po = oracle.bfs_pred(row, col, 4321)
+    assert np.array_equal(dh, do) and np.array_equal(ph, po) and ph[0] == 4321
+    sh = np.empty(n, np.uint32)
+    ctx.sssp(g, 4321, out=sh, pred=ph)
+    so, po = oracle.sssp_pred(row, col, w, 4321)
+    assert np.array_equal(sh, so) and np.array_equal(ph, po)
+    assert not isinstance(ctx.bfs(g, 0), tuple)     # no predecessors unless asked
+    g.free()
+
+
 # --------------------------------------------------------------------- CC
 @pytest.mark.parametrize("name", list(GRAPHS))
 def test_cc_matches_oracle(ctx, name):
