@@ -240,6 +240,36 @@ gfr_status gfr_pagerank_filtered(gfr_ctx *ctx, gfr_graph g, double damping, doub
                                  int32_t max_iter, double *rank_out, uint8_t *active_out,
                                  int32_t *iters_out, double *final_l1_out, gfr_stream stream);
 
+/* ------------------------------------------------------------- operators */
+/*
+ * The advance operator on its own (Sec. 4.1): the edge frontier of a vertex
+ * frontier.  For every entry u of `frontier` (nf ids, host or device memory,
+ * any order, duplicates allowed), in frontier order, every edge e of u in CSR
+ * order: out_src[i] = u, out_edge[i] = e, out_dst[i] = C[e], i counting from 0
+ * in that order.  The degrees are scanned into output offsets and the
+ * load-balanced advance (Sec. 4.4) writes every edge at its offset.
+ * Outputs: device memory, each may be NULL, out_cap elements each.
+ * *count_out (host) = number of edges.  GFR_E_CAPACITY (nothing written) if
+ * that exceeds out_cap or 2^31 - 1; GFR_E_INVALID for an id outside [0,n) or a
+ * host output pointer.
+ */
+gfr_status gfr_advance(gfr_ctx *ctx, gfr_graph g, const int32_t *frontier, int32_t nf,
+                       int32_t *out_src, int32_t *out_edge, int32_t *out_dst, int64_t out_cap,
+                       int64_t *count_out, gfr_stream stream);
+
+/*
+ * The filter operator on its own (Sec. 4.1): cull and deduplicate a vertex
+ * list.  out = the distinct ids of `items` (count ids, host or device memory,
+ * duplicates allowed) whose byte exclude[v] is 0 (exclude: n bytes, host or
+ * device memory, NULL = keep all), in ascending order.  out: device memory,
+ * out_cap elements.  *count_out (host) = number kept.  GFR_E_CAPACITY
+ * (nothing written) if that exceeds out_cap; GFR_E_INVALID for an id outside
+ * [0,n) or a host output pointer.
+ */
+gfr_status gfr_filter(gfr_ctx *ctx, gfr_graph g, const int32_t *items, int64_t count,
+                      const uint8_t *exclude, int32_t *out, int64_t out_cap, int64_t *count_out,
+                      gfr_stream stream);
+
 /* --------------------------------------------- 2-hop and node rankings */
 /*
  * Walks of length two from a seed set (Sec. 4.1: advance from the seeds'

@@ -22,6 +22,8 @@ Every function follows a textbook definition named in the paper:
 * ``ppr``       personalized PageRank, teleport and dangling mass to the seeds.
 * ``salsa``, ``hits``  bipartite node rankings (hubs left, authorities right),
   the rankings Sec. 5.5 lists as built on the same advance.
+* ``advance``, ``filter_ids``  the two operators by their definitions (plain
+  Python, for the operator tests).
 
 All twelve are pinned against brute force, closed forms, library routines and
 invariants in ``tests/test_oracle_pins.py``.
@@ -266,6 +268,34 @@ def sssp_pred(row, col, w, src: int):
 
 def two_hop(row, col, seeds):
     return default().two_hop(row, col, seeds)
+
+
+def advance(row, col, frontier):
+    """The advance operator by its definition (Sec. 4.1): for every frontier entry u in
+    order, every edge e of u in CSR order -> arrays (u, e, col[e])."""
+    row = np.asarray(row, np.int64)
+    src, edge = [], []
+    for u in np.asarray(frontier, np.int64).tolist():
+        if not 0 <= u < row.size - 1:
+            raise ValueError("oracle.advance: vertex out of range")
+        e = np.arange(row[u], row[u + 1], dtype=np.int64)
+        edge.append(e)
+        src.append(np.full(e.size, u, np.int64))
+    edge = np.concatenate(edge) if edge else np.zeros(0, np.int64)
+    src = np.concatenate(src) if src else np.zeros(0, np.int64)
+    return src.astype(np.int32), edge.astype(np.int32), np.asarray(col, np.int32)[edge]
+
+
+def filter_ids(n, items, exclude=None):
+    """The filter operator by its definition (Sec. 4.1): the distinct ids of `items`
+    whose exclude byte is 0, ascending."""
+    keep = set()
+    for v in np.asarray(items, np.int64).tolist():
+        if not 0 <= v < n:
+            raise ValueError("oracle.filter_ids: vertex out of range")
+        if exclude is None or not exclude[v]:
+            keep.add(v)
+    return np.array(sorted(keep), np.int32)
 
 
 def ppr(row, col, seeds, damping: float = 0.85, tol: float = 1e-9, max_iter: int = 1000):

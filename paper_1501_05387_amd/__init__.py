@@ -67,6 +67,8 @@ SIGNATURES = {
                             ctypes.POINTER(_f64), _vp]),
     "gfr_pagerank_filtered": (_i32, [_vp, _i64, _f64, _f64, _i32, _vp, _vp, ctypes.POINTER(_i32),
                                      ctypes.POINTER(_f64), _vp]),
+    "gfr_advance": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp]),
+    "gfr_filter": (_i32, [_vp, _i64, _vp, _i64, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp]),
     "gfr_two_hop": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp]),
     "gfr_ppr": (_i32, [_vp, _i64, _vp, _i32, _f64, _f64, _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_f64),
                        _vp]),
@@ -264,6 +266,54 @@ class Context:
                                                 int(max_iter), p, pa, ctypes.byref(it), ctypes.byref(l1),
                                                 self._stream()))
         return ret, act, it.value, l1.value
+
+    def advance(self, g: Graph, frontier, out_cap=None):
+        """Edge frontier of a vertex frontier (numpy array or device tensor of int32 ids):
+        (src, edge, dst) device tensors, in frontier order then CSR order."""
+        torch = _torch()
+        dev = "cuda:%d" % self.device
+        if isinstance(frontier, torch.Tensor):
+            fr = frontier.to(dev, torch.int32).contiguous()
+            fp, nf = fr.data_ptr(), fr.numel()
+        else:
+            fr = _np(frontier, np.int32)
+            fp, nf = (fr.ctypes.data if fr.size else None), fr.size
+        cnt = _i64()
+        if out_cap is None:   # size the outputs from a counting call
+            st = lib().gfr_advance(self.ptr, g.handle, fp, nf, None, None, None, 0, ctypes.byref(cnt), self._stream())
+            if st not in (GFR_OK, GFR_E_CAPACITY):
+                self._check(st)
+            out_cap = cnt.value
+        outs = [torch.empty(max(int(out_cap), 1), dtype=torch.int32, device=dev) for _ in range(3)]
+        self._check(lib().gfr_advance(self.ptr, g.handle, fp, nf, outs[0].data_ptr(), outs[1].data_ptr(),
+                                      outs[2].data_ptr(), int(out_cap), ctypes.byref(cnt), self._stream()))
+        k = cnt.value
+        return outs[0][:k], outs[1][:k], outs[2][:k]
+
+    def filter(self, g: Graph, items, exclude=None):
+        """Ascending distinct ids of `items` whose exclude byte is 0 (device int32 tensor)."""
+        torch = _torch()
+        dev = "cuda:%d" % self.device
+        if isinstance(items, torch.Tensor):
+            it = items.to(dev, torch.int32).contiguous()
+            ip, cnt_in = it.data_ptr(), it.numel()
+        else:
+            it = _np(items, np.int32)
+            ip, cnt_in = (it.ctypes.data if it.size else None), it.size
+        ep = None
+        if exclude is not None:
+            if isinstance(exclude, torch.Tensor):
+                ex = exclude.to(dev, torch.uint8).contiguous()
+                ep = ex.data_ptr()
+            else:
+                ex = _np(exclude, np.uint8)
+                ep = ex.ctypes.data
+        cap = min(cnt_in, g.n)
+        out = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        cnt = _i64()
+        self._check(lib().gfr_filter(self.ptr, g.handle, ip, cnt_in, ep, out.data_ptr(), cap, ctypes.byref(cnt),
+                                     self._stream()))
+        return out[:cnt.value]
 
     def two_hop(self, g: Graph, seeds, out=None):
         """Walks of length two from the seed set, per end vertex (int64 tensor or uint64 array)."""

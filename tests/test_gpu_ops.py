@@ -1,0 +1,133 @@
+"""GPU parity for the advance and filter operators on their own, through the
+C ABI, against their definitions: every frontier edge exactly once, in
+frontier order then CSR order; filter = the ascending distinct kept ids.
+The graphs include a hub spanning several load-balancing chunks and rows
+whose degrees sit at the wave and chunk sizes and one either side."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1501_05387_amd as gfr
+    c = gfr.Context(0)
+    yield c
+    c.close()
+
+
+def _cutoffs():
+    """Hubs of degree 63, 64, 65, 1023, 1024, 1025 and 2049, each on leaves of its own."""
+    eu, ev, nxt = [], [], 7
+    for h, d in enumerate((63, 64, 65, 1023, 1024, 1025, 2049)):
+        eu += [h] * d
+        ev += list(range(nxt, nxt + d))
+        nxt += d
+    return graphgen.from_edges(nxt + 5, eu, ev)      # five isolated vertices at the end
+
+
+GRAPHS = {
+    "rmat12": lambda: graphgen.rmat(12),
+    "rmat16": lambda: graphgen.rmat(16),
+    "grid96": lambda: graphgen.grid(96),
+    "star5000": lambda: graphgen.from_edges(5001, np.zeros(5000, np.int32), np.arange(1, 5001)),
+    "cutoffs": _cutoffs,
+}
+_cache = {}
+
+
+def graph(name):
+    if name not in _cache:
+        _cache[name] = GRAPHS[name]()
+    return _cache[name]
+
+
+def _frontiers(row, seed=5):
+    n = row.size - 1
+    rng = np.random.default_rng(seed)
+    deg = np.diff(row)
+    iso = np.nonzero(deg == 0)[0]
+    out = {
+        "empty": np.zeros(0, np.int32),
+        "one": np.array([0], np.int32),
+        "random_dup_100": rng.integers(0, n, size=100).astype(np.int32),
+        "random_dup_5000": rng.integers(0, n, size=5000).astype(np.int32),
+        "all_reversed": np.arange(n - 1, -1, -1, dtype=np.int32),
+    }
+    if iso.size:
+        out["isolated_only"] = np.repeat(iso[:3], 2).astype(np.int32)
+    return out
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_advance_matches_definition(ctx, name):
+    import torch
+    row, col = graph(name)
+    g = ctx.graph_load_csr(row, col)
+    for fname, F in _frontiers(row).items():
+        _say("advance", name, fname, F.size)
+        src, edge, dst = oracle.advance(row, col, F)
+        for inp in (F, torch.from_numpy(F).cuda()):     # host and device frontiers
+            s, e, d = ctx.advance(g, inp)
+            assert np.array_equal(s.cpu().numpy(), src)
+            assert np.array_equal(e.cpu().numpy(), edge)
+            assert np.array_equal(d.cpu().numpy(), dst)
+    g.free()
+
+
+def test_advance_capacity_and_errors(ctx):
+    import ctypes
+    import paper_1501_05387_amd as gfr
+    row, col = graph("cutoffs")
+    g = ctx.graph_load_csr(row, col)
+    F = np.arange(7, dtype=np.int32)
+    total = int(np.diff(row)[:7].sum())
+    with pytest.raises(gfr.GfrError) as ei:
+        ctx.advance(g, F, out_cap=total - 1)
+    assert ei.value.status == gfr.GFR_E_CAPACITY
+    cnt = ctypes.c_int64()
+    st = gfr.lib().gfr_advance(ctx.ptr, g.handle, F.ctypes.data, F.size, None, None, None, 0, ctypes.byref(cnt), None)
+    assert st == gfr.GFR_E_CAPACITY and cnt.value == total
+    s, e, d = ctx.advance(g, F, out_cap=total)
+    assert s.numel() == total
+    for bad in ([row.size - 1], [-1]):
+        with pytest.raises(gfr.GfrError) as ei:
+            ctx.advance(g, np.array(bad, np.int32))
+        assert ei.value.status == gfr.GFR_E_INVALID
+    out = np.empty(total, np.int32)                      # host outputs are refused
+    st = gfr.lib().gfr_advance(ctx.ptr, g.handle, F.ctypes.data, F.size, out.ctypes.data, None, None, total,
+                               ctypes.byref(cnt), None)
+    assert st == gfr.GFR_E_INVALID
+    g.free()
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_filter_matches_definition(ctx, name):
+    import torch
+    row, col = graph(name)
+    n = row.size - 1
+    g = ctx.graph_load_csr(row, col)
+    rng = np.random.default_rng(6)
+    ex = (rng.random(n) < 0.3).astype(np.uint8)
+    for fname, X in _frontiers(row).items():
+        _say("filter", name, fname, X.size)
+        assert np.array_equal(ctx.filter(g, X).cpu().numpy(), oracle.filter_ids(n, X))
+        want = oracle.filter_ids(n, X, ex)
+        assert np.array_equal(ctx.filter(g, X, ex).cpu().numpy(), want)
+        got = ctx.filter(g, torch.from_numpy(X).cuda(), torch.from_numpy(ex).cuda())
+        assert np.array_equal(got.cpu().numpy(), want)
+    assert ctx.filter(g, np.arange(n, dtype=np.int32), np.ones(n, np.uint8)).numel() == 0
+    g.free()

@@ -14,6 +14,7 @@ import scipy.sparse as sp
 import scipy.sparse.csgraph as csg
 
 import graphgen
+import oracle
 from tests import brute
 from tests import invariants as inv
 
@@ -480,3 +481,32 @@ def test_input_validation(orc):
     w = np.full(col.size, 0x7FFFFFFF, np.uint32)
     with pytest.raises(OverflowError):
         orc.sssp(row, col, w, 0)
+
+
+# ------------------------------------------------------------ operators ----
+def test_operator_definitions():
+    """The advance and filter oracles: a worked example, then agreement with the
+    adjacency matrix (rows of a sorted CSR list neighbours in ascending order)."""
+    row, col = _path(5)                                  # 0-1-2-3-4
+    src, edge, dst = oracle.advance(row, col, [1, 1, 4, 0])
+    assert src.tolist() == [1, 1, 1, 1, 4, 0]
+    assert dst.tolist() == [0, 2, 0, 2, 3, 1]
+    assert np.array_equal(col[edge], dst)
+    assert oracle.filter_ids(5, [4, 1, 1, 3, 0], [0, 0, 0, 1, 0]).tolist() == [0, 1, 4]
+    assert oracle.filter_ids(5, []).tolist() == []
+    rng = np.random.default_rng(8)
+    for _ in range(20):
+        n = int(rng.integers(1, 40))
+        row, col = _random_graph(rng, n, 0.2)
+        A = np.zeros((n, n), bool)
+        A[np.repeat(np.arange(n), np.diff(row)), col] = True
+        F = rng.integers(0, n, size=int(rng.integers(0, 30)))
+        src, edge, dst = oracle.advance(row, col, F)
+        want_src = [u for u in F.tolist() for _ in range(int(A[u].sum()))]
+        want_dst = [v for u in F.tolist() for v in np.nonzero(A[u])[0].tolist()]
+        assert src.tolist() == want_src and dst.tolist() == want_dst
+        assert edge.size == int(np.diff(row)[F].sum())
+        ex = rng.integers(0, 2, size=n).astype(np.uint8)
+        assert oracle.filter_ids(n, F, ex).tolist() == sorted(set(v for v in F.tolist() if not ex[v]))
+    with pytest.raises(ValueError):
+        oracle.advance(row, col, [n])
