@@ -107,7 +107,9 @@ const char *gfr_last_error(const gfr_ctx *ctx);
  *                     single-source solves (same results, lower cost for few sources)
  *   "profile.kernels" 1: time every launch of the level kernels with HIP events
  *                     (statistics "t.<kernel>.ms" and "t.<kernel>.n")
- *   "serve.budget_bytes"  device bytes the serving runtime may hold for queries
+ *   "serve.budget_bytes"  device bytes the serving runtime's batching sessions may hold;
+ *                     lowering it releases idle sessions beyond it (busy ones when they
+ *                     finish).  The single-source workers' scratch is not counted.
  * GFR_E_INVALID for an unknown key or an out-of-range value.
  */
 gfr_status gfr_set_option(gfr_ctx *ctx, const char *key, double value);

@@ -425,8 +425,23 @@ static void worker_loop(Server *sv)
                     it = sv->queue.erase(it);
                 }
             }
-            // 3. new sessions where the budget allows (idle ones make room);
-            //    their queries are admitted on the next pass
+            // 3. a lowered budget releases idle sessions beyond it; new
+            //    sessions open where the budget allows (idle ones make room),
+            //    and their queries are admitted on the next pass
+            {
+                uint64_t used = 0;
+                for (auto &ep : sv->sessions) used += ep->s->bytes;
+                while ((double)used > budget) {
+                    auto victim = sv->sessions.end();
+                    for (auto it = sv->sessions.begin(); it != sv->sessions.end(); ++it)
+                        if (!(*it)->busy && !(*it)->in_flight &&
+                            (victim == sv->sessions.end() || (*it)->last_used < (*victim)->last_used))
+                            victim = it;
+                    if (victim == sv->sessions.end()) break;
+                    used -= (*victim)->s->bytes;
+                    sv->sessions.erase(victim);
+                }
+            }
             if (!wanted.empty()) {
                 uint64_t used = 0;
                 for (auto &ep : sv->sessions) used += ep->s->bytes;

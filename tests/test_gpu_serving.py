@@ -122,6 +122,63 @@ def test_capacity_rejection(env):
         ctx.set_option("serve.budget_bytes", old)
 
 
+def test_admission_keeps_sessions_within_budget(env):
+    """With a budget below the four (graph, kind) sessions of the mix, sessions
+    are evicted and re-created as keys come and go, the resident footprint never
+    exceeds the budget at any poll, and every result is still exact."""
+    import torch
+    gfr, ctx, graphs = env
+    saved = {k: ctx.get_option(k) for k in ("serve.budget_bytes", "batch.min_bfs", "batch.min_sssp")}
+    try:
+        ctx.set_option("batch.min_bfs", 1)
+        ctx.set_option("batch.min_sssp", 1)
+        keys = [(name, kind) for name in ("rmat12", "grid64") for kind in (gfr.GFR_Q_BFS, gfr.GFR_Q_SSSP)]
+        outs = {}
+        for name, kind in keys:      # one query per key: all four sessions resident
+            row, col, w, g = graphs[name]
+            outs[(name, kind)] = torch.empty(row.size - 1, dtype=torch.int32, device="cuda:0")
+            _drain(ctx, ctx.submit_queries([(kind, g, 1, outs[(name, kind)])]))
+        full = ctx.stat("serve.session_bytes")
+        budget = 0.6 * full
+        ctx.set_option("serve.budget_bytes", budget)
+        # the next pass of the runtime releases the idle sessions beyond the new budget
+        name, kind = keys[0]
+        _drain(ctx, ctx.submit_queries([(kind, graphs[name][3], 2, outs[(name, kind)])]))
+        t0 = time.time()
+        while ctx.stat("serve.session_bytes") > budget:
+            assert time.time() - t0 < 10, "idle sessions beyond a lowered budget were kept"
+            time.sleep(0.01)
+        rng = np.random.default_rng(9)
+        qs, meta = [], []
+        for i in range(160):
+            name, kind = keys[int(rng.integers(0, 4))]
+            row, col, w, g = graphs[name]
+            src = int(rng.integers(0, row.size - 1))
+            out = torch.empty(row.size - 1, dtype=torch.int32, device="cuda:0")
+            qs.append((kind, g, src, out))
+            meta.append((name, kind, src, out))
+        _say("admission under budget", budget, "of", full)
+        tickets = ctx.submit_queries(qs)
+        want, got, t0 = set(tickets), {}, time.time()
+        peak = 0.0
+        while want - set(got):
+            for t, st in ctx.poll(64, 20000):
+                got[t] = st
+            peak = max(peak, ctx.stat("serve.session_bytes"))
+            assert ctx.stat("serve.session_bytes") <= budget
+            assert time.time() - t0 < 90, "serving did not finish under the budget"
+        assert all(got[t] == gfr.GFR_OK for t in tickets)
+        for (name, kind, src, out) in meta[::8]:
+            row, col, w, g = graphs[name]
+            res = out.cpu().numpy()
+            want_r = oracle.bfs(row, col, src) if kind == gfr.GFR_Q_BFS else oracle.sssp(row, col, w, src)
+            assert np.array_equal(res.view(np.uint32) if kind == gfr.GFR_Q_SSSP else res, want_r)
+        _say("peak resident session bytes", peak)
+    finally:
+        for k, v in saved.items():
+            ctx.set_option(k, v)
+
+
 def test_cancel_and_poll_timeout(env):
     import torch
     gfr, ctx, graphs = env
