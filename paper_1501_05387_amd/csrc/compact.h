@@ -310,7 +310,9 @@ __global__ __launch_bounds__(GFR_BLOCK) void compact_kernel(const int32_t *R, in
     }
 }
 
-// launch geometry for nwords words of 32 vertices
+// launch geometry for nwords words of 32 vertices: two work-groups per CU
+// (measured on R-MAT s22: single-source BFS 0.38 -> 0.33 ms against one per
+// CU, batched steps unchanged, four per CU slower)
 struct CompactGeom {
     uint32_t blocks, wpt;
 };
@@ -318,7 +320,7 @@ struct CompactGeom {
 static inline CompactGeom compact_geom(uint32_t nwords, int num_cu)
 {
     CompactGeom g;
-    g.blocks = (uint32_t)num_cu;
+    g.blocks = 2u * (uint32_t)num_cu;
     const uint64_t threads = (uint64_t)g.blocks * GFR_BLOCK;
     g.wpt = (uint32_t)((nwords + threads - 1) / threads);
     if (g.wpt < 1) g.wpt = 1;
