@@ -386,6 +386,22 @@ struct BsMarks {
             a.fbits[w] = m;
             if (!m) return 0u;
             clear_marks(a.nany + 32ull * w);
+            if (__popc(m) >= 8) {
+                // a dense word: its 32 masks move as 256 contiguous bytes (a vertex
+                // without the mark has a zero mask, and its qm is never read)
+                ulonglong2 *pn = (ulonglong2 *)(a.nq + 32ull * w);
+                ulonglong2 *pq = (ulonglong2 *)(a.qm + 32ull * w);
+                ulonglong2 x[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) x[i] = pn[i];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    pn[i] = make_ulonglong2(0ull, 0ull);
+                    pq[i] = x[i];
+                    actq |= x[i].x | x[i].y;
+                }
+                return m;
+            }
             uint32_t bits = m;
             while (bits) {
                 const int bi = __ffs(bits) - 1;
