@@ -131,3 +131,12 @@ def test_filter_matches_definition(ctx, name):
         assert np.array_equal(got.cpu().numpy(), want)
     assert ctx.filter(g, np.arange(n, dtype=np.int32), np.ones(n, np.uint8)).numel() == 0
     g.free()
+
+
+def test_operators_on_a_graph_without_edges(ctx):
+    row = np.zeros(9, np.int32)
+    g = ctx.graph_load_csr(row, np.zeros(0, np.int32))
+    s, e, d = ctx.advance(g, np.array([3, 3, 0], np.int32))
+    assert s.numel() == 0 and e.numel() == 0 and d.numel() == 0
+    assert ctx.filter(g, np.array([5, 1, 5, 7], np.int32)).cpu().numpy().tolist() == [1, 5, 7]
+    g.free()

@@ -194,3 +194,16 @@ def test_bipartite_host_outputs_and_checks(ctx):
     h, a = ctx.hits(g, nl, 3)                    # the failed checks leave the graph usable
     assert np.max(np.abs(_host(h) - oracle.hits(row, col, nl, 3)[0])) <= 1e-12
     g.free()
+
+
+def test_rankings_on_a_graph_without_edges(ctx):
+    row = np.zeros(8, np.int32)
+    col = np.zeros(0, np.int32)
+    g = ctx.graph_load_csr(row, col)
+    for method in ("salsa", "hits"):
+        for iters in (0, 1, 3):
+            h, a = getattr(ctx, method)(g, 3, iters)
+            ho, ao = getattr(oracle, method)(row, col, 3, iters)
+            assert np.array_equal(_host(h), ho) and np.array_equal(_host(a), ao), (method, iters)
+    assert not _host(ctx.two_hop(g, [0, 6])).any()
+    g.free()
