@@ -312,7 +312,9 @@ __global__ __launch_bounds__(GFR_BLOCK) void compact_kernel(const int32_t *R, in
 
 // launch geometry for nwords words of 32 vertices: two work-groups per CU
 // (measured on R-MAT s22: single-source BFS 0.38 -> 0.33 ms against one per
-// CU, batched steps unchanged, four per CU slower)
+// CU, batched steps unchanged, four per CU slower), and no more work-groups
+// than there are words for one word per thread (a small graph keeps its
+// look-back chain short)
 struct CompactGeom {
     uint32_t blocks, wpt;
 };
@@ -321,6 +323,8 @@ static inline CompactGeom compact_geom(uint32_t nwords, int num_cu)
 {
     CompactGeom g;
     g.blocks = 2u * (uint32_t)num_cu;
+    const uint32_t needed = (uint32_t)(((uint64_t)nwords + GFR_BLOCK - 1) / GFR_BLOCK);
+    if (needed < g.blocks) g.blocks = needed < 1u ? 1u : needed;
     const uint64_t threads = (uint64_t)g.blocks * GFR_BLOCK;
     g.wpt = (uint32_t)((nwords + threads - 1) / threads);
     if (g.wpt < 1) g.wpt = 1;
