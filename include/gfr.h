@@ -6,7 +6,11 @@
  * GPU", PPoPP'16): an *advance* operator that expands every frontier vertex's
  * CSR neighbour list under load balancing (Sec. 4.1, Sec. 4.4) and a *filter*
  * operator that culls and deduplicates the result (Sec. 4.1, Sec. 4.5), driving
- * BFS, SSSP, BC, CC and PageRank (Sec. 5).  All kernels are HIP for gfx950.
+ * BFS, SSSP, BC, CC and PageRank (Sec. 5), PageRank with per-vertex
+ * convergence filtering, 2-hop walk counts and the bipartite rankings of
+ * Sec. 5.5 (personalized PageRank, SALSA, HITS).  The two operators are also
+ * callable on their own; batched 64-source BFS / SSSP and a serving runtime
+ * sit on top.  All kernels are HIP for gfx950.
  *
  * General conventions
  *   - Every call returns a gfr_status; nothing throws across the ABI.
@@ -61,7 +65,8 @@ typedef void *gfr_stream;         /* hipStream_t or NULL                        
  *                             <class> is "scalefree" (largest degree at least
  *                             16 times the mean degree) or "mesh" (all others);
  *                             only solver options (bfs.*, sssp.*, advance.*,
- *                             msbfs.*, batch.*) may be given per class.
+ *                             msbfs.*, batch.*, bc.*, twohop.*) may be given
+ *                             per class.
  * Per-class values apply during each call on a graph of that class, except for
  * options later set explicitly with gfr_set_option, which win.  Options change
  * how the result is reached, never the result.  The string is only read
@@ -117,7 +122,8 @@ gfr_status gfr_get_option(gfr_ctx *ctx, const char *key, double *value);
 
 /*
  * Statistics of the last solve on this context: "levels", "push_levels",
- * "pull_levels", "edges_inspected", "iterations", "relaxations", "kernel_ms".
+ * "pull_levels", "edges_inspected", "iterations", "relaxations", "kernel_ms"
+ * (device time of the whole call), plus those a call documents with it.
  * Serving statistics since the last "serve.reset": "serve.completed",
  * "serve.batches" (session steps: one level or relaxation round of one
  * session), "serve.mean_batch" (queries in flight per step), "serve.joined"
