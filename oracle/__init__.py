@@ -22,10 +22,11 @@ Every function follows a textbook definition named in the paper:
 * ``ppr``       personalized PageRank, teleport and dangling mass to the seeds.
 * ``salsa``, ``hits``  bipartite node rankings (hubs left, authorities right),
   the rankings Sec. 5.5 lists as built on the same advance.
-* ``advance``, ``filter_ids``  the two operators by their definitions (plain
-  Python, for the operator tests).
+* ``advance``, ``advance_edges``, ``filter_ids``  the two operators by their
+  definitions, advance from a vertex or from an edge frontier (plain Python,
+  for the operator tests).
 
-All twelve are pinned against brute force, closed forms, library routines and
+All thirteen are pinned against brute force, closed forms, library routines and
 invariants in ``tests/test_oracle_pins.py``.
 """
 from __future__ import annotations
@@ -284,6 +285,25 @@ def advance(row, col, frontier):
     edge = np.concatenate(edge) if edge else np.zeros(0, np.int64)
     src = np.concatenate(src) if src else np.zeros(0, np.int64)
     return src.astype(np.int32), edge.astype(np.int32), np.asarray(col, np.int32)[edge]
+
+
+def advance_edges(row, col, edges):
+    """The advance operator from an edge frontier (Sec. 4.1: from edges to their
+    neighbouring edges and on to the far-end vertices): for every input edge e in
+    order, every edge f of its far end v = col[e] in CSR order -> arrays (e, f, col[f])."""
+    row = np.asarray(row, np.int64)
+    col = np.asarray(col, np.int64)
+    src, edge = [], []
+    for e in np.asarray(edges, np.int64).tolist():
+        if not 0 <= e < col.size:
+            raise ValueError("oracle.advance_edges: edge out of range")
+        v = col[e]
+        f = np.arange(row[v], row[v + 1], dtype=np.int64)
+        edge.append(f)
+        src.append(np.full(f.size, e, np.int64))
+    edge = np.concatenate(edge) if edge else np.zeros(0, np.int64)
+    src = np.concatenate(src) if src else np.zeros(0, np.int64)
+    return src.astype(np.int32), edge.astype(np.int32), col[edge].astype(np.int32)
 
 
 def filter_ids(n, items, exclude=None):

@@ -510,3 +510,34 @@ def test_operator_definitions():
         assert oracle.filter_ids(n, F, ex).tolist() == sorted(set(v for v in F.tolist() if not ex[v]))
     with pytest.raises(ValueError):
         oracle.advance(row, col, [n])
+
+
+def test_edge_advance_definition():
+    """advance_edges: a worked example, then the walk counts of the adjacency
+    matrix: over every edge (u, v), the pairs (u, far end) it leads to count
+    the walks u - v - w, so their histogram is A @ A."""
+    row, col = _path(4)                                  # 0-1-2-3; edges 0:0-1 1:1-0 2:1-2 3:2-1 4:2-3 5:3-2
+    src, edge, dst = oracle.advance_edges(row, col, [0, 5, 0])
+    assert src.tolist() == [0, 0, 5, 5, 0, 0]
+    assert edge.tolist() == [1, 2, 3, 4, 1, 2]
+    assert dst.tolist() == [0, 2, 1, 3, 0, 2]
+    assert [x.size for x in oracle.advance_edges(row, col, [])] == [0, 0, 0]
+    rng = np.random.default_rng(9)
+    for _ in range(20):
+        n = int(rng.integers(1, 40))
+        row, col = _random_graph(rng, n, 0.2)
+        m = col.size
+        A = np.zeros((n, n), np.int64)
+        A[np.repeat(np.arange(n), np.diff(row)), col] = 1
+        tail = np.repeat(np.arange(n), np.diff(row))     # the row each edge sits in
+        src, edge, dst = oracle.advance_edges(row, col, np.arange(m))
+        H = np.zeros((n, n), np.int64)
+        np.add.at(H, (tail[src], dst), 1)
+        assert np.array_equal(H, A @ A)
+        E = rng.integers(0, max(m, 1), size=int(rng.integers(0, 30))) if m else np.zeros(0, np.int64)
+        src, edge, dst = oracle.advance_edges(row, col, E)
+        want_dst = [w for e in E.tolist() for w in np.nonzero(A[col[e]])[0].tolist()]
+        assert src.tolist() == [e for e in E.tolist() for _ in range(int(A[col[e]].sum()))]
+        assert dst.tolist() == want_dst and np.array_equal(tail[edge], np.repeat(col[E], np.diff(row)[col[E]]))
+    with pytest.raises(ValueError):
+        oracle.advance_edges(row, col, [col.size])
