@@ -9,7 +9,8 @@
  * BFS, SSSP, BC, CC and PageRank (Sec. 5), PageRank with per-vertex
  * convergence filtering, 2-hop walk counts and the bipartite rankings of
  * Sec. 5.5 (personalized PageRank, SALSA, HITS).  The two operators are also
- * callable on their own; batched 64-source BFS / SSSP and a serving runtime
+ * callable on their own (advance from a vertex or from an edge frontier);
+ * batched 64-source BFS / SSSP and a serving runtime
  * sit on top.  All kernels are HIP for gfx950.
  *
  * General conventions
@@ -264,6 +265,20 @@ gfr_status gfr_pagerank_filtered(gfr_ctx *ctx, gfr_graph g, double damping, doub
 gfr_status gfr_advance(gfr_ctx *ctx, gfr_graph g, const int32_t *frontier, int32_t nf,
                        int32_t *out_src, int32_t *out_edge, int32_t *out_dst, int64_t out_cap,
                        int64_t *count_out, gfr_stream stream);
+
+/*
+ * The advance operator from an edge frontier (Sec. 4.1: advance may start
+ * from edges as well as from vertices): edge to edge, and edge to vertex.
+ * For every entry e of `edges` (ne edge ids in [0,m), host or device memory,
+ * any order, duplicates allowed), in input order, every edge f of v = C[e] in
+ * CSR order: out_src[i] = e, out_edge[i] = f, out_dst[i] = C[f].  So out_edge
+ * is the edge frontier and out_dst the vertex frontier that the edges lead
+ * to.  Outputs, capacity, *count_out and errors as for gfr_advance
+ * (GFR_E_INVALID for an id outside [0,m), which every id is when m = 0).
+ */
+gfr_status gfr_advance_edges(gfr_ctx *ctx, gfr_graph g, const int32_t *edges, int32_t ne,
+                             int32_t *out_src, int32_t *out_edge, int32_t *out_dst, int64_t out_cap,
+                             int64_t *count_out, gfr_stream stream);
 
 /*
  * The filter operator on its own (Sec. 4.1): cull and deduplicate a vertex

@@ -68,6 +68,7 @@ SIGNATURES = {
     "gfr_pagerank_filtered": (_i32, [_vp, _i64, _f64, _f64, _i32, _vp, _vp, ctypes.POINTER(_i32),
                                      ctypes.POINTER(_f64), _vp]),
     "gfr_advance": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp]),
+    "gfr_advance_edges": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp]),
     "gfr_filter": (_i32, [_vp, _i64, _vp, _i64, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp]),
     "gfr_two_hop": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp]),
     "gfr_ppr": (_i32, [_vp, _i64, _vp, _i32, _f64, _f64, _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_f64),
@@ -270,6 +271,15 @@ class Context:
     def advance(self, g: Graph, frontier, out_cap=None):
         """Edge frontier of a vertex frontier (numpy array or device tensor of int32 ids):
         (src, edge, dst) device tensors, in frontier order then CSR order."""
+        return self._advance("gfr_advance", g, frontier, out_cap)
+
+    def advance_edges(self, g: Graph, edges, out_cap=None):
+        """Advance from an edge frontier (int32 edge ids): for every input edge e, every
+        edge f of its far end, as (e, f, C[f]) device tensors, in input order then CSR order."""
+        return self._advance("gfr_advance_edges", g, edges, out_cap)
+
+    def _advance(self, name, g, frontier, out_cap):
+        call = getattr(lib(), name)
         torch = _torch()
         dev = "cuda:%d" % self.device
         if isinstance(frontier, torch.Tensor):
@@ -280,13 +290,13 @@ class Context:
             fp, nf = (fr.ctypes.data if fr.size else None), fr.size
         cnt = _i64()
         if out_cap is None:   # size the outputs from a counting call
-            st = lib().gfr_advance(self.ptr, g.handle, fp, nf, None, None, None, 0, ctypes.byref(cnt), self._stream())
+            st = call(self.ptr, g.handle, fp, nf, None, None, None, 0, ctypes.byref(cnt), self._stream())
             if st not in (GFR_OK, GFR_E_CAPACITY):
                 self._check(st)
             out_cap = cnt.value
         outs = [torch.empty(max(int(out_cap), 1), dtype=torch.int32, device=dev) for _ in range(3)]
-        self._check(lib().gfr_advance(self.ptr, g.handle, fp, nf, outs[0].data_ptr(), outs[1].data_ptr(),
-                                      outs[2].data_ptr(), int(out_cap), ctypes.byref(cnt), self._stream()))
+        self._check(call(self.ptr, g.handle, fp, nf, outs[0].data_ptr(), outs[1].data_ptr(), outs[2].data_ptr(),
+                         int(out_cap), ctypes.byref(cnt), self._stream()))
         k = cnt.value
         return outs[0][:k], outs[1][:k], outs[2][:k]
 

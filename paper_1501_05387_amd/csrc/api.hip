@@ -808,23 +808,38 @@ static void need_device(const void *p, const char *what)
     if (p && !is_device_ptr(p)) fail(GFR_E_INVALID, std::string(what) + " must be device memory");
 }
 
+static gfr_status advance_call(gfr_ctx *ctx, gfr_graph gh, const int32_t *frontier, int32_t nf, bool edges,
+                               int32_t *out_src, int32_t *out_edge, int32_t *out_dst, int64_t out_cap,
+                               int64_t *count_out, gfr_stream stream)
+{
+    const std::string who = edges ? "advance_edges" : "advance";
+    return guard(ctx, [&](Ctx &c) {
+        Graph &g = get_graph(c, gh);
+        if (nf < 0 || (nf > 0 && !frontier) || out_cap < 0 || !count_out) fail(GFR_E_INVALID, who + ": bad arguments");
+        need_device(out_src, (who + ": out_src").c_str());
+        need_device(out_edge, (who + ": out_edge").c_str());
+        need_device(out_dst, (who + ": out_dst").c_str());
+        hipStream_t s = pick_stream(c, stream);
+        timed_begin(c, s);
+        const int64_t total = run_advance(c, g, frontier, nf, edges, out_src, out_edge, out_dst, out_cap, s);
+        timed_end(c, s);
+        *count_out = total;
+        if (total > out_cap) fail(GFR_E_CAPACITY, who + ": the edge frontier exceeds out_cap");
+        if (total > INT32_MAX) fail(GFR_E_CAPACITY, who + ": more than 2^31 - 1 edges in one call");
+    });
+}
+
 gfr_status gfr_advance(gfr_ctx *ctx, gfr_graph gh, const int32_t *frontier, int32_t nf, int32_t *out_src,
                        int32_t *out_edge, int32_t *out_dst, int64_t out_cap, int64_t *count_out, gfr_stream stream)
 {
-    return guard(ctx, [&](Ctx &c) {
-        Graph &g = get_graph(c, gh);
-        if (nf < 0 || (nf > 0 && !frontier) || out_cap < 0 || !count_out) fail(GFR_E_INVALID, "advance: bad arguments");
-        need_device(out_src, "advance: out_src");
-        need_device(out_edge, "advance: out_edge");
-        need_device(out_dst, "advance: out_dst");
-        hipStream_t s = pick_stream(c, stream);
-        timed_begin(c, s);
-        const int64_t total = run_advance(c, g, frontier, nf, out_src, out_edge, out_dst, out_cap, s);
-        timed_end(c, s);
-        *count_out = total;
-        if (total > out_cap) fail(GFR_E_CAPACITY, "advance: the edge frontier exceeds out_cap");
-        if (total > INT32_MAX) fail(GFR_E_CAPACITY, "advance: more than 2^31 - 1 edges in one call");
-    });
+    return advance_call(ctx, gh, frontier, nf, false, out_src, out_edge, out_dst, out_cap, count_out, stream);
+}
+
+gfr_status gfr_advance_edges(gfr_ctx *ctx, gfr_graph gh, const int32_t *edges, int32_t ne, int32_t *out_src,
+                             int32_t *out_edge, int32_t *out_dst, int64_t out_cap, int64_t *count_out,
+                             gfr_stream stream)
+{
+    return advance_call(ctx, gh, edges, ne, true, out_src, out_edge, out_dst, out_cap, count_out, stream);
 }
 
 gfr_status gfr_filter(gfr_ctx *ctx, gfr_graph gh, const int32_t *items, int64_t count, const uint8_t *exclude,

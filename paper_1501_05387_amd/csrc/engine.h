@@ -287,9 +287,10 @@ void run_two_hop(Ctx &c, Graph &g, const int32_t *seeds, int32_t k, uint64_t *co
 void run_bipartite_rank(Ctx &c, Graph &g, int32_t nl, int32_t iters, bool walk, double *hub, double *auth,
                         hipStream_t s);
 // The operators alone.  Outputs are device pointers.  Both return the output
-// size; when it exceeds out_cap nothing is written.
-int64_t run_advance(Ctx &c, Graph &g, const int32_t *frontier, int32_t nf, int32_t *out_src, int32_t *out_edge,
-                    int32_t *out_dst, int64_t out_cap, hipStream_t s);
+// size; when it exceeds out_cap nothing is written.  With edges = true the
+// frontier holds edge ids and is advanced from the edges' far ends.
+int64_t run_advance(Ctx &c, Graph &g, const int32_t *frontier, int32_t nf, bool edges, int32_t *out_src,
+                    int32_t *out_edge, int32_t *out_dst, int64_t out_cap, hipStream_t s);
 int64_t run_filter(Ctx &c, Graph &g, const int32_t *items, int64_t count, const uint8_t *exclude, int32_t *out,
                    int64_t out_cap, hipStream_t s);
 // Copy `bytes` of device data to a caller's buffer (device or host memory) and wait.

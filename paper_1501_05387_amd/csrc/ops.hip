@@ -8,7 +8,10 @@
 //            scanned into output offsets (the scan of Sec. 4.4), the entries
 //            with edges become a chunked frontier queue, and the
 //            load-balanced advance writes each edge at its offset, so the
-//            output order is exactly the sequential one.
+//            output order is exactly the sequential one.  An edge frontier
+//            (Sec. 4.1 lets advance start from edges as well) is first
+//            gathered to the edges' far ends; each output then carries the
+//            input edge in place of u.
 //   filter   a list of vertices (duplicates allowed) becomes the ascending
 //            list of the distinct vertices not excluded by a byte mask:
 //            items leave a mark byte (idempotent stores, Sec. 4.5), and a
@@ -116,9 +119,12 @@ struct AdvVal {
     }
 };
 
-// entries with edges become the queue; part[c] = entry holding edge c * CH
+// entries with edges become the queue, tagged with their input item (the
+// vertex itself, or the edge it was reached by); part[c] = entry holding edge
+// c * CH
 struct AdvEmit {
     const int32_t *F;
+    const int32_t *T;
     const int32_t *R;
     FrontierQ q;
     __device__ void operator()(int64_t i, P2 x, P2 p) const
@@ -126,7 +132,7 @@ struct AdvEmit {
         if (!x.a) return;
         const int32_t v = F[i];
         const uint32_t slot = (uint32_t)p.b, off = (uint32_t)p.a, d = (uint32_t)x.a;
-        q.v[slot] = v;
+        q.v[slot] = T[i];
         q.off[slot] = off;
         q.row[slot] = R[v];
         for (uint32_t c = (off + GATHER_CH - 1) / GATHER_CH; (uint64_t)c * GATHER_CH < (uint64_t)off + d; ++c)
@@ -165,6 +171,13 @@ __global__ __launch_bounds__(GFR_BLOCK) void advance_emit(FrontierQ q, uint32_t 
     }
 }
 
+// far ends of an edge frontier
+__global__ void edge_heads(const int32_t *E, int64_t count, const int32_t *C, int32_t *V)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        V[i] = C[E[i]];
+}
+
 __global__ void count_out_of_range(const int32_t *x, int64_t count, int32_t n, uint32_t *bad)
 {
     uint32_t b = 0;
@@ -173,9 +186,10 @@ __global__ void count_out_of_range(const int32_t *x, int64_t count, int32_t n, u
     if (b) atomicAdd(bad, b);
 }
 
-// Input list on the device (copied there when it is host memory), range-checked.
+// Input list on the device (copied there when it is host memory), every id
+// checked against [0, n).
 static const int32_t *device_list(Ctx &c, const int32_t *list, int64_t count, int32_t n, int32_t *staging,
-                                  uint32_t *bad, hipStream_t s, const char *who)
+                                  uint32_t *bad, hipStream_t s, const char *who, const char *what = "vertex")
 {
     const int32_t *d = list;
     if (!is_device_ptr(list)) {
@@ -187,26 +201,36 @@ static const int32_t *device_list(Ctx &c, const int32_t *list, int64_t count, in
     GFR_LAUNCH_CHECK();
     GFR_HIP(hipMemcpyAsync(c.pinned, bad, 4, hipMemcpyDeviceToHost, s));
     GFR_HIP(hipStreamSynchronize(s));
-    if (c.pinned[0]) fail(GFR_E_INVALID, std::string(who) + ": vertex id out of range");
+    if (c.pinned[0]) fail(GFR_E_INVALID, std::string(who) + ": " + what + " id out of range");
     return d;
 }
 
-int64_t run_advance(Ctx &c, Graph &g, const int32_t *frontier, int32_t nf, int32_t *out_src, int32_t *out_edge,
-                    int32_t *out_dst, int64_t out_cap, hipStream_t s)
+int64_t run_advance(Ctx &c, Graph &g, const int32_t *frontier, int32_t nf, bool edges, int32_t *out_src,
+                    int32_t *out_edge, int32_t *out_dst, int64_t out_cap, hipStream_t s)
 {
     const int64_t ntiles = (nf + SCAN_TILE - 1) / SCAN_TILE;
     const int64_t cap = std::min<int64_t>(out_cap, INT32_MAX);
     const size_t nparts = (size_t)(cap / GATHER_CH) + 2;
-    c.arena.reserve(al256(4ull * nf) + al256(16ull * (ntiles + 1)) + al256(16) + 3 * al256(4ull * nf) +
+    c.arena.reserve(2 * al256(4ull * nf) + al256(16ull * (ntiles + 1)) + al256(16) + 3 * al256(4ull * nf) +
                     al256(4 * nparts));
     int32_t *staging = c.arena.take<int32_t>(nf);
+    int32_t *heads = c.arena.take<int32_t>(nf);
     P2 *totals = c.arena.take<P2>(ntiles + 1);
     uint32_t *bad = c.arena.take<uint32_t>(4);
     FrontierQ q{c.arena.take<int32_t>(nf), c.arena.take<uint32_t>(nf), c.arena.take<int32_t>(nf),
                 c.arena.take<int32_t>(nparts)};
     if (nf == 0) return 0;
-    const int32_t *F = device_list(c, frontier, nf, g.n, staging, bad, s, "advance");
     const int32_t *R = g.R.as<int32_t>();
+    const int32_t *T, *F;   // tags written as out_src; vertices expanded
+    if (edges) {
+        T = device_list(c, frontier, nf, (int32_t)g.m, staging, bad, s, "advance_edges", "edge");
+        hipLaunchKernelGGL(edge_heads, dim3(grid_blocks(c, 2)), dim3(GFR_BLOCK), 0, s, T, (int64_t)nf,
+                           g.C.as<int32_t>(), heads);
+        GFR_LAUNCH_CHECK();
+        F = heads;
+    } else {
+        T = F = device_list(c, frontier, nf, g.n, staging, bad, s, "advance");
+    }
     hipLaunchKernelGGL(scan_reduce<AdvVal>, dim3((uint32_t)ntiles), dim3(GFR_BLOCK), 0, s, AdvVal{F, R}, (int64_t)nf,
                        totals);
     hipLaunchKernelGGL(scan_totals, dim3(1), dim3(GFR_BLOCK), 0, s, totals, ntiles);
@@ -218,7 +242,7 @@ int64_t run_advance(Ctx &c, Graph &g, const int32_t *frontier, int32_t nf, int32
     const int64_t total = (int64_t)grand.a;
     if (total > out_cap || total > INT32_MAX) return total;   // the caller reports the capacity error
     hipLaunchKernelGGL((scan_emit<AdvVal, AdvEmit>), dim3((uint32_t)ntiles), dim3(GFR_BLOCK), 0, s, AdvVal{F, R},
-                       (int64_t)nf, totals, AdvEmit{F, R, q});
+                       (int64_t)nf, totals, AdvEmit{F, T, R, q});
     if (total > 0)
         hipLaunchKernelGGL(advance_emit, dim3(grid_blocks(c, 4)), dim3(GFR_BLOCK), 0, s, q, (uint32_t)grand.b,
                            (uint32_t)total, g.C.as<int32_t>(), out_src, out_edge, out_dst);

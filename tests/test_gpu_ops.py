@@ -1,6 +1,7 @@
 """GPU parity for the advance and filter operators on their own, through the
 C ABI, against their definitions: every frontier edge exactly once, in
-frontier order then CSR order; filter = the ascending distinct kept ids.
+frontier order then CSR order (from a vertex or from an edge frontier);
+filter = the ascending distinct kept ids.
 The graphs include a hub spanning several load-balancing chunks and rows
 whose degrees sit at the wave and chunk sizes and one either side."""
 from __future__ import annotations
@@ -114,6 +115,65 @@ def test_advance_capacity_and_errors(ctx):
     g.free()
 
 
+def _edge_frontiers(row, col, seed=7):
+    m = col.size
+    rng = np.random.default_rng(seed)
+    deg = np.diff(row)
+    into_big = np.nonzero(deg[col] >= 63)[0]        # edges whose far end spans one or more chunks
+    out = {
+        "empty": np.zeros(0, np.int32),
+        "one": np.array([0], np.int32),
+        "last": np.array([m - 1], np.int32),
+        "random_dup_100": rng.integers(0, m, size=100).astype(np.int32),
+        "random_dup_5000": rng.integers(0, m, size=5000).astype(np.int32),
+        "into_big_dup": np.repeat(into_big[:40], 2).astype(np.int32),
+    }
+    if int((deg.astype(np.int64) ** 2).sum()) <= 20_000_000:
+        out["all_edges_reversed"] = np.arange(m - 1, -1, -1, dtype=np.int32)
+    return out
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_edge_advance_matches_definition(ctx, name):
+    import torch
+    row, col = graph(name)
+    g = ctx.graph_load_csr(row, col)
+    for fname, E in _edge_frontiers(row, col).items():
+        _say("advance_edges", name, fname, E.size)
+        src, edge, dst = oracle.advance_edges(row, col, E)
+        for inp in (E, torch.from_numpy(E).cuda()):     # host and device frontiers
+            s, e, d = ctx.advance_edges(g, inp)
+            assert np.array_equal(s.cpu().numpy(), src)
+            assert np.array_equal(e.cpu().numpy(), edge)
+            assert np.array_equal(d.cpu().numpy(), dst)
+    g.free()
+
+
+def test_edge_advance_capacity_and_errors(ctx):
+    import ctypes
+    import paper_1501_05387_amd as gfr
+    row, col = graph("cutoffs")
+    g = ctx.graph_load_csr(row, col)
+    into_hub = np.nonzero(col < 7)[0]
+    E = np.array([into_hub[0], into_hub[-1], col.size - 1], np.int32)   # into hubs 0 and 6, and the last edge
+    deg = np.diff(row)
+    total = int(deg[col[E]].sum())
+    with pytest.raises(gfr.GfrError) as ei:
+        ctx.advance_edges(g, E, out_cap=total - 1)
+    assert ei.value.status == gfr.GFR_E_CAPACITY
+    cnt = ctypes.c_int64()
+    st = gfr.lib().gfr_advance_edges(ctx.ptr, g.handle, E.ctypes.data, E.size, None, None, None, 0,
+                                     ctypes.byref(cnt), None)
+    assert st == gfr.GFR_E_CAPACITY and cnt.value == total
+    s, e, d = ctx.advance_edges(g, E, out_cap=total)
+    assert s.numel() == total
+    for bad in ([col.size], [-1], [0, col.size + 5]):
+        with pytest.raises(gfr.GfrError) as ei:
+            ctx.advance_edges(g, np.array(bad, np.int32))
+        assert ei.value.status == gfr.GFR_E_INVALID
+    g.free()
+
+
 @pytest.mark.parametrize("name", list(GRAPHS))
 def test_filter_matches_definition(ctx, name):
     import torch
@@ -134,9 +194,14 @@ def test_filter_matches_definition(ctx, name):
 
 
 def test_operators_on_a_graph_without_edges(ctx):
+    import paper_1501_05387_amd as gfr
     row = np.zeros(9, np.int32)
     g = ctx.graph_load_csr(row, np.zeros(0, np.int32))
     s, e, d = ctx.advance(g, np.array([3, 3, 0], np.int32))
     assert s.numel() == 0 and e.numel() == 0 and d.numel() == 0
+    assert ctx.advance_edges(g, np.zeros(0, np.int32))[0].numel() == 0
+    with pytest.raises(gfr.GfrError) as ei:               # no edge id is valid
+        ctx.advance_edges(g, np.array([0], np.int32))
+    assert ei.value.status == gfr.GFR_E_INVALID
     assert ctx.filter(g, np.array([5, 1, 5, 7], np.int32)).cpu().numpy().tolist() == [1, 5, 7]
     g.free()
