@@ -812,8 +812,8 @@ static gfr_status advance_call(gfr_ctx *ctx, gfr_graph gh, const int32_t *fronti
                                int32_t *out_src, int32_t *out_edge, int32_t *out_dst, int64_t out_cap,
                                int64_t *count_out, gfr_stream stream)
 {
-    const std::string who = edges ? "advance_edges" : "advance";
     return guard(ctx, [&](Ctx &c) {
+        const std::string who = edges ? "advance_edges" : "advance";
         Graph &g = get_graph(c, gh);
         if (nf < 0 || (nf > 0 && !frontier) || out_cap < 0 || !count_out) fail(GFR_E_INVALID, who + ": bad arguments");
         need_device(out_src, (who + ": out_src").c_str());
