@@ -4,6 +4,8 @@ Each case below copies ``oracle/oracle.c``, plants one mistake of the kind a
 reader might make (a dropped term, a wrong sign or index, a missing case),
 compiles the copy into a temporary library and runs the pins of
 ``test_oracle_pins.py`` against it.  The test passes only if some pin fails.
+The operators' plain-Python definitions get the same treatment: a wrong
+version of the function is swapped in for one run of their pins.
 The real oracle is never modified.
 """
 from __future__ import annotations
@@ -11,6 +13,7 @@ from __future__ import annotations
 import os
 import subprocess
 
+import numpy as np
 import pytest
 
 import oracle
@@ -91,3 +94,70 @@ def test_pins_catch_mutant(tmp_path, name, old, new):
     O = _build_mutant(tmp_path, name, old, new)
     with pytest.raises((AssertionError, ValueError, OverflowError)):
         _all_pins(O)
+
+
+# The operator definitions are plain Python (oracle/__init__.py); their mutants
+# are wrong versions of the same functions, swapped in for one run of the pins.
+_ADVANCE, _ADVANCE_EDGES, _FILTER = oracle.advance, oracle.advance_edges, oracle.filter_ids
+
+def _advance_skips_last_edge(row, col, frontier):
+    row = np.asarray(row, np.int64)
+    src, edge = [], []
+    for u in np.asarray(frontier, np.int64).tolist():
+        e = np.arange(row[u], max(row[u], row[u + 1] - 1), dtype=np.int64)
+        edge.append(e)
+        src.append(np.full(e.size, u, np.int64))
+    edge = np.concatenate(edge) if edge else np.zeros(0, np.int64)
+    src = np.concatenate(src) if src else np.zeros(0, np.int64)
+    return src.astype(np.int32), edge.astype(np.int32), np.asarray(col, np.int32)[edge]
+
+
+def _advance_sorted_frontier(row, col, frontier):
+    return _ADVANCE(row, col, np.sort(np.asarray(frontier, np.int64)))
+
+
+def _advance_edges_from_tail(row, col, edges):
+    row = np.asarray(row, np.int64)
+    col = np.asarray(col, np.int64)
+    tail = np.repeat(np.arange(row.size - 1), np.diff(row))
+    src, edge = [], []
+    for e in np.asarray(edges, np.int64).tolist():
+        v = tail[e]                                      # the edge's own row instead of its far end
+        f = np.arange(row[v], row[v + 1], dtype=np.int64)
+        edge.append(f)
+        src.append(np.full(f.size, e, np.int64))
+    edge = np.concatenate(edge) if edge else np.zeros(0, np.int64)
+    src = np.concatenate(src) if src else np.zeros(0, np.int64)
+    return src.astype(np.int32), edge.astype(np.int32), col[edge].astype(np.int32)
+
+
+def _advance_edges_tags_vertex(row, col, edges):
+    src, edge, dst = _ADVANCE_EDGES(row, col, edges)
+    return np.asarray(col, np.int32)[src], edge, dst     # tags the far end instead of the input edge
+
+
+def _filter_keeps_duplicates(n, items, exclude=None):
+    keep = [v for v in np.asarray(items, np.int64).tolist() if exclude is None or not exclude[v]]
+    return np.array(sorted(keep), np.int32)
+
+
+def _filter_ignores_exclude(n, items, exclude=None):
+    return _FILTER(n, items, None)
+
+
+PY_MUTANTS = [
+    ("advance_skips_last_edge", "advance", _advance_skips_last_edge),
+    ("advance_sorted_frontier", "advance", _advance_sorted_frontier),
+    ("advance_edges_from_tail", "advance_edges", _advance_edges_from_tail),
+    ("advance_edges_tags_vertex", "advance_edges", _advance_edges_tags_vertex),
+    ("filter_keeps_duplicates", "filter_ids", _filter_keeps_duplicates),
+    ("filter_ignores_exclude", "filter_ids", _filter_ignores_exclude),
+]
+
+
+@pytest.mark.parametrize("name,attr,fn", PY_MUTANTS, ids=[m[0] for m in PY_MUTANTS])
+def test_operator_pins_catch_mutant(monkeypatch, name, attr, fn):
+    monkeypatch.setattr(oracle, attr, fn)
+    with pytest.raises((AssertionError, ValueError, IndexError)):
+        pins.test_operator_definitions()
+        pins.test_edge_advance_definition()
