@@ -278,10 +278,16 @@ def suite(args, log):
         ts = _timed(ctx, lambda: ctx.bc(g, src32), 2, warm=1)
         d32 = ctx.bfs_batch(g, src32).view(32, n).cpu().numpy()
         te32 = sum(te_of(row, d32[i]) for i in range(32))
+        bc32 = ctx.bc(g, src32).cpu().numpy().astype(np.float64)
+        ident = float(sum(np.sum(d32[i][d32[i] > 0] - 1, dtype=np.float64) for i in range(32)))
         bc4 = ctx.bc(g, src32[:4]).cpu().numpy().astype(np.float64)
         ref4 = oracle.bc(row, col, src32[:4])
+        nz = ref4 != 0
         d4["bc_32"] = {"ms_median": float(np.median(ts)), "gteps_2x": 2.0 * te32 / (float(np.median(ts)) * 1e-3) / 1e9,
-                       "max_rel_err_4_sources": float(np.max(np.abs(bc4 - ref4) / np.maximum(np.abs(ref4), 1.0)))}
+                       "max_rel_err_4_sources": float(np.max(np.abs(bc4 - ref4) / np.maximum(np.abs(ref4), 1.0))),
+                       "mean_rel_err_4_sources": float(np.mean(np.abs(bc4[nz] - ref4[nz]) / ref4[nz])),
+                       "zero_where_oracle_zero": bool(np.all(bc4[~nz] == 0)),
+                       "identity_rel_residual_32": abs(float(bc32.sum()) - ident) / ident}
         log("d4 bc", d4["bc_32"])
         rep["d4_rmat23"] = d4
         g.free()
