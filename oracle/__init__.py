@@ -25,8 +25,10 @@ Every function follows a textbook definition named in the paper:
 * ``advance``, ``advance_edges``, ``filter_ids``  the two operators by their
   definitions, advance from a vertex or from an edge frontier (plain Python,
   for the operator tests).
+* ``scan``, ``split``  the exclusive prefix sum and the near/far split of a
+  frontier by their definitions (plain Python).
 
-All thirteen are pinned against brute force, closed forms, library routines and
+All fifteen are pinned against brute force, closed forms, library routines and
 invariants in ``tests/test_oracle_pins.py``.
 """
 from __future__ import annotations
@@ -304,6 +306,29 @@ def advance_edges(row, col, edges):
     edge = np.concatenate(edge) if edge else np.zeros(0, np.int64)
     src = np.concatenate(src) if src else np.zeros(0, np.int64)
     return src.astype(np.int32), edge.astype(np.int32), col[edge].astype(np.int32)
+
+
+def scan(values):
+    """Exact exclusive prefix sum (the scan that gives the advance its output
+    offsets, Sec. 4.4): out[i] = values[0] + ... + values[i-1] as uint64, and the
+    total.  numpy's cumulative sum is the step."""
+    v = np.asarray(values, np.uint64)
+    inc = np.cumsum(v, dtype=np.uint64)
+    out = np.zeros(v.size, np.uint64)
+    out[1:] = inc[:-1]
+    return out, int(inc[-1]) if v.size else 0
+
+
+def split(items, dist, threshold):
+    """The near/far split of a frontier (Sec. 4.5, the priority queue): near =
+    the items whose dist is below the threshold, far = the others, each in
+    input order."""
+    near, far = [], []
+    for x in np.asarray(items, np.int64).tolist():
+        if not 0 <= x < len(dist):
+            raise ValueError("oracle.split: vertex out of range")
+        (near if int(dist[x]) < int(threshold) else far).append(x)
+    return np.array(near, np.int32), np.array(far, np.int32)
 
 
 def filter_ids(n, items, exclude=None):

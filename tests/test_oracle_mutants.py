@@ -99,6 +99,7 @@ def test_pins_catch_mutant(tmp_path, name, old, new):
 # The operator definitions are plain Python (oracle/__init__.py); their mutants
 # are wrong versions of the same functions, swapped in for one run of the pins.
 _ADVANCE, _ADVANCE_EDGES, _FILTER = oracle.advance, oracle.advance_edges, oracle.filter_ids
+_SCAN, _SPLIT = oracle.scan, oracle.split
 
 def _advance_skips_last_edge(row, col, frontier):
     row = np.asarray(row, np.int64)
@@ -145,7 +146,31 @@ def _filter_ignores_exclude(n, items, exclude=None):
     return _FILTER(n, items, None)
 
 
+def _scan_inclusive(values):
+    v = np.asarray(values, np.uint64)
+    inc = np.cumsum(v, dtype=np.uint64)
+    return inc, int(inc[-1]) if v.size else 0
+
+
+def _scan_in_32_bits(values):
+    out, tot = _SCAN(values)
+    return out & np.uint64(0xFFFFFFFF), tot & 0xFFFFFFFF
+
+
+def _split_at_or_below(items, dist, threshold):
+    return _SPLIT(items, dist, int(threshold) + 1)
+
+
+def _split_far_reversed(items, dist, threshold):
+    near, far = _SPLIT(items, dist, threshold)
+    return near, far[::-1].copy()
+
+
 PY_MUTANTS = [
+    ("scan_inclusive", "scan", _scan_inclusive),
+    ("scan_in_32_bits", "scan", _scan_in_32_bits),
+    ("split_at_or_below", "split", _split_at_or_below),
+    ("split_far_reversed", "split", _split_far_reversed),
     ("advance_skips_last_edge", "advance", _advance_skips_last_edge),
     ("advance_sorted_frontier", "advance", _advance_sorted_frontier),
     ("advance_edges_from_tail", "advance_edges", _advance_edges_from_tail),
@@ -161,3 +186,5 @@ def test_operator_pins_catch_mutant(monkeypatch, name, attr, fn):
     with pytest.raises((AssertionError, ValueError, IndexError)):
         pins.test_operator_definitions()
         pins.test_edge_advance_definition()
+        pins.test_scan_definition()
+        pins.test_split_definition()

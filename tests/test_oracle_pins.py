@@ -541,3 +541,56 @@ def test_edge_advance_definition():
         assert dst.tolist() == want_dst and np.array_equal(tail[edge], np.repeat(col[E], np.diff(row)[col[E]]))
     with pytest.raises(ValueError):
         oracle.advance_edges(row, col, [col.size])
+
+
+def test_scan_definition():
+    """scan: closed forms (ones give 0..k-1, 0..k-1 give the triangular numbers
+    i(i-1)/2, a constant c gives c*i), sums taken one by one on random inputs,
+    exactness past 2^32 and 2^53, and the empty input."""
+    out, tot = oracle.scan(np.ones(1000, np.uint32))
+    assert out.tolist() == list(range(1000)) and tot == 1000
+    k = 3000
+    out, tot = oracle.scan(np.arange(k, dtype=np.uint32))
+    i = np.arange(k, dtype=np.uint64)
+    assert np.array_equal(out, i * (i - 1) // 2) and tot == k * (k - 1) // 2
+    out, _ = oracle.scan(np.full(500, 7, np.uint32))
+    assert np.array_equal(out, 7 * np.arange(500, dtype=np.uint64))
+    rng = np.random.default_rng(11)
+    for _ in range(10):
+        v = rng.integers(0, 2**32, size=int(rng.integers(1, 60)), dtype=np.uint64).astype(np.uint32)
+        out, tot = oracle.scan(v)
+        acc = 0
+        for j, x in enumerate(v.tolist()):
+            assert int(out[j]) == acc
+            acc += x
+        assert tot == acc
+    big = np.full(3_000_000, 2**32 - 1, np.uint32)             # total above 2^53
+    out, tot = oracle.scan(big)
+    assert tot == 3_000_000 * (2**32 - 1) and int(out[-1]) == 2_999_999 * (2**32 - 1)
+    out, tot = oracle.scan(np.zeros(0, np.uint32))
+    assert out.size == 0 and tot == 0
+
+
+def test_split_definition():
+    """split: a worked example, then on random inputs: near and far together are
+    the items (as a multiset), each keeps the input order, every near item is
+    below the threshold and every far item is not; thresholds 0 and above every
+    value put everything far and near."""
+    dist = np.array([5, 0, 9, 3, 3], np.uint32)
+    near, far = oracle.split([4, 2, 1, 4, 0, 3], dist, 4)
+    assert near.tolist() == [4, 1, 4, 3] and far.tolist() == [2, 0]
+    rng = np.random.default_rng(12)
+    for _ in range(20):
+        n = int(rng.integers(1, 50))
+        d = rng.integers(0, 100, size=n).astype(np.uint32)
+        X = rng.integers(0, n, size=int(rng.integers(0, 80)))
+        t = int(rng.integers(0, 110))
+        near, far = oracle.split(X, d, t)
+        assert sorted(near.tolist() + far.tolist()) == sorted(X.tolist())
+        assert np.all(d[near] < t) and np.all(d[far] >= t)
+        assert near.tolist() == [x for x in X.tolist() if d[x] < t]
+        assert far.tolist() == [x for x in X.tolist() if d[x] >= t]
+        assert oracle.split(X, d, 0)[0].size == 0
+        assert oracle.split(X, d, 101)[1].size == 0
+    with pytest.raises(ValueError):
+        oracle.split([3], np.zeros(3, np.uint32), 1)
