@@ -9,7 +9,8 @@
  * BFS, SSSP, BC, CC and PageRank (Sec. 5), PageRank with per-vertex
  * convergence filtering, 2-hop walk counts and the bipartite rankings of
  * Sec. 5.5 (personalized PageRank, SALSA, HITS).  The two operators are also
- * callable on their own (advance from a vertex or from an edge frontier);
+ * callable on their own (advance from a vertex or from an edge frontier),
+ * with the scan and the near/far split they are built from;
  * batched 64-source BFS / SSSP and a serving runtime
  * sit on top.  All kernels are HIP for gfx950.
  *
@@ -292,6 +293,30 @@ gfr_status gfr_advance_edges(gfr_ctx *ctx, gfr_graph g, const int32_t *edges, in
 gfr_status gfr_filter(gfr_ctx *ctx, gfr_graph g, const int32_t *items, int64_t count,
                       const uint8_t *exclude, int32_t *out, int64_t out_cap, int64_t *count_out,
                       gfr_stream stream);
+
+/*
+ * The scan on its own (Sec. 4.4: the exclusive prefix sum that turns a
+ * frontier's degrees into output offsets): out[i] = in[0] + ... + in[i-1],
+ * exact in 64 bits.  in: count uint32 values, host or device memory.  out:
+ * count uint64 values, device memory.  *total_out (host, may be NULL) = the
+ * sum of all values.  GFR_E_INVALID for a host `out` or missing pointers.
+ */
+gfr_status gfr_scan(gfr_ctx *ctx, const uint32_t *in, int64_t count, uint64_t *out, uint64_t *total_out,
+                    gfr_stream stream);
+
+/*
+ * The near/far split of a frontier on its own (Sec. 4.5, the priority queue
+ * that organises a frontier into a near and a far slice): near_out = the
+ * entries v of `items` with dist[v] < threshold, far_out = the others, each
+ * in input order (duplicates kept).  items: count vertex ids, host or device
+ * memory.  dist: n values, host or device memory.  near_out, far_out: device
+ * memory, out_cap entries each.  *near_count_out, *far_count_out (host) are
+ * always set; GFR_E_CAPACITY (nothing written) if either exceeds out_cap;
+ * GFR_E_INVALID for an id outside [0,n), a host output or missing pointers.
+ */
+gfr_status gfr_split(gfr_ctx *ctx, gfr_graph g, const int32_t *items, int64_t count, const uint32_t *dist,
+                     uint32_t threshold, int32_t *near_out, int32_t *far_out, int64_t out_cap,
+                     int64_t *near_count_out, int64_t *far_count_out, gfr_stream stream);
 
 /* --------------------------------------------- 2-hop and node rankings */
 /*

@@ -69,6 +69,9 @@ SIGNATURES = {
                                      ctypes.POINTER(_f64), _vp]),
     "gfr_advance": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp]),
     "gfr_advance_edges": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp]),
+    "gfr_scan": (_i32, [_vp, _vp, _i64, _vp, ctypes.POINTER(_u64), _vp]),
+    "gfr_split": (_i32, [_vp, _i64, _vp, _i64, _vp, _u32, _vp, _vp, _i64, ctypes.POINTER(_i64),
+                         ctypes.POINTER(_i64), _vp]),
     "gfr_filter": (_i32, [_vp, _i64, _vp, _i64, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp]),
     "gfr_two_hop": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp]),
     "gfr_ppr": (_i32, [_vp, _i64, _vp, _i32, _f64, _f64, _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_f64),
@@ -324,6 +327,46 @@ class Context:
         self._check(lib().gfr_filter(self.ptr, g.handle, ip, cnt_in, ep, out.data_ptr(), cap, ctypes.byref(cnt),
                                      self._stream()))
         return out[:cnt.value]
+
+    def _list_arg(self, x, np_dtype):
+        """(pointer, count, keep-alive) of 32-bit values: a numpy array (converted to
+        np_dtype) or a tensor moved to this device (32-bit tensors are passed as they are)."""
+        torch = _torch()
+        if isinstance(x, torch.Tensor):
+            t = x.to("cuda:%d" % self.device)
+            if t.dtype not in (torch.int32, torch.uint32):
+                t = t.to(torch.int32)
+            t = t.contiguous()
+            return t.data_ptr(), t.numel(), t
+        a = _np(x, np_dtype)
+        return (a.ctypes.data if a.size else None), a.size, a
+
+    def scan(self, values):
+        """Exclusive prefix sum of uint32 values (numpy array or tensor): (uint64 sums as an
+        int64 device tensor, total)."""
+        torch = _torch()
+        vp, cnt_in, keep = self._list_arg(values, np.uint32)
+        out = torch.empty(max(cnt_in, 1), dtype=torch.int64, device="cuda:%d" % self.device)
+        tot = _u64()
+        self._check(lib().gfr_scan(self.ptr, vp, cnt_in, out.data_ptr(), ctypes.byref(tot), self._stream()))
+        del keep
+        return out[:cnt_in], tot.value
+
+    def split(self, g: Graph, items, dist, threshold):
+        """Near/far split of `items` by dist[v] < threshold (dist: n uint32 values, numpy or
+        tensor): (near, far) int32 device tensors, each in input order."""
+        torch = _torch()
+        ip, cnt_in, keep_i = self._list_arg(items, np.int32)
+        dp, nd, keep_d = self._list_arg(dist, np.uint32)
+        if nd != g.n:
+            raise ValueError("split: dist must hold n = %d values" % g.n)
+        cap = max(cnt_in, 1)
+        outs = [torch.empty(cap, dtype=torch.int32, device="cuda:%d" % self.device) for _ in range(2)]
+        nn, nf = _i64(), _i64()
+        self._check(lib().gfr_split(self.ptr, g.handle, ip, cnt_in, dp, int(threshold), outs[0].data_ptr(),
+                                    outs[1].data_ptr(), cap, ctypes.byref(nn), ctypes.byref(nf), self._stream()))
+        del keep_i, keep_d
+        return outs[0][:nn.value], outs[1][:nf.value]
 
     def two_hop(self, g: Graph, seeds, out=None):
         """Walks of length two from the seed set, per end vertex (int64 tensor or uint64 array)."""

@@ -859,6 +859,42 @@ gfr_status gfr_filter(gfr_ctx *ctx, gfr_graph gh, const int32_t *items, int64_t 
     });
 }
 
+gfr_status gfr_scan(gfr_ctx *ctx, const uint32_t *in, int64_t count, uint64_t *out, uint64_t *total_out,
+                    gfr_stream stream)
+{
+    return guard(ctx, [&](Ctx &c) {
+        if (count < 0 || (count > 0 && (!in || !out))) fail(GFR_E_INVALID, "scan: bad arguments");
+        need_device(out, "scan: out");
+        hipStream_t s = pick_stream(c, stream);
+        timed_begin(c, s);
+        const uint64_t total = run_scan(c, in, count, (unsigned long long *)out, s);
+        timed_end(c, s);
+        if (total_out) *total_out = total;
+    });
+}
+
+gfr_status gfr_split(gfr_ctx *ctx, gfr_graph gh, const int32_t *items, int64_t count, const uint32_t *dist,
+                     uint32_t threshold, int32_t *near_out, int32_t *far_out, int64_t out_cap,
+                     int64_t *near_count_out, int64_t *far_count_out, gfr_stream stream)
+{
+    return guard(ctx, [&](Ctx &c) {
+        Graph &g = get_graph(c, gh);
+        if (count < 0 || (count > 0 && (!items || !dist)) || out_cap < 0 || !near_count_out || !far_count_out ||
+            (out_cap > 0 && (!near_out || !far_out)))
+            fail(GFR_E_INVALID, "split: bad arguments");
+        need_device(near_out, "split: near_out");
+        need_device(far_out, "split: far_out");
+        hipStream_t s = pick_stream(c, stream);
+        timed_begin(c, s);
+        int64_t nn = 0, nf = 0;
+        run_split(c, g, items, count, dist, threshold, near_out, far_out, out_cap, &nn, &nf, s);
+        timed_end(c, s);
+        *near_count_out = nn;
+        *far_count_out = nf;
+        if (nn > out_cap || nf > out_cap) fail(GFR_E_CAPACITY, "split: a list exceeds out_cap");
+    });
+}
+
 gfr_status gfr_two_hop(gfr_ctx *ctx, gfr_graph gh, const int32_t *seeds, int32_t k, uint64_t *count_out,
                        gfr_stream stream)
 {

@@ -293,6 +293,12 @@ int64_t run_advance(Ctx &c, Graph &g, const int32_t *frontier, int32_t nf, bool 
                     int32_t *out_edge, int32_t *out_dst, int64_t out_cap, hipStream_t s);
 int64_t run_filter(Ctx &c, Graph &g, const int32_t *items, int64_t count, const uint8_t *exclude, int32_t *out,
                    int64_t out_cap, hipStream_t s);
+// Exclusive uint64 prefix sum of `in` (host or device) into device `out`; returns the total.
+uint64_t run_scan(Ctx &c, const uint32_t *in, int64_t count, unsigned long long *out, hipStream_t s);
+// Near/far split of `items` by dist[item] < threshold into device lists, input order kept; the
+// counts are always set, and nothing is written when either exceeds out_cap.
+void run_split(Ctx &c, Graph &g, const int32_t *items, int64_t count, const uint32_t *dist, uint32_t threshold,
+               int32_t *near, int32_t *far, int64_t out_cap, int64_t *n_near, int64_t *n_far, hipStream_t s);
 // Copy `bytes` of device data to a caller's buffer (device or host memory) and wait.
 void deliver(Ctx &c, void *user, const void *dev, size_t bytes, hipStream_t s);
 // Per-vertex convergence filtering; returns the final frontier membership

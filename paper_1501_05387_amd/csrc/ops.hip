@@ -16,6 +16,12 @@
 //            list of the distinct vertices not excluded by a byte mask:
 //            items leave a mark byte (idempotent stores, Sec. 4.5), and a
 //            scan over the marks compacts them in vertex order.
+//   scan     the exact exclusive prefix sum (uint64) of a uint32 array: the
+//            scan that turns degrees into output offsets (Sec. 4.4), alone.
+//   split    the near/far split of a frontier (Sec. 4.5, priority queue):
+//            items whose distance is below a threshold go to the near list,
+//            the others to the far list, both in input order (one scan of
+//            the pair (near, far) gives every item its slot).
 //
 // Both scans run in three launches: per-tile totals, one work-group scanning
 // the tile totals, and a pass that recomputes each tile's prefix and writes.
@@ -311,6 +317,99 @@ int64_t run_filter(Ctx &c, Graph &g, const int32_t *items, int64_t count, const 
     GFR_LAUNCH_CHECK();
     c.stats.v["kept"] = (double)kept;
     return kept;
+}
+
+// ------------------------------------------------------------- scan
+
+struct ScanVal {
+    const uint32_t *x;
+    __device__ P2 operator()(int64_t i) const { return P2{(unsigned long long)x[i], 0ull}; }
+};
+
+struct ScanEmit {
+    unsigned long long *out;
+    __device__ void operator()(int64_t i, P2, P2 p) const { out[i] = p.a; }
+};
+
+uint64_t run_scan(Ctx &c, const uint32_t *in, int64_t count, unsigned long long *out, hipStream_t s)
+{
+    const int64_t ntiles = (count + SCAN_TILE - 1) / SCAN_TILE;
+    c.arena.reserve(al256(4ull * count) + al256(16ull * (ntiles + 1)));
+    uint32_t *staging = c.arena.take<uint32_t>(count);
+    P2 *totals = c.arena.take<P2>(ntiles + 1);
+    if (count == 0) return 0;
+    const uint32_t *X = in;
+    if (!is_device_ptr(in)) {
+        GFR_HIP(hipMemcpyAsync(staging, in, 4ull * count, hipMemcpyHostToDevice, s));
+        X = staging;
+    }
+    hipLaunchKernelGGL(scan_reduce<ScanVal>, dim3((uint32_t)ntiles), dim3(GFR_BLOCK), 0, s, ScanVal{X}, count, totals);
+    hipLaunchKernelGGL(scan_totals, dim3(1), dim3(GFR_BLOCK), 0, s, totals, ntiles);
+    hipLaunchKernelGGL((scan_emit<ScanVal, ScanEmit>), dim3((uint32_t)ntiles), dim3(GFR_BLOCK), 0, s, ScanVal{X},
+                       count, totals, ScanEmit{out});
+    GFR_LAUNCH_CHECK();
+    GFR_HIP(hipMemcpyAsync(c.pinned, totals + ntiles, sizeof(P2), hipMemcpyDeviceToHost, s));
+    GFR_HIP(hipStreamSynchronize(s));
+    P2 grand;
+    memcpy(&grand, c.pinned, sizeof grand);
+    return grand.a;
+}
+
+// ------------------------------------------------------------- split
+
+struct SplitVal {
+    const int32_t *X;
+    const uint32_t *dist;
+    uint32_t thr;
+    __device__ P2 operator()(int64_t i) const
+    {
+        const bool nr = dist[X[i]] < thr;
+        return P2{nr ? 1ull : 0ull, nr ? 0ull : 1ull};
+    }
+};
+
+struct SplitEmit {
+    const int32_t *X;
+    int32_t *near, *far;
+    __device__ void operator()(int64_t i, P2 x, P2 p) const
+    {
+        if (x.a) near[p.a] = X[i];
+        else far[p.b] = X[i];
+    }
+};
+
+void run_split(Ctx &c, Graph &g, const int32_t *items, int64_t count, const uint32_t *dist, uint32_t threshold,
+               int32_t *near, int32_t *far, int64_t out_cap, int64_t *n_near, int64_t *n_far, hipStream_t s)
+{
+    const int32_t n = g.n;
+    const int64_t ntiles = (count + SCAN_TILE - 1) / SCAN_TILE;
+    c.arena.reserve(al256(4ull * count) + al256(16ull * (ntiles + 1)) + al256(16) + al256(4ull * n));
+    int32_t *staging = c.arena.take<int32_t>(count);
+    P2 *totals = c.arena.take<P2>(ntiles + 1);
+    uint32_t *bad = c.arena.take<uint32_t>(4);
+    uint32_t *dist_dev = c.arena.take<uint32_t>(n);
+    *n_near = *n_far = 0;
+    if (count == 0) return;
+    const int32_t *X = device_list(c, items, count, n, staging, bad, s, "split");
+    const uint32_t *D = dist;
+    if (!is_device_ptr(dist)) {
+        GFR_HIP(hipMemcpyAsync(dist_dev, dist, 4ull * n, hipMemcpyHostToDevice, s));
+        D = dist_dev;
+    }
+    const SplitVal val{X, D, threshold};
+    hipLaunchKernelGGL(scan_reduce<SplitVal>, dim3((uint32_t)ntiles), dim3(GFR_BLOCK), 0, s, val, count, totals);
+    hipLaunchKernelGGL(scan_totals, dim3(1), dim3(GFR_BLOCK), 0, s, totals, ntiles);
+    GFR_LAUNCH_CHECK();
+    GFR_HIP(hipMemcpyAsync(c.pinned, totals + ntiles, sizeof(P2), hipMemcpyDeviceToHost, s));
+    GFR_HIP(hipStreamSynchronize(s));
+    P2 grand;
+    memcpy(&grand, c.pinned, sizeof grand);
+    *n_near = (int64_t)grand.a;
+    *n_far = (int64_t)grand.b;
+    if (*n_near > out_cap || *n_far > out_cap) return;   // the caller reports the capacity error
+    hipLaunchKernelGGL((scan_emit<SplitVal, SplitEmit>), dim3((uint32_t)ntiles), dim3(GFR_BLOCK), 0, s, val, count,
+                       totals, SplitEmit{X, near, far});
+    GFR_LAUNCH_CHECK();
 }
 
 }  // namespace gfr

@@ -1,7 +1,8 @@
 """GPU parity for the advance and filter operators on their own, through the
 C ABI, against their definitions: every frontier edge exactly once, in
 frontier order then CSR order (from a vertex or from an edge frontier);
-filter = the ascending distinct kept ids.
+filter = the ascending distinct kept ids; scan = the exact exclusive prefix
+sum; split = the near and far lists in input order.
 The graphs include a hub spanning several load-balancing chunks and rows
 whose degrees sit at the wave and chunk sizes and one either side."""
 from __future__ import annotations
@@ -190,6 +191,76 @@ def test_filter_matches_definition(ctx, name):
         got = ctx.filter(g, torch.from_numpy(X).cuda(), torch.from_numpy(ex).cuda())
         assert np.array_equal(got.cpu().numpy(), want)
     assert ctx.filter(g, np.arange(n, dtype=np.int32), np.ones(n, np.uint8)).numel() == 0
+    g.free()
+
+
+SCAN_SIZES = (0, 1, 2047, 2048, 2049, 100_000, 3_000_001)   # tile is 2048: empty, one, ragged, several tiles
+
+
+@pytest.mark.parametrize("count", SCAN_SIZES)
+def test_scan_matches_definition(ctx, count):
+    import torch
+    rng = np.random.default_rng(count + 1)
+    for kind in ("small", "full"):
+        hi = 100 if kind == "small" else 2**32
+        v = rng.integers(0, hi, size=count, dtype=np.uint64).astype(np.uint32)
+        _say("scan", count, kind)
+        want, tot = oracle.scan(v)
+        for inp in (v, torch.from_numpy(v.view(np.int32)).cuda()):   # host and device input
+            out, total = ctx.scan(inp)
+            assert total == tot
+            assert np.array_equal(out.cpu().numpy().view(np.uint64), want)
+
+
+def test_scan_past_2_pow_53(ctx):
+    v = np.full(3_000_000, 2**32 - 1, np.uint32)
+    out, total = ctx.scan(v)
+    assert total == 3_000_000 * (2**32 - 1)
+    got = out.cpu().numpy().view(np.uint64)
+    assert int(got[-1]) == 2_999_999 * (2**32 - 1) and int(got[1_234_567]) == 1_234_567 * (2**32 - 1)
+
+
+@pytest.mark.parametrize("name", ["rmat12", "grid96", "cutoffs"])
+def test_split_matches_definition(ctx, name):
+    import torch
+    row, col = graph(name)
+    n = row.size - 1
+    g = ctx.graph_load_csr(row, col)
+    rng = np.random.default_rng(13)
+    dist = rng.integers(0, 1000, size=n, dtype=np.uint64).astype(np.uint32)
+    dist[:5] = 0xFFFFFFFF                                          # unreached vertices are always far
+    for fname, X in _frontiers(row).items():
+        for thr in (0, 1, 500, 1000, 0xFFFFFFFF):
+            _say("split", name, fname, X.size, thr)
+            near, far = oracle.split(X, dist, thr)
+            for xs, ds in ((X, dist), (torch.from_numpy(X).cuda(), torch.from_numpy(dist.view(np.int32)).cuda())):
+                gn, gf = ctx.split(g, xs, ds, thr)
+                assert np.array_equal(gn.cpu().numpy(), near)
+                assert np.array_equal(gf.cpu().numpy(), far)
+    g.free()
+
+
+def test_split_capacity_and_errors(ctx):
+    import ctypes
+    import paper_1501_05387_amd as gfr
+    row, col = graph("grid96")
+    n = row.size - 1
+    g = ctx.graph_load_csr(row, col)
+    dist = (np.arange(n) % 7).astype(np.uint32)
+    X = np.arange(100, dtype=np.int32)
+    want_near, want_far = oracle.split(X, dist, 3)
+    nn, nf = ctypes.c_int64(), ctypes.c_int64()
+    st = gfr.lib().gfr_split(ctx.ptr, g.handle, X.ctypes.data, X.size, dist.ctypes.data, 3, None, None, 0,
+                             ctypes.byref(nn), ctypes.byref(nf), None)
+    assert st == gfr.GFR_E_CAPACITY and (nn.value, nf.value) == (want_near.size, want_far.size)
+    for bad in ([n], [-1]):
+        with pytest.raises(gfr.GfrError) as ei:
+            ctx.split(g, np.array(bad, np.int32), dist, 3)
+        assert ei.value.status == gfr.GFR_E_INVALID
+    out = np.empty(100, np.int32)                                  # host outputs are refused
+    st = gfr.lib().gfr_split(ctx.ptr, g.handle, X.ctypes.data, X.size, dist.ctypes.data, 3, out.ctypes.data,
+                             out.ctypes.data, 100, ctypes.byref(nn), ctypes.byref(nf), None)
+    assert st == gfr.GFR_E_INVALID
     g.free()
 
 
