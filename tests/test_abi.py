@@ -47,6 +47,26 @@ def test_library_has_no_oracle_dependency():
     assert b"or_bfs" not in data and b"liboracle" not in data
 
 
+def test_package_never_reaches_the_oracle():
+    # no module of the product package (nor its kernels' sources) names the oracle
+    pkg = os.path.dirname(gfr.__file__)
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "liboracle" not in text and "or_bfs" not in text, f
+
+
+def test_binding_fails_loudly_without_the_library():
+    # a fresh interpreter pointed at a missing library must raise, not fall back
+    code = ("import sys; sys.path.insert(0, %r); import paper_1501_05387_amd as g; "
+            "g.LIB_PATH = '/nonexistent/libgfr.so'\n"
+            "try:\n    g.Context(0)\nexcept ImportError:\n    sys.exit(0)\nsys.exit(3)") % ROOT
+    import subprocess
+    import sys
+    assert subprocess.run([sys.executable, "-c", code], timeout=300).returncode == 0
+
+
 def test_validate_accepts_generated_graphs():
     row, col = graphgen.rmat(10)
     w = graphgen.weights(row, col)
