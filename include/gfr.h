@@ -92,6 +92,9 @@ const char *gfr_last_error(const gfr_ctx *ctx);
  *   "bfs.alpha"       push->pull when frontier edges > unvisited edges / alpha
  *   "bfs.beta"        pull->push when frontier vertices < n / beta
  *   "bfs.dedup"       0 atomic claim (each vertex enqueued once), 1 idempotent (Sec. 4.5)
+ *   "bfs.frontier"    0 auto, 1 queue levels (advance + compaction), 2 mark-byte levels:
+ *                     the frontier is a byte per vertex, one launch per level, push
+ *                     only (auto: mark bytes on mesh-class graphs unless pull is forced)
  *   "sssp.delta"      bucket width of the near/far priority queue (Sec. 4.5);
  *                     0 = "sssp.delta_factor" (default 2) times the mean edge weight
  *   "advance.chunk"   edges per work-group chunk of the load-balanced advance (Sec. 4.4),

@@ -289,6 +289,7 @@ struct OptKey {
 static const OptKey kOptKeys[] = {
     {"bfs.direction", 0, 2, true},       {"bfs.alpha", 1e-6, 1e9, true},
     {"bfs.beta", 1e-6, 1e9, true},       {"bfs.dedup", 0, 1, true},
+    {"bfs.frontier", 0, 2, true},
     {"sssp.delta", 0, 4.0e9, true},      {"advance.chunk", 256, 4096, true},
     {"sssp.delta_factor", 1e-3, 1e6, true}, {"batch.delta_factor", 0, 1e6, true},
     {"msbfs.alpha", 1e-6, 1e9, true},    {"batch.delta", 0, 4.0e9, true},
@@ -315,6 +316,7 @@ void option_set(Options &o, const std::string &key, double v)
     else if (key == "bfs.alpha") o.bfs_alpha = v;
     else if (key == "bfs.beta") o.bfs_beta = v;
     else if (key == "bfs.dedup") o.bfs_dedup = (int)v;
+    else if (key == "bfs.frontier") o.bfs_frontier = (int)v;
     else if (key == "sssp.delta") o.sssp_delta = v;
     else if (key == "sssp.delta_factor") o.sssp_delta_factor = v;
     else if (key == "batch.delta_factor") o.batch_delta_factor = v;
@@ -347,6 +349,7 @@ static double option_get(const Options &o, const std::string &key)
     if (key == "bfs.alpha") return o.bfs_alpha;
     if (key == "bfs.beta") return o.bfs_beta;
     if (key == "bfs.dedup") return o.bfs_dedup;
+    if (key == "bfs.frontier") return o.bfs_frontier;
     if (key == "sssp.delta") return o.sssp_delta;
     if (key == "sssp.delta_factor") return o.sssp_delta_factor;
     if (key == "batch.delta_factor") return o.batch_delta_factor;

@@ -23,6 +23,18 @@
 //               (the rule of Sec. 4.5, with tunable ratios alpha and beta).
 // The control state lives in device memory, so the host enqueues levels
 // speculatively and only reads one word back every few levels.
+//
+// On mesh-like graphs (small, even degrees, long diameters) the frontier is
+// kept as mark bytes only, with one launch per level (bfs_bitmap_level): each
+// thread scans 16 mark bytes of the current level, consumes them, and expands
+// every marked vertex's list (through a per-work-group LDS list); an unvisited
+// neighbour (depth still -1) gets its depth and a mark byte for the next level,
+// with plain idempotent stores
+// (Sec. 4.5).  There is no queue and no compaction: on such graphs a level's
+// cost is the chain of memory round trips of its launches, and this halves the
+// number of launches and drops the compaction's scan and look-back.  Each
+// work-group records whether it marked anything; the next launch's first
+// work-group reads those flags and ends the traversal when all are zero.
 #include "compact.h"
 #include "device.h"
 #include "engine.h"
@@ -246,8 +258,153 @@ __global__ void bfs_init(BfsArgs a, int32_t src, uint32_t chunk, uint32_t force,
     for (uint32_t c = threadIdx.x; (uint64_t)c * chunk < (uint64_t)deg; c += blockDim.x) a.q.part[c] = 0;
 }
 
+struct BmArgs {
+    const int32_t *R;
+    const int32_t *C;
+    int32_t n;
+    int32_t *depth;
+    uint8_t *mk[2];      // mark bytes of the frontier, by level parity (n rounded up to 16 bytes)
+    uint32_t *flags;     // [2][gridDim]: did the work-group mark a vertex, by level parity
+    BfsCtl *ctl;
+};
+
+__global__ void bfs_bitmap_init(BmArgs a, int32_t src)
+{
+    BfsCtl *ctl = a.ctl;
+    a.depth[src] = 0;
+    a.mk[0][src] = 1;
+    ctl->dir = DIR_PUSH;
+    ctl->level = 0;
+    ctl->err = 0;
+    ctl->push_levels = ctl->pull_levels = 0;
+    ctl->push_entries = ctl->push_edges = ctl->push_new = 0ull;
+    ctl->pull_unvisited = ctl->pull_inspected = ctl->pull_new = 0ull;
+}
+
+// level L of a mark-byte traversal (one launch per level; L is the launch index)
+__global__ __launch_bounds__(GFR_BLOCK) void bfs_bitmap_level(BmArgs a, int32_t L)
+{
+    BfsCtl *ctl = a.ctl;
+    if (ctl->dir == DIR_DONE) return;
+    const uint32_t G = gridDim.x;
+    uint8_t *cur = a.mk[L & 1];
+    uint8_t *nxt = a.mk[(L & 1) ^ 1];
+    if (L > 0 && blockIdx.x == 0) {
+        // the previous level marked nothing: this level's frontier is empty
+        const uint32_t *fprev = a.flags + (size_t)((L & 1) ^ 1) * G;
+        uint32_t any = 0;
+        for (uint32_t i = threadIdx.x; i < G; i += GFR_BLOCK) any |= fprev[i];
+        if (!__syncthreads_or((int)any)) {
+            if (threadIdx.x == 0) {
+                ctl->level = L;
+                ctl->push_levels = (uint32_t)L;
+                ctl->dir = DIR_DONE;
+            }
+            return;
+        }
+    }
+    // Rounds of 256 chunks of 16 mark bytes per work-group: the marked
+    // vertices of a round are appended to an LDS list, then the whole group
+    // expands the list, one vertex per thread, with the column and depth loads
+    // of eight edges issued before any test.
+    constexpr int BM_LIST = GFR_BLOCK * 16;
+    __shared__ int32_t s_v[BM_LIST];
+    __shared__ uint32_t s_cnt;
+    int found = 0;
+    const size_t nchunks = ((size_t)a.n + 15) / 16;
+    for (size_t c0 = (size_t)blockIdx.x * GFR_BLOCK; c0 < nchunks; c0 += (size_t)G * GFR_BLOCK) {
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        const size_t ci = c0 + threadIdx.x;
+        if (ci < nchunks) {
+            uint4 *p = (uint4 *)(cur + ci * 16);
+            const uint4 w = *p;
+            if ((w.x | w.y | w.z | w.w) != 0u) {
+                *p = make_uint4(0u, 0u, 0u, 0u);   // consumed: clean when it next receives marks
+                const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if ((ws[j >> 2] >> (8 * (j & 3))) & 0xFFu) s_v[atomicAdd(&s_cnt, 1u)] = (int32_t)(ci * 16 + j);
+            }
+        }
+        __syncthreads();
+        const uint32_t cnt = s_cnt;   // at most 16 per thread: fits BM_LIST
+        for (uint32_t i = threadIdx.x; i < cnt; i += GFR_BLOCK) {
+            const int32_t v = s_v[i];   // only vertices < n are ever marked
+            const int32_t e1 = a.R[v + 1];
+            for (int32_t e = a.R[v]; e < e1; e += 8) {
+                int32_t u[8], d[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) u[k] = a.C[min(e + k, e1 - 1)];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) d[k] = a.depth[u[k]];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if (e + k < e1 && d[k] < 0) {
+                        a.depth[u[k]] = L + 1;
+                        nxt[u[k]] = 1;
+                        found = 1;
+                    }
+                }
+            }
+        }
+        __syncthreads();   // the list is reused by the next round
+    }
+    found = __syncthreads_or(found);
+    if (threadIdx.x == 0) a.flags[(size_t)(L & 1) * G + blockIdx.x] = (uint32_t)found;
+}
+
+static void run_bfs_bitmap(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s)
+{
+    const int32_t n = g.n;
+    const size_t nb = ((size_t)n + 15) / 16 * 16;
+    const int G = grid_blocks(c, 8);
+    c.arena.reserve(2 * al256(nb) + al256(8ull * G) + al256(sizeof(BfsCtl)));
+    BmArgs a;
+    a.R = g.R.as<int32_t>();
+    a.C = g.C.as<int32_t>();
+    a.n = n;
+    a.depth = depth;
+    a.mk[0] = c.arena.take<uint8_t>(nb);
+    a.mk[1] = c.arena.take<uint8_t>(nb);
+    a.flags = c.arena.take<uint32_t>(2ull * G);
+    a.ctl = c.arena.take<BfsCtl>(1);
+    fill_u32(depth, 0xFFFFFFFFu, (size_t)n, s);
+    fill_u32(a.mk[0], 0u, nb / 4, s);
+    fill_u32(a.mk[1], 0u, nb / 4, s);
+    fill_u32(a.flags, 0u, 2ull * G, s);
+    hipLaunchKernelGGL(bfs_bitmap_init, dim3(1), dim3(1), 0, s, a, src);
+    GFR_LAUNCH_CHECK();
+    int32_t level = 0;
+    auto launch = [&]() {
+        c.ktimer.run("bfs_bitmap_level", s, [&]() {
+            hipLaunchKernelGGL(bfs_bitmap_level, dim3(G), dim3(GFR_BLOCK), 0, s, a, level);
+        });
+        ++level;
+    };
+    const int32_t launched = run_until_done(c, &a.ctl->dir, DIR_DONE, g.bfs_levels_hint + 2, (int64_t)n + 4, s,
+                                            launch);
+    BfsCtl h;
+    GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
+    GFR_HIP(hipStreamSynchronize(s));
+    memcpy(&h, c.pinned, sizeof(BfsCtl));
+    c.stats.v["levels"] += h.level;
+    c.stats.v["push_levels"] += h.push_levels;
+    c.stats.v["pull_levels"] += 0.0;
+    c.stats.v["launches"] += launched;
+    c.stats.v["solves"] += 1.0;
+    g.bfs_levels_hint = h.level;
+}
+
 void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s)
 {
+    // mark-byte levels on mesh-like graphs (bfs.frontier 0 auto, 1 queue, 2 mark bytes); a forced pull
+    // direction needs the queue path's frontier bitmap
+    const int fr = c.opt.bfs_frontier;
+    if (c.opt.bfs_direction != 2 && (fr == 2 || (fr == 0 && g.cls == GRAPH_MESH))) {
+        run_bfs_bitmap(c, g, src, depth, s);
+        return;
+    }
     const int32_t n = g.n;
     const uint32_t chunk = (uint32_t)c.opt.advance_chunk;
     const uint32_t nwords = (uint32_t)(((int64_t)n + 63) / 64) * 2u;

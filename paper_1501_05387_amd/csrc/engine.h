@@ -115,6 +115,7 @@ struct Options {
     double bfs_alpha = 15.0;
     double bfs_beta = 18.0;
     int bfs_dedup = 0;          // 0 atomic, 1 idempotent
+    int bfs_frontier = 0;       // 0 auto (mark bytes on mesh-class graphs), 1 queue, 2 mark bytes
     double sssp_delta = 0.0;    // 0 -> sssp_delta_factor x mean edge weight
     double sssp_delta_factor = 2.0;
     int advance_chunk = 1024;

@@ -168,8 +168,10 @@ def suite(args, log):
         dep = ctx.bfs_batch(g, srcs).view(64, n).cpu().numpy()
         te = np.array([te_of(row, dep[i]) for i in range(64)], dtype=np.float64)
         d2 = {}
-        for mode, direction in (("push_bfs", 1), ("do_bfs", 0)):
+        for mode, direction, frontier in (("push_bfs", 1, 0), ("do_bfs", 0, 0), ("queue_push_bfs", 1, 1),
+                                          ("queue_do_bfs", 0, 1)):
             ctx.set_option("bfs.direction", direction)
+            ctx.set_option("bfs.frontier", frontier)
             gt, gbs, lvls = [], [], []
             for i, sidx in enumerate(srcs):
                 ts = _timed(ctx, lambda: ctx.bfs(g, int(sidx)), 10, warm=1)
@@ -182,6 +184,7 @@ def suite(args, log):
                         "alg_frac_of_peak_p50": float(np.median(gbs)) / HBM_PEAK_GBS, "levels_p50": float(np.median(lvls))}
             log("d2", mode, d2[mode]["gteps"])
         ctx.set_option("bfs.direction", 0)
+        ctx.set_option("bfs.frontier", 0)
         gt, gbs, rr = [], [], []
         for i, sidx in enumerate(srcs):
             ts = _timed(ctx, lambda: ctx.sssp(g, int(sidx)), 10, warm=1)
@@ -216,8 +219,10 @@ def suite(args, log):
         srcs = graphgen.sample_sources(row, col, 16)
         g = ctx.graph_load_csr(row, col, w)
         d3 = {}
-        for mode, direction in (("push_bfs", 1), ("do_bfs", 0)):
+        for mode, direction, frontier in (("push_bfs", 1, 0), ("do_bfs", 0, 0), ("queue_push_bfs", 1, 1),
+                                          ("queue_do_bfs", 0, 1)):
             ctx.set_option("bfs.direction", direction)
+            ctx.set_option("bfs.frontier", frontier)
             gt, upl, logs = [], [], []
             for sidx in srcs:
                 ts = _timed(ctx, lambda: ctx.bfs(g, int(sidx)), 3, warm=1)

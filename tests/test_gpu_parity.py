@@ -104,6 +104,27 @@ def test_bfs_matches_oracle(ctx, name, direction):
         g.free()
 
 
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("frontier", [1, 2])
+def test_bfs_frontier_representations(ctx, name, frontier):
+    """Queue levels (advance + compaction) and mark-byte levels (one launch per
+    level) give the oracle's depths on every graph, whichever the graph class."""
+    row, col, w = graph(name)
+    g = _load(ctx, row, col)
+    ctx.set_option("bfs.frontier", frontier)
+    try:
+        for s in _sources(row, col, 4):
+            _say("bfs", name, "frontier", frontier, "src", s)
+            got = _host(ctx.bfs(g, s))
+            want = oracle.bfs(row, col, s)
+            assert np.array_equal(got, want), (name, frontier, s, int(np.sum(got != want)))
+            if frontier == 2:
+                assert ctx.stat("levels") == int(want.max()) + 1 and ctx.stat("pull_levels") == 0
+    finally:
+        ctx.set_option("bfs.frontier", 0)
+        g.free()
+
+
 def test_bfs_rmat16_from_vertex0_all_chunks(ctx):
     row, col, _ = graph("rmat16")
     g = _load(ctx, row, col)
