@@ -177,7 +177,9 @@ gfr_status gfr_graph_info(gfr_ctx *ctx, gfr_graph g, int32_t *n, int64_t *m,
 /*
  * Breadth-first search (Sec. 5.1): depth_out[v] = hop distance from `source`,
  * depth_out[source] = 0, unreached vertices -1.  n int32 elements.
- * Level-synchronous advance + filter with a per-level push/pull choice.
+ * Level-synchronous advance + filter with a per-level push/pull choice; on
+ * mesh-class graphs the frontier stays as mark bytes, one launch per level
+ * (option "bfs.frontier").  The depths are the same either way.
  * pred_out (n int32, may be NULL): a BFS tree read off the depths --
  * pred[source] = source, unreached -1, otherwise the first neighbour in v's
  * row one level up (the smallest such id when rows are sorted).
