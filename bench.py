@@ -52,12 +52,35 @@ def bfs_bytes(st: dict, solves: int, n: int) -> float:
     return push + pull
 
 
-def bsssp_bytes(st: dict, n: int) -> float:
-    """Algorithmic bytes of bsssp_relax (64 queries per pass): per edge visit the
-    column and weight (8 B) and the target's 256-byte distance row; per
-    improvement one 4-byte atomic.  (The 8-byte query-mask atomicOr of an
-    improved edge visit is left out, so the figure is a lower bound.)"""
+def bsssp_bytes(st: dict) -> float:
+    """Algorithmic bytes of bsssp_relax over its queries, by the SSSP work model:
+    16 B per (vertex, query) frontier entry (queue slot and distance), 12 B per
+    (edge, query) relaxation (column, weight, target distance) and 8 B per
+    improvement (the atomic update and its mark).  These are the method's own
+    bytes, the same per query as for a single-source solve; the batched kernel
+    shares every column and weight among the queries active on an edge."""
+    return 16 * st["pair_entries"] + 12 * st["lane_relaxations"] + 8 * st["improvements"]
+
+
+def bsssp_row_bytes(st: dict) -> float:
+    """Bytes the batched layout moves per edge visit: column and weight (8 B)
+    plus the target's whole 64-query distance row (256 B), plus 4 B per
+    improvement.  A layout figure (what the kernel touches), not the work
+    model."""
     return (8 + 256) * st["relaxations"] + 4 * st["improvements"]
+
+
+def host_cpu() -> tuple:
+    """(logical cores, CPU model name) of this host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return os.cpu_count() or 0, model
 
 
 def msbfs_bytes(st: dict, n: int) -> float:
@@ -77,8 +100,8 @@ def sssp_bytes(st: dict) -> float:
 
 
 STAT_KEYS = ["m", "push_entries", "push_edges", "push_new", "pull_levels", "pull_unvisited",
-             "pull_inspected", "pull_new", "near_entries", "relaxations", "improvements",
-             "far_entries", "iterations", "levels", "launches", "solves"]
+             "pull_inspected", "pull_new", "near_entries", "relaxations", "lane_relaxations",
+             "pair_entries", "improvements", "far_entries", "iterations", "levels", "launches", "solves"]
 
 
 def read_stats(ctx, keys):
@@ -136,21 +159,49 @@ def serve_leg(ctx, resident, nq, log, rates=SERVE_RATES):
             torch.cuda.synchronize()
             ctx.stat("serve.reset")
             done = {}
+            t_sub = np.zeros(nq)
+            t_end = {}
+            tick_of = {}
+
+            def drain(timeout_us):
+                got = ctx.poll(256, timeout_us)
+                now = time.perf_counter()
+                for t, st in got:
+                    done[t] = st
+                    t_end[t] = now
+
             t0 = time.perf_counter()
             for i in range(nq):
                 while time.perf_counter() - t0 < arrive[i]:
-                    done.update(ctx.poll(256, 0))
-                ctx.submit_queries([(int(kinds[i]), resident[scales[i]][3], srcs[i], outs[i])])
+                    drain(0)
+                t_sub[i] = time.perf_counter()
+                tick_of[ctx.submit_queries([(int(kinds[i]), resident[scales[i]][3], srcs[i], outs[i])])[0]] = i
             while len(done) < nq:
-                done.update(ctx.poll(256, 100000))
+                drain(100000)
             span = time.perf_counter() - t0
             ok = all(st == gfr.GFR_OK for st in done.values()) and all(
                 torch.equal(outs[i], ref[(scales[i], int(kinds[i]), srcs[i])]) for i in range(nq))
+            # per-query latency seen by the caller (submit -> poll returns it), by class
+            lat = np.zeros(nq)
+            for t, i in tick_of.items():
+                lat[i] = (t_end[t] - t_sub[i]) * 1e3
+            p99 = float(np.percentile(lat, 99))
+            cls = {}
+            for sc in SERVE_SCALES:
+                for kd, kn in ((gfr.GFR_Q_BFS, "bfs"), (gfr.GFR_Q_SSSP, "sssp")):
+                    sel = np.array([scales[i] == sc and kinds[i] == kd for i in range(nq)])
+                    if sel.any():
+                        cls["s%d_%s" % (sc, kn)] = {"n": int(sel.sum()),
+                                                   "p50_ms": round(float(np.percentile(lat[sel], 50)), 3),
+                                                   "p99_ms": round(float(np.percentile(lat[sel], 99)), 3),
+                                                   "in_tail": int((lat[sel] > p99).sum())}
             pts.append({"offered_qps": rate if rate < 1e8 else None, "qps": round(nq / span, 1),
                         "p50_ms": round(ctx.stat("serve.p50_ms"), 3), "p99_ms": round(ctx.stat("serve.p99_ms"), 3),
+                        "caller_p50_ms": round(float(np.percentile(lat, 50)), 3), "caller_p99_ms": round(p99, 3),
                         "mean_batch": round(ctx.stat("serve.mean_batch"), 2),
-                        "joined_running": int(ctx.stat("serve.joined")), "results_equal": bool(ok)})
-            log("serve %s rate %s: %s" % (mode, rate, pts[-1]))
+                        "joined_running": int(ctx.stat("serve.joined")), "results_equal": bool(ok),
+                        "by_class": cls})
+            log("serve %s rate %s: %s" % (mode, rate, {k: v for k, v in pts[-1].items() if k != "by_class"}))
         res[mode] = pts
     ctx.set_option("serve.max_batch", 64)
     res["queries_per_point"] = nq
@@ -169,7 +220,7 @@ def main():
     ap.add_argument("--sources", type=int, default=64)
     ap.add_argument("--cpu-sources", type=int, default=5, help="oracle sample size (sources, about 12 s of CPU work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-queries", type=int, default=512, help="queries per serving point (0: skip)")
+    ap.add_argument("--serve-queries", type=int, default=10000, help="queries per serving point (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="finish with one device copy of this many MiB (a known-size kernel that "
                          "calibrates the HBM byte counters of a profiler run)")
@@ -286,24 +337,39 @@ def main():
     ss = ss_acc
     ktimes = {k: tuple(v) for k, v in kacc.items()}
     kernels = {k: {"ms": v[0], "launches": v[1]} for k, v in ktimes.items()}
-    kernels["bsssp_relax"]["bytes"] = bsssp_bytes(ss, n)
+    kernels["bsssp_relax"]["bytes"] = bsssp_bytes(ss)
+    kernels["bsssp_relax"]["row_layout_bytes"] = bsssp_row_bytes(ss)
     kernels["msbfs_level"]["bytes"] = msbfs_bytes(sb, n)
     for k in ("bsssp_relax", "msbfs_level"):
         kernels[k]["GBs"] = kernels[k]["bytes"] / max(kernels[k]["ms"], 1e-9) / 1e6
     dom = max(("msbfs_level", "bsssp_relax"), key=lambda k: kernels[k]["ms"])
     kd = kernels[dom]
     achieved = kd["bytes"] / kd["launches"] / (kd["ms"] / kd["launches"] * 1e-3) / 1e9
-    traffic = None
+    # measured HBM bytes per launch: not counted by this run (a counter run
+    # is a profiler pass of its own); taken from the committed counter
+    # summary when it was made for the current kernel sources, else null
+    traffic, traffic_src = None, None
     tfile = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tfile):
         tj = json.load(open(tfile))
         ent = tj.get("%s/rmat%d" % (dom, args.scale))
         if ent and ent.get("source_digest") == kernel_source_digest():
             traffic = ent.get("bytes_per_launch")
+            traffic_src = "copied from profiles/traffic.json (rocprofv3 FETCH_SIZE + WRITE_SIZE, same kernel sources)"
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_source": traffic_src,
                 "bytes_per_launch": kd["bytes"] / kd["launches"],
+                "bytes_model": ("16 B per (vertex, query) frontier entry + 12 B per (edge, query) relaxation "
+                                "+ 8 B per improvement" if dom == "bsssp_relax" else "see msbfs_bytes"),
                 "avg_launch_us": kd["ms"] / kd["launches"] * 1e3}
+    if dom == "bsssp_relax":
+        roofline["row_layout_bytes_per_launch"] = kd["row_layout_bytes"] / kd["launches"]
+        # re-relaxation factor: (edge, query) relaxations over the edges the
+        # queries reach (sum of reached degrees), the floor of one relaxation each
+        roofline["r_lane"] = round(ss["lane_relaxations"] / (te_sssp * args.steps), 4)
+        roofline["edge_visits_per_batch_over_m"] = round(
+            ss["relaxations"] / args.steps / max(1, (args.sources + 63) // 64) / m, 4)
     log("kernels:", json.dumps(kernels))
 
     cpu = None
@@ -324,9 +390,11 @@ def main():
             te += 2 * int(np.diff(row)[reached].sum())
             ok = ok and np.array_equal(d2[i].cpu().numpy(), db)
             ok = ok and np.array_equal(s2[i].cpu().numpy().view(np.uint32), ds)
+        ncores, model = host_cpu()
         cpu = {"value": round(te / tc / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-               "sample": "queue BFS + binary-heap Dijkstra from %d of the %d sources, 1 thread, "
-                         "%.1f s" % (k, args.sources, tc)}
+               "host_cores": ncores, "cpu_model": model,
+               "sample": "queue BFS + binary-heap Dijkstra from %d of the %d sources, 1 thread of %d host "
+                         "cores (%s), %.1f s" % (k, args.sources, ncores, model, tc)}
         parity = ok
         log("cpu oracle: %.3f GTEPS on %d source(s), parity %s" % (te / tc / 1e9, k, ok))
 
@@ -385,6 +453,9 @@ def main():
         torch.bitwise_not(a, out=b)
         torch.cuda.synchronize()
         log("copy probe: bitwise_not over %d MiB (reads and writes %d bytes)" % (args.copy_probe_mib, nw * 4))
+        # a second known-size kernel that only reads: the sum of the same words
+        tot = int(torch.sum(a).item())
+        log("read probe: sum over %d MiB (reads %d bytes), total %d" % (args.copy_probe_mib, nw * 4, tot))
         del a, b
     g.free()
     ctx.close()

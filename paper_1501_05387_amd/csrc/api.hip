@@ -294,7 +294,8 @@ static const OptKey kOptKeys[] = {
     {"sssp.delta_factor", 1e-3, 1e6, true}, {"batch.delta_factor", 0, 1e6, true},
     {"msbfs.alpha", 1e-6, 1e9, true},    {"batch.delta", 0, 4.0e9, true},
     {"batch.min_bfs", 1, 1e9, true},     {"batch.min_sssp", 1, 1e9, true},
-    {"batch.pull_alpha", 0, 1e6, true},  {"bc.direction", 0, 2, true},
+    {"batch.pull_alpha", 0, 1e6, true},  {"batch.narrow", 0, 2, true},
+    {"bc.direction", 0, 2, true},
     {"bc.alpha", 1e-6, 1e9, true},       {"bc.beta", 1e-6, 1e9, true},
     {"twohop.direction", 0, 2, true},    {"twohop.alpha", 1e-6, 1e9, true},
     {"serve.budget_bytes", 0, 1e15, false}, {"serve.max_batch", 1, 64, false},
@@ -325,6 +326,7 @@ void option_set(Options &o, const std::string &key, double v)
     else if (key == "batch.min_bfs") o.batch_min_bfs = (int)v;
     else if (key == "batch.min_sssp") o.batch_min_sssp = (int)v;
     else if (key == "batch.pull_alpha") o.batch_pull_alpha = v;
+    else if (key == "batch.narrow") o.batch_narrow = (int)v;
     else if (key == "bc.direction") o.bc_direction = (int)v;
     else if (key == "bc.alpha") o.bc_alpha = v;
     else if (key == "bc.beta") o.bc_beta = v;
@@ -359,6 +361,7 @@ static double option_get(const Options &o, const std::string &key)
     if (key == "batch.min_bfs") return o.batch_min_bfs;
     if (key == "batch.min_sssp") return o.batch_min_sssp;
     if (key == "batch.pull_alpha") return o.batch_pull_alpha;
+    if (key == "batch.narrow") return o.batch_narrow;
     if (key == "bc.direction") return o.bc_direction;
     if (key == "bc.alpha") return o.bc_alpha;
     if (key == "bc.beta") return o.bc_beta;

@@ -382,7 +382,7 @@ static void run_bfs_bitmap(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStr
         });
         ++level;
     };
-    const int32_t launched = run_until_done(c, &a.ctl->dir, DIR_DONE, g.bfs_levels_hint + 2, (int64_t)n + 4, s,
+    const int32_t launched = run_until_done(c, &a.ctl->dir, DIR_DONE, g.levels_hint() + 2, (int64_t)n + 4, s,
                                             launch);
     BfsCtl h;
     GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
@@ -393,7 +393,7 @@ static void run_bfs_bitmap(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStr
     c.stats.v["pull_levels"] += 0.0;
     c.stats.v["launches"] += launched;
     c.stats.v["solves"] += 1.0;
-    g.bfs_levels_hint = h.level;
+    g.bfs_levels_hint.store(h.level, std::memory_order_relaxed);
 }
 
 void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s)
@@ -457,7 +457,7 @@ void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s)
                                cg.wpt, marks, a.q, chunk, status, &a.ctl->parity, &a.ctl->err);
         });
     };
-    const int32_t launched = run_until_done(c, &a.ctl->dir, DIR_DONE, g.bfs_levels_hint + 1,
+    const int32_t launched = run_until_done(c, &a.ctl->dir, DIR_DONE, g.levels_hint() + 1,
                                             (int64_t)n + 4, s, launch);
     BfsCtl h;
     GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
@@ -476,7 +476,7 @@ void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s)
     c.stats.v["pull_new"] += (double)h.pull_new;
     c.stats.v["launches"] += launched;
     c.stats.v["solves"] += 1.0;
-    g.bfs_levels_hint = h.level;
+    g.bfs_levels_hint.store(h.level, std::memory_order_relaxed);
 }
 
 }  // namespace gfr

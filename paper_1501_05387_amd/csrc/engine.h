@@ -105,9 +105,15 @@ struct Graph {
     int32_t full_nf = 0;
     int32_t n_isolated = 0;
     int32_t bip_checked_nl = -1;   // last side split verified for the bipartite rankings
-    // hints for the speculative level loop
-    int32_t bfs_levels_hint = 8;
-    int32_t sssp_iter_hint = 16;
+    // hints for the speculative level loop (the size of the first batch of
+    // launches); written by every solve on the graph, also from the serving
+    // threads, hence atomic (relaxed: a stale hint only sizes a batch)
+    std::atomic<int32_t> bfs_levels_hint{8};
+    std::atomic<int32_t> sssp_iter_hint{16};
+    int32_t levels_hint() const { return bfs_levels_hint.load(std::memory_order_relaxed); }
+    int32_t iter_hint() const { return sssp_iter_hint.load(std::memory_order_relaxed); }
+    // a batched SSSP on this graph outgrew 16-bit distance rows once
+    std::atomic<bool> narrow_overflowed{false};
 };
 
 struct Options {
@@ -125,6 +131,7 @@ struct Options {
     double batch_delta = 0.0;   // batched SSSP bucket width; 0 -> batch_delta_factor
     double batch_delta_factor = 0.0;   // x mean edge weight; 0 -> one bucket (frontier order)
     double batch_pull_alpha = 0.0;     // batched SSSP: pull sweep when frontier edges > m / alpha (0: never)
+    int batch_narrow = 1;       // batched SSSP 16-bit distance rows: 0 never, 1 auto, 2 always tried first
     int serve_max_batch = 64;
     int serve_graphs = 1;       // serving sessions replay their rounds from captured hipGraphs
     int batch_min_bfs = 8;      // fewer sources than this: sequential single-source BFS

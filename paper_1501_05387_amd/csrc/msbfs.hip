@@ -401,7 +401,7 @@ void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t 
                                    cg.wpt, MsMarks{a}, a.q, chunk, status, &a.ctl->parity, &a.ctl->err);
             });
         };
-        run_until_done(c, &a.ctl->dir, MS_DONE, g.bfs_levels_hint + 2, (int64_t)n + 8, s, launch);
+        run_until_done(c, &a.ctl->dir, MS_DONE, g.levels_hint() + 2, (int64_t)n + 8, s, launch);
         MsCtl h;
         GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, s));
         GFR_HIP(hipStreamSynchronize(s));

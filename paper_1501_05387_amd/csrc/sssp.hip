@@ -370,7 +370,7 @@ void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s)
     };
     // every iteration relaxes or splits; the loop is bounded well below this cap
     const int64_t cap = 64ll * n + 1024;
-    const int32_t launched = run_until_done(c, &a.ctl->mode, SS_DONE, g.sssp_iter_hint + 1, cap, s, launch);
+    const int32_t launched = run_until_done(c, &a.ctl->mode, SS_DONE, g.iter_hint() + 1, cap, s, launch);
     SsspCtl h;
     GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(SsspCtl), hipMemcpyDeviceToHost, s));
     GFR_HIP(hipStreamSynchronize(s));
@@ -387,7 +387,7 @@ void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s)
     c.stats.v["delta"] = delta;
     c.stats.v["launches"] += launched;
     c.stats.v["solves"] += 1.0;
-    g.sssp_iter_hint = (int32_t)h.iter;
+    g.sssp_iter_hint.store((int32_t)h.iter, std::memory_order_relaxed);
 }
 
 }  // namespace gfr

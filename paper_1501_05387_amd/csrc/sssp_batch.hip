@@ -10,6 +10,14 @@
 // single-source SSSP; the queries share the near/far bucket bound of the
 // priority queue (Sec. 4.5), which only changes the schedule, not the result.
 //
+// Narrow rows: a batch first runs with 16-bit distances (128-byte rows, half
+// the bytes of every random row access), unreached = 0xFFFF.  A relaxation
+// that would store a distance of 0xFFFF or more sets the overflow flag, the
+// traversal stops, and the batch is solved again with 32-bit rows; so a
+// finished narrow batch stored exactly the distances the wide one would.
+// Queries 2k and 2k+1 share a 32-bit word of a narrow row, which is lowered
+// with compare-and-swap (there is no 16-bit atomic minimum).
+//
 // Marks: per vertex a 64-bit mask of the queries improved in an iteration
 // (one atomicOr of the wave's ballot per improved edge, not one byte store
 // per improving lane) plus a byte any[v] for the compaction's scan.
@@ -51,6 +59,7 @@ struct BsCtl {
     float pull_alpha;            // pull when the frontier's edges exceed m / pull_alpha (0: never)
     unsigned long long m;
     uint32_t pull_iters, pad2;
+    unsigned long long lane_relaxed;   // (edge, query) relaxations: edges visited x queries active at the source
 };
 
 struct BsArgs {
@@ -59,12 +68,13 @@ struct BsArgs {
     const uint32_t *W;
     int32_t n;
     uint32_t nwords;
-    uint32_t *D;                 // [n][64]
+    uint32_t *D;                 // [n][64] wide rows
+    uint16_t *D16;               // [n][64] narrow rows (the same memory)
     unsigned long long *qm;      // query mask of every queued vertex
     unsigned long long *nq, *fq; // [n] queries improved into the near / far set
     uint8_t *nany, *fany;        // [n] (padded)
     FrontierQ q;
-    uint32_t *part;              // per work-group [improvements, far marks written]
+    uint32_t *part;              // per work-group [improvements, far marks written, lane relaxations, 0]
     unsigned long long *actp;    // per compaction group: OR of the query masks it queued
     uint32_t *fbits;             // [nwords] frontier bitmap of the next relaxation (qm valid where set)
     FrontierQ full;              // every vertex with edges (pull sweeps)
@@ -73,10 +83,61 @@ struct BsArgs {
 };
 
 constexpr int BS_UNROLL = 8;   // edges relaxed together (two distance rows each)
+constexpr uint32_t BS_INF = 0xFFFFFFFFu;
+constexpr uint32_t BS_INF16 = 0xFFFFu;
+
+// distance of query q at vertex v in 32-bit form (unreached: BS_INF)
+template <bool NARROW>
+__device__ __forceinline__ uint32_t bs_load(const BsArgs &a, size_t v, int q)
+{
+    if (NARROW) {
+        const uint32_t x = a.D16[v * 64 + q];
+        return x == BS_INF16 ? BS_INF : x;
+    }
+    return a.D[v * 64 + q];
+}
+
+template <bool NARROW>
+__device__ __forceinline__ void bs_store(const BsArgs &a, size_t v, int q, uint32_t d)
+{
+    if (NARROW) a.D16[v * 64 + q] = (uint16_t)(d == BS_INF ? BS_INF16 : d);
+    else a.D[v * 64 + q] = d;
+}
+
+// Lower the distance of the calling lane's query at vertex v to nd where
+// `imp` is set; `cur` is the value the lane loaded.  Called by the whole
+// wave.  Wide rows: one non-returning atomicMin per improving lane.  Narrow
+// rows: the even lane of each pair writes the pair's word by compare-and-swap
+// (a failed swap returns a word another update lowered; the minima are taken
+// again against it until the swap succeeds or nothing is left to lower).
+template <bool NARROW>
+__device__ __forceinline__ void bs_lower(const BsArgs &a, size_t v, int lane, uint32_t nd, bool imp, uint32_t cur)
+{
+    if (!NARROW) {
+        if (imp) atomicMin(a.D + v * 64 + lane, nd);
+        return;
+    }
+    const uint32_t want = imp ? nd : BS_INF16;   // nd < 0xFFFF wherever imp holds
+    const uint32_t raw = cur == BS_INF ? BS_INF16 : cur;
+    const uint32_t want_p = (uint32_t)__shfl_xor((int)want, 1, 64);
+    const uint32_t raw_p = (uint32_t)__shfl_xor((int)raw, 1, 64);
+    if ((lane & 1) == 0 && (want < raw || want_p < raw_p)) {
+        uint32_t *w = (uint32_t *)(a.D16 + v * 64 + lane);
+        uint32_t expect = raw | (raw_p << 16);
+        for (;;) {
+            const uint32_t lo = min(expect & 0xFFFFu, want), hi = min(expect >> 16, want_p);
+            const uint32_t desired = lo | (hi << 16);
+            if (desired == expect) break;
+            const uint32_t old = atomicCAS(w, expect, desired);
+            if (old == expect) break;
+            expect = old;
+        }
+    }
+}
 
 __device__ __forceinline__ int32_t lane_bcast(int32_t x, int j) { return __builtin_amdgcn_readlane(x, j); }
 
-template <int CH>
+template <int CH, bool NARROW>
 __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
 {
     BsCtl *ctl = a.ctl;
@@ -89,7 +150,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
     const int lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     constexpr uint32_t QW = CH / GFR_WAVES;
     const uint32_t nchunks = (mf + CH - 1) / CH;
-    uint32_t nimp = 0, nfar = 0;
+    uint32_t nimp = 0, nfar = 0, nlr = 0;
     bool ovf = false;
     for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
         const uint32_t e0 = c * CH;
@@ -139,16 +200,25 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
                 const unsigned long long nd64 = (unsigned long long)du + w;
                 const bool fits = nd64 < 0xFFFFFFFFull;
                 const uint32_t nd = (uint32_t)nd64;
-                const bool imp = act & fits & (nd < dv);
-                ovf |= act & !fits;
-                // non-returning atomicMin: the mark follows the pre-check, a
-                // superset of the true improvements (a marked vertex is simply
-                // relaxed again with its current distance)
-                const bool near_imp = imp & (nd < hi), far_imp = imp & (nd >= hi);
-                if (imp) {
-                    atomicMin(a.D + (size_t)v * 64 + lane, nd);
-                    ++nimp;
+                bool imp;
+                if (NARROW) {
+                    // an improvement that does not fit a narrow row stops the
+                    // batch (it is solved again with wide rows), and so does
+                    // a sum the wide rows would reject
+                    const bool cand = act & (nd64 < (unsigned long long)dv);
+                    imp = cand & (nd64 < (unsigned long long)BS_INF16);
+                    ovf |= (cand & !imp) | (act & !fits);
+                } else {
+                    imp = act & fits & (nd < dv);
+                    ovf |= act & !fits;
                 }
+                nlr += act ? 1u : 0u;
+                // the update does not return a value: the mark follows the
+                // pre-check, a superset of the true improvements (a marked
+                // vertex is simply relaxed again with its current distance)
+                const bool near_imp = imp & (nd < hi), far_imp = imp & (nd >= hi);
+                if (ballot(imp)) bs_lower<NARROW>(a, (size_t)v, lane, nd, imp, dv);
+                nimp += imp ? 1u : 0u;
                 const uint64_t bn = ballot(near_imp), bf = ballot(far_imp);
                 if (lane == 0) {
                     if (bn) {
@@ -166,7 +236,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
             if (u_first == lane_bcast(ul, nb - 1)) {
                 // the whole group leaves one vertex (edges are in source
                 // order): its distance row and query bit are loaded once
-                const uint32_t du = a.D[(size_t)u_first * 64 + lane];
+                const uint32_t du = bs_load<NARROW>(a, (size_t)u_first, lane);
                 const uint32_t q0 = (uint32_t)lane_bcast(qlo, 0), q1 = (uint32_t)lane_bcast(qhi, 0);
                 const bool act_u = (((lane < 32 ? q0 : q1) >> (lane & 31)) & 1u) != 0;
                 for (int j0 = 0; j0 < nb; j0 += 16) {
@@ -177,7 +247,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
                         const int src = min(j0 + j, nb - 1);   // a padded edge repeats the last one
                         vv[j] = lane_bcast(vl, src);
                         ww[j] = (uint32_t)lane_bcast(wl, src);
-                        dv[j] = a.D[(size_t)vv[j] * 64 + lane];
+                        dv[j] = bs_load<NARROW>(a, (size_t)vv[j], lane);
                     }
 #pragma unroll
                     for (int j = 0; j < 16; ++j) relax(vv[j], ww[j], du, dv[j], act_u & (j0 + j < nb));
@@ -194,8 +264,8 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
                         ww[j] = (uint32_t)lane_bcast(wl, src);
                         const uint32_t q0 = (uint32_t)lane_bcast(qlo, src), q1 = (uint32_t)lane_bcast(qhi, src);
                         qw[j] = lane < 32 ? q0 : q1;
-                        du[j] = a.D[(size_t)u * 64 + lane];
-                        dv[j] = a.D[(size_t)vv[j] * 64 + lane];
+                        du[j] = bs_load<NARROW>(a, (size_t)u, lane);
+                        dv[j] = bs_load<NARROW>(a, (size_t)vv[j], lane);
                     }
 #pragma unroll
                     for (int j = 0; j < BS_UNROLL; ++j)
@@ -205,21 +275,25 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
         }
     }
     if (ovf) ctl->overflow = 1u;
-    __shared__ uint32_t s_a[GFR_WAVES], s_b[GFR_WAVES];
+    __shared__ uint32_t s_a[GFR_WAVES], s_b[GFR_WAVES], s_c[GFR_WAVES];
     nimp = wave_sum_u32(nimp);
+    nlr = wave_sum_u32(nlr);
     if (lane == 0) {
         s_a[wave] = nimp;
         s_b[wave] = nfar;
+        s_c[wave] = nlr;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t x = 0, y = 0;
+        uint32_t x = 0, y = 0, z = 0;
         for (int k = 0; k < GFR_WAVES; ++k) {
             x += s_a[k];
             y += s_b[k];
+            z += s_c[k];
         }
-        a.part[2 * blockIdx.x] = x;
-        a.part[2 * blockIdx.x + 1] = y;
+        a.part[4 * blockIdx.x] = x;
+        a.part[4 * blockIdx.x + 1] = y;
+        a.part[4 * blockIdx.x + 2] = z;
     }
 }
 
@@ -231,7 +305,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
 // per improving edge.  Sources outside the frontier cost one bitmap probe.
 constexpr int BP_UNROLL = 8;
 
-template <int CH>
+template <int CH, bool NARROW>
 __global__ __launch_bounds__(GFR_BLOCK) void bsssp_pull(BsArgs a)
 {
     BsCtl *ctl = a.ctl;
@@ -245,19 +319,21 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_pull(BsArgs a)
     const int lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     constexpr uint32_t QW = CH / GFR_WAVES;
     const uint32_t nchunks = (mf + CH - 1) / CH;
-    uint32_t nimp = 0, nfar = 0;
+    uint32_t nimp = 0, nfar = 0, nlr = 0;
     bool ovf = false;
     int32_t cur = -1;                 // owner whose minimum is being formed (wave-uniform)
     uint32_t acc = 0xFFFFFFFFu;       // its minimum for this lane's query
     uint32_t old = 0;                 // the owner's distance, loaded when the owner starts
     auto flush = [&]() {
         if (cur >= 0) {
-            const bool imp = acc < old;
-            const bool near_imp = imp & (acc < hi), far_imp = imp & (acc >= hi);
-            if (imp) {
-                atomicMin(a.D + (size_t)cur * 64 + lane, acc);
-                ++nimp;
+            bool imp = acc < old;
+            if (NARROW && imp && acc >= BS_INF16) {
+                ovf = true;   // does not fit a narrow row: the batch is solved again with wide rows
+                imp = false;
             }
+            const bool near_imp = imp & (acc < hi), far_imp = imp & (acc >= hi);
+            if (ballot(imp)) bs_lower<NARROW>(a, (size_t)cur, lane, acc, imp, old);
+            nimp += imp ? 1u : 0u;
             const uint64_t bn = ballot(near_imp), bf = ballot(far_imp);
             if (lane == 0) {
                 if (bn) {
@@ -327,7 +403,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_pull(BsArgs a)
                     ww[k] = (uint32_t)lane_bcast(wl, j);
                     const uint32_t q0 = (uint32_t)lane_bcast(qlo, j), q1 = (uint32_t)lane_bcast(qhi, j);
                     qw[k] = lane < 32 ? q0 : q1;
-                    du[k] = a.D[(size_t)u * 64 + lane];
+                    du[k] = bs_load<NARROW>(a, (size_t)u, lane);
                 }
 #pragma unroll
                 for (int k = 0; k < BP_UNROLL; ++k) {
@@ -335,9 +411,10 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_pull(BsArgs a)
                     if (vv[k] != cur) {
                         flush();
                         cur = vv[k];
-                        old = a.D[(size_t)cur * 64 + lane];   // read by the owner's flush
+                        old = bs_load<NARROW>(a, (size_t)cur, lane);   // read by the owner's flush
                     }
                     const bool on = ((qw[k] >> (lane & 31)) & 1u) != 0;
+                    nlr += on ? 1u : 0u;
                     const unsigned long long nd64 = (unsigned long long)du[k] + ww[k];
                     const bool fits = nd64 < 0xFFFFFFFFull;
                     ovf |= on & !fits;
@@ -350,31 +427,37 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_pull(BsArgs a)
         cur = -1;
     }
     if (ovf) ctl->overflow = 1u;
-    __shared__ uint32_t s_a[GFR_WAVES], s_b[GFR_WAVES];
+    __shared__ uint32_t s_a[GFR_WAVES], s_b[GFR_WAVES], s_c[GFR_WAVES];
     nimp = wave_sum_u32(nimp);
+    nlr = wave_sum_u32(nlr);
     if (lane == 0) {
         s_a[wave] = nimp;
         s_b[wave] = nfar;
+        s_c[wave] = nlr;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t x = 0, y = 0;
+        uint32_t x = 0, y = 0, z = 0;
         for (int k = 0; k < GFR_WAVES; ++k) {
             x += s_a[k];
             y += s_b[k];
+            z += s_c[k];
         }
-        a.part[2 * blockIdx.x] = x;
-        a.part[2 * blockIdx.x + 1] = y;
+        a.part[4 * blockIdx.x] = x;
+        a.part[4 * blockIdx.x + 1] = y;
+        a.part[4 * blockIdx.x + 2] = z;
     }
 }
 
 // 64 mark bytes (0/1) of one vertex -> query mask; clears them when `clear`
+template <bool NARROW>
 struct BsMarks {
     BsArgs a;
     uint32_t nparts;
     uint32_t nactp;   // compaction groups
     uint32_t kept = 0, kmin = 0xFFFFFFFFu;
     unsigned long long actq = 0;
+    uint32_t pairs = 0;   // (vertex, query) pairs queued by this thread
 
     __device__ bool skip() const { return a.ctl->mode == BS_DONE; }
 
@@ -399,6 +482,7 @@ struct BsMarks {
                     pn[i] = make_ulonglong2(0ull, 0ull);
                     pq[i] = x[i];
                     actq |= x[i].x | x[i].y;
+                    pairs += __popcll(x[i].x) + __popcll(x[i].y);
                 }
                 return m;
             }
@@ -411,6 +495,7 @@ struct BsMarks {
                 a.nq[v] = 0ull;
                 a.qm[v] = qv;
                 actq |= qv;
+                pairs += __popcll(qv);
             }
             return m;
         }
@@ -429,7 +514,7 @@ struct BsMarks {
             while (fm) {
                 const int qq = __ffsll(fm) - 1;
                 fm &= fm - 1;
-                const uint32_t d = a.D[(size_t)v * 64 + qq];
+                const uint32_t d = bs_load<NARROW>(a, (size_t)v, qq);
                 if (d < hi) {
                     if (d >= lo) nm |= 1ull << qq;
                 } else {
@@ -443,6 +528,7 @@ struct BsMarks {
             if (nm) {
                 a.qm[v] = nm;
                 out |= 1u << bi;
+                pairs += __popcll(nm);
             }
         }
         a.fbits[w] = out;
@@ -451,6 +537,17 @@ struct BsMarks {
 
     __device__ void partial(uint32_t)
     {
+        {
+            __shared__ uint32_t s_p[GFR_WAVES];
+            const uint32_t p = wave_sum_u32(pairs);
+            if (lane_id() == 0) s_p[threadIdx.x / 64] = p;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint32_t t = 0;
+                for (int i = 0; i < GFR_WAVES; ++i) t += s_p[i];
+                if (t) atomicAdd(&a.ctl->pair_entries, (unsigned long long)t);
+            }
+        }
         if (a.ctl->mode == BS_RELAX) {
             // OR of the queued query masks of this group
             __shared__ unsigned long long s_q[GFR_WAVES];
@@ -497,23 +594,30 @@ struct BsMarks {
         BsCtl *ctl = a.ctl;
         const uint32_t mode = ctl->mode;
         uint32_t imp = 0, far = 0;
+        unsigned long long lr = 0;
         if (mode == BS_RELAX) {
             for (uint32_t i = threadIdx.x; i < nparts; i += GFR_BLOCK) {
-                imp += a.part[2 * i];
-                far += a.part[2 * i + 1];
+                imp += a.part[4 * i];
+                far += a.part[4 * i + 1];
+                lr += a.part[4 * i + 2];
             }
             __shared__ uint32_t s_i[GFR_WAVES], s_f[GFR_WAVES];
+            __shared__ unsigned long long s_l[GFR_WAVES];
             imp = wave_sum_u32(imp);
             far = wave_sum_u32(far);
+            lr = wave_sum_u64(lr);
             if (lane_id() == 0) {
                 s_i[threadIdx.x / 64] = imp;
                 s_f[threadIdx.x / 64] = far;
+                s_l[threadIdx.x / 64] = lr;
             }
             __syncthreads();
             imp = far = 0;
+            lr = 0;
             for (int i = 0; i < GFR_WAVES; ++i) {
                 imp += s_i[i];
                 far += s_f[i];
+                lr += s_l[i];
             }
         }
         unsigned long long act = 0;
@@ -538,6 +642,7 @@ struct BsMarks {
             ctl->relaxed += ctl->dir == BS_PULL ? ctl->m : ctl->mf;
             ctl->pull_iters += ctl->dir == BS_PULL ? 1u : 0u;
             ctl->improvements += imp;
+            ctl->lane_relaxed += lr;
             if (far) ctl->far_any = 1u;
         } else {
             ctl->far_any = atomicAdd(&ctl->split_kept, 0u) != 0u;
@@ -573,12 +678,13 @@ struct BsMarks {
     }
 };
 
+template <bool NARROW>
 __global__ void bsssp_init(BsArgs a, const int32_t *src, int32_t k, uint32_t delta, float pull_alpha)
 {
     if (threadIdx.x == 0) {
         for (int32_t q = 0; q < k; ++q) {
             const int32_t v = src[q];
-            a.D[(size_t)v * 64 + q] = 0u;
+            bs_store<NARROW>(a, (size_t)v, q, 0u);
             a.nq[v] |= 1ull << q;
             a.nany[v] = 1;
         }
@@ -593,7 +699,7 @@ __global__ void bsssp_init(BsArgs a, const int32_t *src, int32_t k, uint32_t del
         ctl->split_kept = 0;
         ctl->split_min = 0xFFFFFFFFu;
         ctl->overflow = ctl->parity = ctl->err = ctl->splits = 0;
-        ctl->relaxed = ctl->improvements = ctl->pair_entries = 0ull;
+        ctl->relaxed = ctl->improvements = ctl->pair_entries = ctl->lane_relaxed = 0ull;
         ctl->active = 0ull;
         ctl->dir = BS_PUSH;
         ctl->pull_alpha = pull_alpha;
@@ -603,8 +709,9 @@ __global__ void bsssp_init(BsArgs a, const int32_t *src, int32_t k, uint32_t del
 }
 
 // out[q][v] = D[v][q] for the queries q in `lanes`: 64 vertices x 64 queries
-// per tile through LDS
-__global__ __launch_bounds__(GFR_BLOCK) void bsssp_transpose(const uint32_t *D, int32_t n, unsigned long long lanes,
+// per tile through LDS (narrow rows widened, 0xFFFF -> 0xFFFFFFFF)
+template <bool NARROW>
+__global__ __launch_bounds__(GFR_BLOCK) void bsssp_transpose(BsArgs a, int32_t n, unsigned long long lanes,
                                                              uint32_t *out)
 {
     __shared__ uint32_t tile[64][65];
@@ -614,7 +721,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_transpose(const uint32_t *D, 
         __syncthreads();
         for (int i = threadIdx.x; i < 64 * 64; i += GFR_BLOCK) {
             const int r = i / 64, q = i % 64;
-            tile[r][q] = (v0 + r < n) ? D[(size_t)(v0 + r) * 64 + q] : 0u;
+            tile[r][q] = (v0 + r < n) ? bs_load<NARROW>(a, (size_t)(v0 + r), q) : 0u;
         }
         __syncthreads();
         for (int i = threadIdx.x; i < 64 * 64; i += GFR_BLOCK) {
@@ -645,7 +752,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     if (c.opt.batch_delta > 0) delta = (uint32_t)c.opt.batch_delta;
     else if (c.opt.batch_delta_factor > 0) delta = sssp_auto_delta(g, c.opt.batch_delta_factor);
     c.arena.reserve(al256(256ull * n) + al256(8ull * n) + 2 * al256(8ull * n) + 2 * al256(32ull * nwords) +
-                    3 * al256(4ull * n) + al256(4 * nparts) + al256(8ull * G) + al256(16ull * cg.blocks) +
+                    3 * al256(4ull * n) + al256(4 * nparts) + al256(16ull * G) + al256(16ull * cg.blocks) +
                     al256(sizeof(BsCtl)) + al256(4 * 64) + al256(8ull * cg.blocks) + al256(4ull * nwords));
     BsArgs a;
     a.R = g.R.as<int32_t>();
@@ -654,6 +761,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     a.n = n;
     a.nwords = nwords;
     a.D = c.arena.take<uint32_t>(64ull * n);
+    a.D16 = (uint16_t *)a.D;
     a.qm = c.arena.take<unsigned long long>(n);
     a.nq = c.arena.take<unsigned long long>(n);
     a.fq = c.arena.take<unsigned long long>(n);
@@ -663,7 +771,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     a.q.off = c.arena.take<uint32_t>(n);
     a.q.row = c.arena.take<int32_t>(n);
     a.q.part = c.arena.take<int32_t>(nparts);
-    a.part = c.arena.take<uint32_t>(2ull * G);
+    a.part = c.arena.take<uint32_t>(4ull * G);
     unsigned long long *status = c.arena.take<unsigned long long>(2ull * cg.blocks);
     a.ctl = c.arena.take<BsCtl>(1);
     int32_t *dsrc = c.arena.take<int32_t>(64);
@@ -672,53 +780,91 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     a.full = g.full;
     a.full_nf = (uint32_t)g.full_nf;
     a.full_mf = (uint32_t)g.m;
-    double iters = 0, relaxed = 0, imps = 0, pulls = 0;
+    double iters = 0, relaxed = 0, imps = 0, pulls = 0, lanes = 0, pairs = 0, fallbacks = 0, narrow_batches = 0;
+    // narrow rows first (option batch.narrow: 0 never, 1 auto, 2 always
+    // tried first); auto skips them on mesh-class graphs, whose long paths
+    // outgrow 16 bits, and on graphs where a batch has overflowed them before
+    const int nopt = c.opt.batch_narrow;
+    bool narrow = nopt == 2 || (nopt == 1 && g.cls == GRAPH_SCALEFREE && !g.narrow_overflowed.load());
     for (int32_t g0 = 0; g0 < k; g0 += 64) {
         const int32_t kk = std::min<int32_t>(64, k - g0);
-        fill_u32(a.D, 0xFFFFFFFFu, 64ull * n, s);
-        fill_u32(a.nq, 0u, 2ull * n, s);
-        fill_u32(a.fq, 0u, 2ull * n, s);
-        fill_u32(a.nany, 0u, 8ull * nwords, s);
-        fill_u32(a.fany, 0u, 8ull * nwords, s);
-        fill_u32(a.part, 0u, 2ull * G, s);
-        fill_u32(status, 0u, 4ull * cg.blocks, s);
-        GFR_HIP(hipMemcpyAsync(dsrc, sources + g0, 4ull * kk, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(bsssp_init, dim3(1), dim3(64), 0, s, a, dsrc, kk, delta, (float)c.opt.batch_pull_alpha);
-        BsMarks marks{a, (uint32_t)G, cg.blocks};
-        auto compact = [&]() {
-            c.ktimer.run("bsssp_compact", s, [&]() {
-                hipLaunchKernelGGL(compact_kernel<BsMarks>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R, n, nwords,
-                                   cg.wpt, marks, a.q, chunk, status, &a.ctl->parity, &a.ctl->err);
-            });
-        };
-        compact();   // queue of the sources
-        GFR_LAUNCH_CHECK();
-        auto launch = [&]() {
-            c.ktimer.run("bsssp_relax", s, [&]() {
-                hipLaunchKernelGGL(bsssp_relax<1024>, dim3(G), dim3(GFR_BLOCK), 0, s, a);
-            });
-            c.ktimer.run("bsssp_pull", s, [&]() {
-                hipLaunchKernelGGL(bsssp_pull<1024>, dim3(G), dim3(GFR_BLOCK), 0, s, a);
-            });
-            compact();
-        };
-        run_until_done(c, &a.ctl->mode, BS_DONE, g.sssp_iter_hint + 1, 64ll * n + 1024, s, launch);
         BsCtl h;
-        GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(BsCtl), hipMemcpyDeviceToHost, s));
-        GFR_HIP(hipStreamSynchronize(s));
-        memcpy(&h, c.pinned, sizeof(BsCtl));
-        if (h.err) fail(GFR_E_DEVICE, "sssp_batch: frontier compaction look-back timed out");
+        for (;;) {
+            fill_u32(a.D, 0xFFFFFFFFu, (narrow ? 32ull : 64ull) * n, s);
+            fill_u32(a.nq, 0u, 2ull * n, s);
+            fill_u32(a.fq, 0u, 2ull * n, s);
+            fill_u32(a.nany, 0u, 8ull * nwords, s);
+            fill_u32(a.fany, 0u, 8ull * nwords, s);
+            fill_u32(a.part, 0u, 4ull * G, s);
+            fill_u32(status, 0u, 4ull * cg.blocks, s);
+            GFR_HIP(hipMemcpyAsync(dsrc, sources + g0, 4ull * kk, hipMemcpyHostToDevice, s));
+            if (narrow)
+                hipLaunchKernelGGL(bsssp_init<true>, dim3(1), dim3(64), 0, s, a, dsrc, kk, delta,
+                                   (float)c.opt.batch_pull_alpha);
+            else
+                hipLaunchKernelGGL(bsssp_init<false>, dim3(1), dim3(64), 0, s, a, dsrc, kk, delta,
+                                   (float)c.opt.batch_pull_alpha);
+            auto compact = [&]() {
+                c.ktimer.run("bsssp_compact", s, [&]() {
+                    if (narrow)
+                        hipLaunchKernelGGL(compact_kernel<BsMarks<true>>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R,
+                                           n, nwords, cg.wpt, BsMarks<true>{a, (uint32_t)G, cg.blocks}, a.q, chunk,
+                                           status, &a.ctl->parity, &a.ctl->err);
+                    else
+                        hipLaunchKernelGGL(compact_kernel<BsMarks<false>>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s,
+                                           a.R, n, nwords, cg.wpt, BsMarks<false>{a, (uint32_t)G, cg.blocks}, a.q,
+                                           chunk, status, &a.ctl->parity, &a.ctl->err);
+                });
+            };
+            compact();   // queue of the sources
+            GFR_LAUNCH_CHECK();
+            auto launch = [&]() {
+                c.ktimer.run("bsssp_relax", s, [&]() {
+                    if (narrow) hipLaunchKernelGGL((bsssp_relax<1024, true>), dim3(G), dim3(GFR_BLOCK), 0, s, a);
+                    else hipLaunchKernelGGL((bsssp_relax<1024, false>), dim3(G), dim3(GFR_BLOCK), 0, s, a);
+                });
+                c.ktimer.run("bsssp_pull", s, [&]() {
+                    if (narrow) hipLaunchKernelGGL((bsssp_pull<1024, true>), dim3(G), dim3(GFR_BLOCK), 0, s, a);
+                    else hipLaunchKernelGGL((bsssp_pull<1024, false>), dim3(G), dim3(GFR_BLOCK), 0, s, a);
+                });
+                compact();
+            };
+            run_until_done(c, &a.ctl->mode, BS_DONE, g.iter_hint() + 1, 64ll * n + 1024, s, launch);
+            GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(BsCtl), hipMemcpyDeviceToHost, s));
+            GFR_HIP(hipStreamSynchronize(s));
+            memcpy(&h, c.pinned, sizeof(BsCtl));
+            if (h.err) fail(GFR_E_DEVICE, "sssp_batch: frontier compaction look-back timed out");
+            if (narrow && h.overflow) {
+                // a distance outgrew the narrow rows: this batch again, wide
+                narrow = false;
+                g.narrow_overflowed.store(true);
+                fallbacks += 1;
+                continue;
+            }
+            break;
+        }
         if (h.overflow) fail(GFR_E_INVALID, "sssp_batch: a path weight does not fit below 0xFFFFFFFF");
-        hipLaunchKernelGGL(bsssp_transpose, dim3(G), dim3(GFR_BLOCK), 0, s, a.D, n,
-                           kk == 64 ? ~0ull : ((1ull << kk) - 1ull), dist + (size_t)g0 * n);
+        if (narrow)
+            hipLaunchKernelGGL(bsssp_transpose<true>, dim3(G), dim3(GFR_BLOCK), 0, s, a, n,
+                               kk == 64 ? ~0ull : ((1ull << kk) - 1ull), dist + (size_t)g0 * n);
+        else
+            hipLaunchKernelGGL(bsssp_transpose<false>, dim3(G), dim3(GFR_BLOCK), 0, s, a, n,
+                               kk == 64 ? ~0ull : ((1ull << kk) - 1ull), dist + (size_t)g0 * n);
         GFR_LAUNCH_CHECK();
+        narrow_batches += narrow ? 1 : 0;
         iters += h.iter;
         relaxed += (double)h.relaxed;
         imps += (double)h.improvements;
         pulls += h.pull_iters;
+        lanes += (double)h.lane_relaxed;
+        pairs += (double)h.pair_entries;
     }
+    c.stats.v["narrow_batches"] += narrow_batches;   // batches solved with 16-bit rows
+    c.stats.v["narrow_fallbacks"] += fallbacks;      // batches solved again with 32-bit rows
     c.stats.v["iterations"] += iters;
     c.stats.v["relaxations"] += relaxed;   // edge visits, each serving up to 64 queries
+    c.stats.v["lane_relaxations"] += lanes;   // (edge, query) relaxations
+    c.stats.v["pair_entries"] += pairs;       // (vertex, query) entries of the near queues
     c.stats.v["improvements"] += imps;
     c.stats.v["pull_iterations"] += pulls;
     c.stats.v["solves"] += k;
@@ -768,7 +914,7 @@ __global__ void bs_session_init(BsArgs a, float pull_alpha)
     ctl->split_kept = 0;
     ctl->split_min = 0xFFFFFFFFu;
     ctl->overflow = ctl->parity = ctl->err = ctl->splits = 0;
-    ctl->relaxed = ctl->improvements = ctl->pair_entries = 0ull;
+    ctl->relaxed = ctl->improvements = ctl->pair_entries = ctl->lane_relaxed = 0ull;
     ctl->active = 0ull;
     ctl->dir = BS_PUSH;
     ctl->pull_alpha = pull_alpha;
@@ -782,7 +928,7 @@ struct BsLayout {
     size_t total() const
     {
         return al256(256 * n) + al256(8 * n) + 2 * al256(8 * n) + 2 * al256(32 * nwords) + 3 * al256(4 * n) +
-               al256(4 * nparts) + al256(8 * G) + al256(16 * blocks) + al256(sizeof(BsCtl)) + al256(8 * blocks) +
+               al256(4 * nparts) + al256(16 * G) + al256(16 * blocks) + al256(sizeof(BsCtl)) + al256(8 * blocks) +
                al256(4 * 128) + al256(4 * 64 * n) + al256(4 * nwords);
     }
 };
@@ -838,6 +984,7 @@ struct BsSession final : LaneSession {
         a.n = g.n;
         a.nwords = nwords;
         a.D = (uint32_t *)take(256 * L.n);
+        a.D16 = nullptr;   // sessions keep wide rows (lanes join at different times; no batch to solve again)
         a.qm = (unsigned long long *)take(8 * L.n);
         a.nq = (unsigned long long *)take(8 * L.n);
         a.fq = (unsigned long long *)take(8 * L.n);
@@ -847,7 +994,7 @@ struct BsSession final : LaneSession {
         a.q.off = (uint32_t *)take(4 * L.n);
         a.q.row = (int32_t *)take(4 * L.n);
         a.q.part = (int32_t *)take(4 * L.nparts);
-        a.part = (uint32_t *)take(8 * L.G);
+        a.part = (uint32_t *)take(16 * L.G);
         status = (unsigned long long *)take(16 * L.blocks);
         a.ctl = (BsCtl *)take(sizeof(BsCtl));
         a.actp = (unsigned long long *)take(8 * L.blocks);
@@ -862,7 +1009,7 @@ struct BsSession final : LaneSession {
         fill_u32(a.fq, 0u, 2 * L.n, stream);
         fill_u32(a.nany, 0u, 8 * L.nwords, stream);
         fill_u32(a.fany, 0u, 8 * L.nwords, stream);
-        fill_u32(a.part, 0u, 2 * L.G, stream);
+        fill_u32(a.part, 0u, 4 * L.G, stream);
         fill_u32(status, 0u, 4 * L.blocks, stream);
         hipLaunchKernelGGL(bs_session_init, dim3(1), dim3(64), 0, stream, a, (float)o.batch_pull_alpha);
         GFR_LAUNCH_CHECK();
@@ -893,11 +1040,11 @@ struct BsSession final : LaneSession {
     void release(unsigned long long) override {}   // a finished lane has no queued pairs left
     void enqueue_step() override
     {
-        hipLaunchKernelGGL(bsssp_relax<1024>, dim3(G), dim3(GFR_BLOCK), 0, stream, a);
-        hipLaunchKernelGGL(bsssp_pull<1024>, dim3(G), dim3(GFR_BLOCK), 0, stream, a);
-        hipLaunchKernelGGL(compact_kernel<BsMarks>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, stream, a.R, a.n, nwords,
-                           cg.wpt, BsMarks{a, (uint32_t)G, cg.blocks}, a.q, 1024u, status, &a.ctl->parity,
-                           &a.ctl->err);
+        hipLaunchKernelGGL((bsssp_relax<1024, false>), dim3(G), dim3(GFR_BLOCK), 0, stream, a);
+        hipLaunchKernelGGL((bsssp_pull<1024, false>), dim3(G), dim3(GFR_BLOCK), 0, stream, a);
+        hipLaunchKernelGGL(compact_kernel<BsMarks<false>>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, stream, a.R, a.n,
+                           nwords, cg.wpt, BsMarks<false>{a, (uint32_t)G, cg.blocks}, a.q, 1024u, status,
+                           &a.ctl->parity, &a.ctl->err);
         GFR_LAUNCH_CHECK();
         GFR_HIP(hipMemcpyAsync(pin, a.ctl, sizeof(BsCtl), hipMemcpyDeviceToHost, stream));
     }
@@ -917,7 +1064,8 @@ struct BsSession final : LaneSession {
     void extract(unsigned long long lanes) override
     {
         if (!lanes) return;
-        hipLaunchKernelGGL(bsssp_transpose, dim3(G), dim3(GFR_BLOCK), 0, stream, a.D, a.n, lanes, (uint32_t *)stage);
+        hipLaunchKernelGGL(bsssp_transpose<false>, dim3(G), dim3(GFR_BLOCK), 0, stream, a, a.n, lanes,
+                           (uint32_t *)stage);
         GFR_LAUNCH_CHECK();
     }
 };

@@ -565,3 +565,64 @@ def test_sssp_batch_pull_sweeps(ctx, name, alpha):
         ctx.set_option("batch.pull_alpha", 0)
         ctx.set_option("batch.min_sssp", 24)
         g.free()
+
+
+@pytest.mark.parametrize("name", ["rmat16", "grid96", "path3000", "star5000"])
+@pytest.mark.parametrize("narrow", [0, 2])
+def test_sssp_batch_row_width(ctx, name, narrow):
+    """Batched SSSP with 32-bit distance rows (narrow 0) and with 16-bit rows
+    tried first (narrow 2) equals the oracle.  On the lattice (weights up to
+    1000) and the long path, distances outgrow 16 bits, the narrow attempt
+    overflows and the batch is solved again with wide rows."""
+    row, col, w = graph(name)
+    n = row.size - 1
+    rng = np.random.default_rng(5)
+    src = rng.integers(0, n, size=70).astype(np.int32)   # two batches, the second ragged
+    src[0] = 0
+    src[1] = src[2]
+    g = _load(ctx, row, col, w)
+    ctx.set_option("batch.narrow", narrow)
+    ctx.set_option("batch.min_sssp", 1)
+    try:
+        _say("sssp_batch row width", name, narrow)
+        s = _host(ctx.sssp_batch(g, src)).view(np.uint32).reshape(src.size, n)
+        nb, fb = ctx.stat("narrow_batches"), ctx.stat("narrow_fallbacks")
+        ref = [oracle.sssp(row, col, w, int(x)) for x in src]
+        for i in range(src.size):
+            assert np.array_equal(s[i], ref[i]), (name, narrow, i)
+        maxd = max(int(r[r != 0xFFFFFFFF].max()) for r in ref)
+        if narrow == 0:
+            assert nb == 0 and fb == 0
+        elif maxd < 0xFFFF:
+            assert nb == 2 and fb == 0, (maxd, nb, fb)
+        else:
+            assert fb >= 1 and nb + fb >= 1, (maxd, nb, fb)
+    finally:
+        ctx.set_option("batch.narrow", 1)
+        ctx.set_option("batch.min_sssp", 24)
+        g.free()
+
+
+@pytest.mark.parametrize("second", [0x7FFF, 0x8000, 0xFFFE])
+def test_sssp_batch_narrow_boundary(ctx, second):
+    """Path 0 - 1 - 2 with weights 0x7FFF and `second`: the far end sits at
+    0xFFFE (the largest narrow distance), at 0xFFFF (does not fit: solved
+    again with wide rows) or at 0x17FFD; every result equals the oracle."""
+    row = np.array([0, 1, 3, 4], np.int32)
+    col = np.array([1, 0, 2, 1], np.int32)
+    w = np.array([0x7FFF, 0x7FFF, second, second], np.uint32)
+    g = _load(ctx, row, col, w)
+    src = np.array([0, 2, 1, 0], np.int32)
+    ctx.set_option("batch.narrow", 2)
+    ctx.set_option("batch.min_sssp", 1)
+    try:
+        s = _host(ctx.sssp_batch(g, src)).view(np.uint32).reshape(src.size, 3)
+        for i in range(src.size):
+            assert np.array_equal(s[i], oracle.sssp(row, col, w, int(src[i]))), (second, i)
+        fits = 0x7FFF + second < 0xFFFF
+        assert ctx.stat("narrow_batches") == (1 if fits else 0)
+        assert ctx.stat("narrow_fallbacks") == (0 if fits else 1)
+    finally:
+        ctx.set_option("batch.narrow", 1)
+        ctx.set_option("batch.min_sssp", 24)
+        g.free()
