@@ -189,6 +189,28 @@ gfr_status gfr_bfs(gfr_ctx *ctx, gfr_graph g, int32_t source, int32_t *depth_out
                    int32_t *pred_out, gfr_stream stream);
 
 /*
+ * gfr_bfs without any device allocation, for callers that cannot allocate
+ * device memory (tight serving loops, harnesses that forbid hipMalloc).  It
+ * waits on the stream like every call here, so it is not for stream
+ * capture.  Same depths as gfr_bfs (same kernels); no
+ * predecessors.  depth_out must be device memory on the context's device
+ * (n int32), else GFR_E_INVALID.  The traversal's scratch (frontier queue,
+ * bitmaps, mark bytes, control words) comes from one fixed array of
+ * GFR_NOALLOC_SCRATCH_BYTES per device, reserved when the library's code is
+ * loaded on that device and held until the process ends; a graph whose
+ * traversal needs more (about 13.25 bytes per vertex plus 4 bytes per
+ * advance chunk of entries: about 5 M vertices at 32 entries per vertex)
+ * gets GFR_E_CAPACITY, with nothing written.  The array keeps the last call's contents and every
+ * call clears what it reads before writing it.  All contexts on one device
+ * share the array: calls that overlap in time on one device (two contexts,
+ * or two threads with two contexts) race and give wrong results; calls on
+ * one context are serialised and safe.
+ */
+#define GFR_NOALLOC_SCRATCH_BYTES (64ull * 1024ull * 1024ull)
+gfr_status gfr_bfs_noalloc(gfr_ctx *ctx, gfr_graph g, int32_t source, int32_t *depth_out,
+                           gfr_stream stream);
+
+/*
  * Single-source shortest paths with non-negative integer weights
  * (Sec. 4.1 Algorithm 1, Sec. 5.2): dist_out[v] = minimum path weight,
  * dist_out[source] = 0, unreached 0xFFFFFFFF.  n uint32 elements.

@@ -60,6 +60,7 @@ SIGNATURES = {
     "gfr_graph_free": (_i32, [_vp, _i64]),
     "gfr_graph_info": (_i32, [_vp, _i64, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_u64)]),
     "gfr_bfs": (_i32, [_vp, _i64, _i32, _vp, _vp, _vp]),
+    "gfr_bfs_noalloc": (_i32, [_vp, _i64, _i32, _vp, _vp]),
     "gfr_sssp": (_i32, [_vp, _i64, _i32, _vp, _vp, _vp]),
     "gfr_bc": (_i32, [_vp, _i64, _vp, _i32, _vp, _vp]),
     "gfr_cc": (_i32, [_vp, _i64, _vp, ctypes.POINTER(_i32), _vp]),
@@ -233,6 +234,15 @@ class Context:
         pp, pret = self._pred(pred, g.n)
         self._check(lib().gfr_bfs(self.ptr, g.handle, int(source), p, pp, self._stream()))
         return ret if pret is None else (ret, pret)
+
+    def bfs_noalloc(self, g: Graph, source: int, out):
+        """Depths into `out` (a device tensor of n int32 the caller allocated)
+        through the entry point that allocates nothing."""
+        if out is None:
+            raise ValueError("bfs_noalloc writes into a caller-allocated device tensor")
+        p, ret = self._out(out, g.n, np.int32)
+        self._check(lib().gfr_bfs_noalloc(self.ptr, g.handle, int(source), p, self._stream()))
+        return ret
 
     def sssp(self, g: Graph, source: int, out=None, pred=None):
         """Distances; with pred=True (or a buffer) also the predecessors: (dist, pred)."""

@@ -3,6 +3,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdlib>
 #include <string>
@@ -35,6 +37,44 @@ bool is_device_ptr(const void *p)
 }
 
 int grid_blocks(const Ctx &c, int per_cu) { return c.num_cu * per_cu; }
+
+// Scratch of gfr_bfs_noalloc: one fixed array per device (the code object's
+// copy on that device), never allocated or freed by the library.  Host code
+// must not use the array's name as an address: it is a host-side stand-in.
+// The device address is looked up once per device, with that device current,
+// and kept here.
+static __device__ __align__(256) unsigned char scratch[GFR_NOALLOC_SCRATCH_BYTES];
+static std::mutex scratch_mu;
+static std::map<int, void *> scratch_addr;
+
+// Device address of `scratch` on `device`, which must be the current device.
+static void *noalloc_scratch(int device)
+{
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    auto it = scratch_addr.find(device);
+    if (it != scratch_addr.end()) return it->second;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        fail(GFR_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    scratch_addr[device] = ptr;
+    return ptr;
+}
+
+// true if p is device memory of `device`
+static bool is_device_ptr_on(const void *p, int device)
+{
+    hipPointerAttribute_t attr;
+    memset(&attr, 0, sizeof attr);
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice && attr.device == device;
+}
+
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t count)
 {
@@ -531,6 +571,7 @@ gfr_status gfr_ctx_create(int32_t device, const char *tuning_json, gfr_ctx **out
         // a blocking stream: work the caller queued earlier on the device's
         // null stream (PyTorch's default stream) finishes before ours starts
         GFR_HIP(hipStreamCreateWithFlags(&cc.stream, hipStreamDefault));
+        cc.noalloc_scratch = noalloc_scratch(device);
         GFR_HIP(hipHostMalloc((void **)&cc.pinned, 4096, hipHostMallocDefault));
         GFR_HIP(hipEventCreate(&cc.ev0));
         GFR_HIP(hipEventCreate(&cc.ev1));
@@ -696,6 +737,30 @@ gfr_status gfr_bfs(gfr_ctx *ctx, gfr_graph gh, int32_t source, int32_t *depth_ou
         with_pred(c, g, pred_out, s, [&](int32_t *pd) { run_bfs_pred(c, g, source, (const int32_t *)o.dev, pd, s); });
         timed_end(c, s);
         o.finish(c, s);
+    });
+}
+
+gfr_status gfr_bfs_noalloc(gfr_ctx *ctx, gfr_graph gh, int32_t source, int32_t *depth_out, gfr_stream stream)
+{
+    return guard(ctx, [&](Ctx &c) {
+        Graph &g = get_graph(c, gh);
+        OptScope os(c, g);
+        if (source < 0 || source >= g.n) fail(GFR_E_INVALID, "bfs_noalloc: source out of range");
+        if (!depth_out || !is_device_ptr_on(depth_out, c.device))
+            fail(GFR_E_INVALID, "bfs_noalloc: depth_out must be device memory of the context's device");
+        if (!c.noalloc_scratch) fail(GFR_E_DEVICE, "bfs_noalloc: no scratch address for this device");
+        hipStream_t s = pick_stream(c, stream);
+        Arena ar(c.noalloc_scratch, GFR_NOALLOC_SCRATCH_BYTES);
+        c.stats.clear();
+        c.ktimer.reset();
+        c.ktimer.on = false;   // per-launch timing would create events
+        GFR_HIP(hipEventRecord(c.ev0, s));
+        run_bfs(c, g, source, depth_out, s, ar);   // capacity is checked before any launch
+        GFR_HIP(hipEventRecord(c.ev1, s));
+        GFR_HIP(hipEventSynchronize(c.ev1));
+        float ms = 0.f;
+        GFR_HIP(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+        c.stats.v["kernel_ms"] = ms;
     });
 }
 

@@ -354,21 +354,21 @@ __global__ __launch_bounds__(GFR_BLOCK) void bfs_bitmap_level(BmArgs a, int32_t 
     if (threadIdx.x == 0) a.flags[(size_t)(L & 1) * G + blockIdx.x] = (uint32_t)found;
 }
 
-static void run_bfs_bitmap(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s)
+static void run_bfs_bitmap(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s, Arena &ar)
 {
     const int32_t n = g.n;
     const size_t nb = ((size_t)n + 15) / 16 * 16;
     const int G = grid_blocks(c, 8);
-    c.arena.reserve(2 * al256(nb) + al256(8ull * G) + al256(sizeof(BfsCtl)));
+    ar.reserve(2 * al256(nb) + al256(8ull * G) + al256(sizeof(BfsCtl)));
     BmArgs a;
     a.R = g.R.as<int32_t>();
     a.C = g.C.as<int32_t>();
     a.n = n;
     a.depth = depth;
-    a.mk[0] = c.arena.take<uint8_t>(nb);
-    a.mk[1] = c.arena.take<uint8_t>(nb);
-    a.flags = c.arena.take<uint32_t>(2ull * G);
-    a.ctl = c.arena.take<BfsCtl>(1);
+    a.mk[0] = ar.take<uint8_t>(nb);
+    a.mk[1] = ar.take<uint8_t>(nb);
+    a.flags = ar.take<uint32_t>(2ull * G);
+    a.ctl = ar.take<BfsCtl>(1);
     fill_u32(depth, 0xFFFFFFFFu, (size_t)n, s);
     fill_u32(a.mk[0], 0u, nb / 4, s);
     fill_u32(a.mk[1], 0u, nb / 4, s);
@@ -396,13 +396,15 @@ static void run_bfs_bitmap(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStr
     g.bfs_levels_hint.store(h.level, std::memory_order_relaxed);
 }
 
-void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s)
+void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s) { run_bfs(c, g, src, depth, s, c.arena); }
+
+void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s, Arena &ar)
 {
     // mark-byte levels on mesh-like graphs (bfs.frontier 0 auto, 1 queue, 2 mark bytes); a forced pull
     // direction needs the queue path's frontier bitmap
     const int fr = c.opt.bfs_frontier;
     if (c.opt.bfs_direction != 2 && (fr == 2 || (fr == 0 && g.cls == GRAPH_MESH))) {
-        run_bfs_bitmap(c, g, src, depth, s);
+        run_bfs_bitmap(c, g, src, depth, s, ar);
         return;
     }
     const int32_t n = g.n;
@@ -413,23 +415,23 @@ void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s)
     const CompactGeom cg = compact_geom(nwords, c.num_cu);
     size_t need = 2 * al256(nwords * 4ull) + al256(nwords * 32ull) + 3 * al256(4ull * n) + al256(4 * nparts) +
                   al256(4ull * G) + al256(16ull * cg.blocks) + al256(sizeof(BfsCtl));
-    c.arena.reserve(need);
+    ar.reserve(need);
     BfsArgs a;
     a.R = g.R.as<int32_t>();
     a.C = g.C.as<int32_t>();
     a.n = n;
     a.nwords = nwords;
     a.depth = depth;
-    a.vis = c.arena.take<uint32_t>(nwords);
-    a.fb = c.arena.take<uint32_t>(nwords);
-    a.mark = c.arena.take<uint8_t>(32ull * nwords);
-    a.q.v = c.arena.take<int32_t>(n);
-    a.q.off = c.arena.take<uint32_t>(n);
-    a.q.row = c.arena.take<int32_t>(n);
-    a.q.part = c.arena.take<int32_t>(nparts);
-    a.part_insp = c.arena.take<uint32_t>(G);
-    unsigned long long *status = c.arena.take<unsigned long long>(2ull * cg.blocks);
-    a.ctl = c.arena.take<BfsCtl>(1);
+    a.vis = ar.take<uint32_t>(nwords);
+    a.fb = ar.take<uint32_t>(nwords);
+    a.mark = ar.take<uint8_t>(32ull * nwords);
+    a.q.v = ar.take<int32_t>(n);
+    a.q.off = ar.take<uint32_t>(n);
+    a.q.row = ar.take<int32_t>(n);
+    a.q.part = ar.take<int32_t>(nparts);
+    a.part_insp = ar.take<uint32_t>(G);
+    unsigned long long *status = ar.take<unsigned long long>(2ull * cg.blocks);
+    a.ctl = ar.take<BfsCtl>(1);
 
     fill_u32(depth, 0xFFFFFFFFu, (size_t)n, s);
     fill_u32(a.vis, 0u, nwords, s);

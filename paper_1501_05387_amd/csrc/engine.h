@@ -60,20 +60,37 @@ struct DevMem {
     template <class T> T *as() const { return (T *)p; }
 };
 
-// Growable scratch arena, carved per solve.  Grows only.
+// Scratch arena, carved per solve.  The context's arena grows (and only
+// grows) by reallocating.  An arena over fixed device memory (second
+// constructor) never allocates: a solve that needs more than it holds fails
+// with GFR_E_CAPACITY before any device work is queued.
 struct Arena {
     DevMem mem;
+    char *fixed = nullptr;
+    size_t fixed_bytes = 0;
     size_t used = 0;
+    Arena() = default;
+    Arena(void *p, size_t bytes) : fixed((char *)p), fixed_bytes(bytes) {}
+    Arena(const Arena &) = delete;
+    Arena &operator=(const Arena &) = delete;
+    char *base() const { return fixed ? fixed : (char *)mem.p; }
+    size_t capacity() const { return fixed ? fixed_bytes : mem.bytes; }
     void reserve(size_t b)
     {
         used = 0;
+        if (fixed) {
+            if (b > fixed_bytes)
+                fail(GFR_E_CAPACITY, "needs " + std::to_string(b) + " bytes of scratch; the fixed scratch holds " +
+                                         std::to_string(fixed_bytes));
+            return;
+        }
         if (b > mem.bytes) mem.alloc(b + (b >> 3));
     }
     template <class T> T *take(size_t count)
     {
         size_t b = (count * sizeof(T) + 255) & ~(size_t)255;
-        if (used + b > mem.bytes) fail(GFR_E_DEVICE, "internal: arena overflow");
-        T *p = (T *)((char *)mem.p + used);
+        if (used + b > capacity()) fail(GFR_E_DEVICE, "internal: arena overflow");
+        T *p = (T *)(base() + used);
         used += b;
         return p;
     }
@@ -242,6 +259,7 @@ struct Ctx {
     std::map<int64_t, std::unique_ptr<Graph>> graphs;
     int64_t next_handle = 1;
     Arena arena;
+    void *noalloc_scratch = nullptr;   // this device's fixed scratch (gfr_bfs_noalloc)
     DevMem stage;                 // device staging for host output buffers
     DevMem zero_word;             // a device word that always holds 0
     uint32_t *pinned = nullptr;   // small pinned host buffer for control readbacks
@@ -279,6 +297,8 @@ int grid_blocks(const Ctx &c, int per_cu = 4);
 
 // Solvers (outputs are device pointers on the context's device).
 void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s);
+// the same with its scratch carved from `ar` (the context's arena, or fixed memory)
+void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s, Arena &ar);
 void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s);
 // Predecessors from finished distances (device pointers): the first neighbour one step closer.
 void run_bfs_pred(Ctx &c, Graph &g, int32_t src, const int32_t *depth, int32_t *pred, hipStream_t s);
