@@ -95,6 +95,9 @@ const char *gfr_last_error(const gfr_ctx *ctx);
  *   "bfs.frontier"    0 auto, 1 queue levels (advance + compaction), 2 mark-byte levels:
  *                     the frontier is a byte per vertex, one launch per level, push
  *                     only (auto: mark bytes on mesh-class graphs unless pull is forced)
+ *   "sssp.frontier"   0 auto (= 1), 1 queue iterations (advance + compaction), 2 mark-byte
+ *                     iterations: the near and far sets are bytes per vertex, one launch
+ *                     per iteration
  *   "sssp.delta"      bucket width of the near/far priority queue (Sec. 4.5);
  *                     0 = "sssp.delta_factor" (default 2) times the mean edge weight
  *   "advance.chunk"   edges per work-group chunk of the load-balanced advance (Sec. 4.4),
@@ -105,6 +108,18 @@ const char *gfr_last_error(const gfr_ctx *ctx);
  *   "batch.pull_alpha" batched SSSP: relax by a pull sweep (one owner-side minimum per
  *                     vertex and query) when the frontier's edges exceed m / alpha;
  *                     0 (default) = always push
+ *   "batch.narrow"    batched SSSP distance rows: 0 (default) 32 bits; 1 auto (scale-free graphs
+ *                     start at the narrowest width no earlier batch on the graph outgrew); 2 try
+ *                     16 bits first; 3 try 8 bits first.  A batch whose distances outgrow its rows
+ *                     is solved again with rows twice as wide; results do not change
+ *   "batch.blocks_per_cu"  batched SSSP relaxation grid: work-groups per CU (default 64, at
+ *                     most 64, and never more than one per 1024 edges of the graph), 0 = as
+ *                     many as are resident at once
+ *   "batch.pair"      batched SSSP with 32-bit rows: 1 relaxes two edges per distance-row
+ *                     load (each half-wave one edge), 0 (default) one edge per load
+ *   "graph.steps"     1: the level loops of BFS, SSSP and the batched solvers replay their
+ *                     speculative batches of level launches from hipGraphs captured once per
+ *                     distinct set of launch arguments; 0 (default): plain launches
  *   "bc.direction"    BC forward discovery (Sec. 5.3 with the push/pull choice of
  *                     Sec. 4.5): 0 auto, 1 push only, 2 pull only; results do not change
  *   "bc.alpha", "bc.beta"  the same ratios as bfs.alpha / bfs.beta for BC's levels

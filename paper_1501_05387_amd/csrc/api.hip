@@ -38,6 +38,17 @@ bool is_device_ptr(const void *p)
 
 int grid_blocks(const Ctx &c, int per_cu) { return c.num_cu * per_cu; }
 
+int resident_grid(const Ctx &c, const void *kernel, int per_cu)
+{
+    if (per_cu > 0) return c.num_cu * per_cu;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, GFR_BLOCK, 0) != hipSuccess || nb < 1) {
+        (void)hipGetLastError();
+        nb = 4;
+    }
+    return c.num_cu * nb;
+}
+
 // Scratch of gfr_bfs_noalloc: one fixed array per device (the code object's
 // copy on that device), never allocated or freed by the library.  Host code
 // must not use the array's name as an address: it is a host-side stand-in.
@@ -74,7 +85,6 @@ static bool is_device_ptr_on(const void *p, int device)
     }
     return attr.type == hipMemoryTypeDevice && attr.device == device;
 }
-
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t count)
 {
@@ -329,12 +339,14 @@ struct OptKey {
 static const OptKey kOptKeys[] = {
     {"bfs.direction", 0, 2, true},       {"bfs.alpha", 1e-6, 1e9, true},
     {"bfs.beta", 1e-6, 1e9, true},       {"bfs.dedup", 0, 1, true},
-    {"bfs.frontier", 0, 2, true},
+    {"bfs.frontier", 0, 2, true},        {"sssp.frontier", 0, 2, true},
     {"sssp.delta", 0, 4.0e9, true},      {"advance.chunk", 256, 4096, true},
     {"sssp.delta_factor", 1e-3, 1e6, true}, {"batch.delta_factor", 0, 1e6, true},
     {"msbfs.alpha", 1e-6, 1e9, true},    {"batch.delta", 0, 4.0e9, true},
     {"batch.min_bfs", 1, 1e9, true},     {"batch.min_sssp", 1, 1e9, true},
-    {"batch.pull_alpha", 0, 1e6, true},  {"batch.narrow", 0, 2, true},
+    {"batch.pull_alpha", 0, 1e6, true},  {"batch.narrow", 0, 3, true},
+    {"batch.blocks_per_cu", 0, 64, true}, {"graph.steps", 0, 1, false},
+    {"batch.pair", 0, 1, true},
     {"bc.direction", 0, 2, true},
     {"bc.alpha", 1e-6, 1e9, true},       {"bc.beta", 1e-6, 1e9, true},
     {"twohop.direction", 0, 2, true},    {"twohop.alpha", 1e-6, 1e9, true},
@@ -358,6 +370,7 @@ void option_set(Options &o, const std::string &key, double v)
     else if (key == "bfs.beta") o.bfs_beta = v;
     else if (key == "bfs.dedup") o.bfs_dedup = (int)v;
     else if (key == "bfs.frontier") o.bfs_frontier = (int)v;
+    else if (key == "sssp.frontier") o.sssp_frontier = (int)v;
     else if (key == "sssp.delta") o.sssp_delta = v;
     else if (key == "sssp.delta_factor") o.sssp_delta_factor = v;
     else if (key == "batch.delta_factor") o.batch_delta_factor = v;
@@ -366,6 +379,9 @@ void option_set(Options &o, const std::string &key, double v)
     else if (key == "batch.min_bfs") o.batch_min_bfs = (int)v;
     else if (key == "batch.min_sssp") o.batch_min_sssp = (int)v;
     else if (key == "batch.pull_alpha") o.batch_pull_alpha = v;
+    else if (key == "batch.blocks_per_cu") o.batch_blocks_per_cu = (int)v;
+    else if (key == "graph.steps") o.step_graphs = (int)v;
+    else if (key == "batch.pair") o.batch_pair = (int)v;
     else if (key == "batch.narrow") o.batch_narrow = (int)v;
     else if (key == "bc.direction") o.bc_direction = (int)v;
     else if (key == "bc.alpha") o.bc_alpha = v;
@@ -392,6 +408,7 @@ static double option_get(const Options &o, const std::string &key)
     if (key == "bfs.beta") return o.bfs_beta;
     if (key == "bfs.dedup") return o.bfs_dedup;
     if (key == "bfs.frontier") return o.bfs_frontier;
+    if (key == "sssp.frontier") return o.sssp_frontier;
     if (key == "sssp.delta") return o.sssp_delta;
     if (key == "sssp.delta_factor") return o.sssp_delta_factor;
     if (key == "batch.delta_factor") return o.batch_delta_factor;
@@ -401,6 +418,9 @@ static double option_get(const Options &o, const std::string &key)
     if (key == "batch.min_bfs") return o.batch_min_bfs;
     if (key == "batch.min_sssp") return o.batch_min_sssp;
     if (key == "batch.pull_alpha") return o.batch_pull_alpha;
+    if (key == "batch.blocks_per_cu") return o.batch_blocks_per_cu;
+    if (key == "graph.steps") return o.step_graphs;
+    if (key == "batch.pair") return o.batch_pair;
     if (key == "batch.narrow") return o.batch_narrow;
     if (key == "bc.direction") return o.bc_direction;
     if (key == "bc.alpha") return o.bc_alpha;
@@ -598,6 +618,7 @@ gfr_status gfr_ctx_destroy(gfr_ctx *ctx)
     (void)hipSetDevice(c->device);
     serve_shutdown(*c);
     c->graphs.clear();
+    c->step_graphs.clear();
     c->arena.mem.release();
     c->stage.release();
     c->zero_word.release();

@@ -417,6 +417,7 @@ void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s, Arena
                   al256(4ull * G) + al256(16ull * cg.blocks) + al256(sizeof(BfsCtl));
     ar.reserve(need);
     BfsArgs a;
+    memset(&a, 0, sizeof a);   // padding too: the bytes key the captured steps
     a.R = g.R.as<int32_t>();
     a.C = g.C.as<int32_t>();
     a.n = n;
@@ -459,8 +460,11 @@ void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s, Arena
                                cg.wpt, marks, a.q, chunk, status, &a.ctl->parity, &a.ctl->err);
         });
     };
+    // (no captured steps over fixed scratch: instantiating a graph may allocate)
+    StepKey key("bfs");
+    key.add(a).add(G).add(cg).add(chunk).add(status);
     const int32_t launched = run_until_done(c, &a.ctl->dir, DIR_DONE, g.levels_hint() + 1,
-                                            (int64_t)n + 4, s, launch);
+                                            (int64_t)n + 4, s, launch, ar.fixed ? nullptr : &key);
     BfsCtl h;
     GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, s));
     GFR_HIP(hipStreamSynchronize(s));

@@ -61,6 +61,13 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x)
     return x;
 }
 
+__device__ __forceinline__ uint32_t wave_or_u32(uint32_t x)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x |= (uint32_t)__shfl_xor((int)x, d, 64);
+    return x;
+}
+
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x)
 {
 #pragma unroll

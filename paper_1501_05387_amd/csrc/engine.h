@@ -129,8 +129,9 @@ struct Graph {
     std::atomic<int32_t> sssp_iter_hint{16};
     int32_t levels_hint() const { return bfs_levels_hint.load(std::memory_order_relaxed); }
     int32_t iter_hint() const { return sssp_iter_hint.load(std::memory_order_relaxed); }
-    // a batched SSSP on this graph outgrew 16-bit distance rows once
-    std::atomic<bool> narrow_overflowed{false};
+    // narrowest distance-row width (8, 16 or 32 bits) that no batched SSSP
+    // on this graph has outgrown
+    std::atomic<int> row_bits_min{8};
 };
 
 struct Options {
@@ -139,6 +140,7 @@ struct Options {
     double bfs_beta = 18.0;
     int bfs_dedup = 0;          // 0 atomic, 1 idempotent
     int bfs_frontier = 0;       // 0 auto (mark bytes on mesh-class graphs), 1 queue, 2 mark bytes
+    int sssp_frontier = 0;      // 0 auto (queue iterations), 1 queue, 2 mark bytes
     double sssp_delta = 0.0;    // 0 -> sssp_delta_factor x mean edge weight
     double sssp_delta_factor = 2.0;
     int advance_chunk = 1024;
@@ -148,7 +150,10 @@ struct Options {
     double batch_delta = 0.0;   // batched SSSP bucket width; 0 -> batch_delta_factor
     double batch_delta_factor = 0.0;   // x mean edge weight; 0 -> one bucket (frontier order)
     double batch_pull_alpha = 0.0;     // batched SSSP: pull sweep when frontier edges > m / alpha (0: never)
-    int batch_narrow = 1;       // batched SSSP 16-bit distance rows: 0 never, 1 auto, 2 always tried first
+    int batch_narrow = 0;       // batched SSSP narrow rows: 0 never, 1 auto, 2 from 16 bits, 3 from 8 bits
+    int batch_blocks_per_cu = 64;  // batched SSSP relax grid: work-groups per CU, 0 = as many as are resident
+    int batch_pair = 0;         // batched SSSP, 32-bit rows: relax two edges per row instruction
+    int step_graphs = 0;        // replay level steps from captured hipGraphs
     int serve_max_batch = 64;
     int serve_graphs = 1;       // serving sessions replay their rounds from captured hipGraphs
     int batch_min_bfs = 8;      // fewer sources than this: sequential single-source BFS
@@ -248,6 +253,64 @@ struct KernelTimer {
     }
 };
 
+// Captured level steps of the speculative level loop: a batch of k step
+// launches is captured into a hipGraph the first time and replayed after.
+// The key holds the bytes of every argument and the geometry of the step's
+// launches, so a replay launches exactly what the direct launches would; the
+// kernels read all state that changes from device memory.
+struct StepGraphs {
+    struct Entry {
+        std::string key;
+        int32_t k;
+        hipGraphExec_t exec;
+        uint64_t last;
+    };
+    std::vector<Entry> v;
+    uint64_t tick = 0;
+    static constexpr size_t kMax = 64;
+    StepGraphs() = default;
+    StepGraphs(const StepGraphs &) = delete;
+    StepGraphs &operator=(const StepGraphs &) = delete;
+    hipGraphExec_t find(const std::string &key, int32_t k)
+    {
+        for (auto &e : v)
+            if (e.k == k && e.key == key) {
+                e.last = ++tick;
+                return e.exec;
+            }
+        return nullptr;
+    }
+    void put(const std::string &key, int32_t k, hipGraphExec_t exec)
+    {
+        if (v.size() >= kMax) {
+            size_t old = 0;
+            for (size_t i = 1; i < v.size(); ++i)
+                if (v[i].last < v[old].last) old = i;
+            (void)hipGraphExecDestroy(v[old].exec);
+            v.erase(v.begin() + (long)old);
+        }
+        v.push_back({key, k, exec, ++tick});
+    }
+    void clear()
+    {
+        for (auto &e : v) (void)hipGraphExecDestroy(e.exec);
+        v.clear();
+    }
+    ~StepGraphs() { clear(); }
+};
+
+// Key bytes of a step: append every launch argument struct (zero-filled
+// before its fields were set, so padding compares equal) and the geometry.
+struct StepKey {
+    std::string k;
+    explicit StepKey(const char *tag) : k(tag) { k.push_back('\0'); }
+    template <class T> StepKey &add(const T &x)
+    {
+        k.append((const char *)&x, sizeof(T));
+        return *this;
+    }
+};
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -270,6 +333,7 @@ struct Ctx {
     Server *server = nullptr;     // owned; destroyed by serve_shutdown
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     KernelTimer ktimer;
+    StepGraphs step_graphs;       // captured level steps, replayed by run_until_done
     Bounce bounce;                // for results written to pageable host memory
     // context-wide options as set (OptScope only changes `opt`), for the
     // serving thread, which holds opt_mu instead of mu to read them
@@ -294,6 +358,10 @@ struct OptScope {
 Graph &get_graph(Ctx &c, gfr_graph h);
 bool is_device_ptr(const void *p);
 int grid_blocks(const Ctx &c, int per_cu = 4);
+// Work-groups of GFR_BLOCK threads for a grid-stride kernel: per_cu per CU,
+// or (per_cu = 0) as many as are resident at once on every CU, so that no
+// work-group of a statically divided grid starts after the others finish.
+int resident_grid(const Ctx &c, const void *kernel, int per_cu);
 
 // Solvers (outputs are device pointers on the context's device).
 void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s);
@@ -395,15 +463,41 @@ bool serve_stat(Ctx &c, const std::string &key, double *value);
 void fill_u32(void *p, uint32_t value, size_t count, hipStream_t s);
 
 // Spin on a device word until the speculative level loop reports completion.
-// Launches `launch(k)` batches and reads *flag (device) back after each batch.
+// Launches `launch()` batches and reads *flag (device) back after each batch.
+// With a step key (and option "graph.steps" on, per-launch timing off), each
+// batch of k steps is replayed from a hipGraph captured the first time that
+// key and k were seen; a capture that fails falls back to direct launches.
 template <class LaunchFn>
 int32_t run_until_done(Ctx &c, const uint32_t *flag_dev, uint32_t done_value, int32_t first_batch,
-                       int64_t max_launches, hipStream_t s, LaunchFn launch)
+                       int64_t max_launches, hipStream_t s, LaunchFn launch, const StepKey *key = nullptr)
 {
     int64_t launched = 0;
     int32_t batch = first_batch < 1 ? 1 : first_batch;
+    const bool graphs = key && c.opt.step_graphs && !c.ktimer.on;
     for (;;) {
-        for (int32_t i = 0; i < batch; ++i) launch();
+        hipGraphExec_t exec = graphs ? c.step_graphs.find(key->k, batch) : nullptr;
+        if (graphs && !exec) {
+            hipGraph_t gr = nullptr;
+            bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                for (int32_t i = 0; i < batch; ++i) launch();
+                ok = hipStreamEndCapture(s, &gr) == hipSuccess && gr;
+            }
+            if (ok) ok = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0) == hipSuccess;
+            if (gr) (void)hipGraphDestroy(gr);
+            if (ok) {
+                c.step_graphs.put(key->k, batch, exec);
+            } else {
+                (void)hipGetLastError();
+                exec = nullptr;
+            }
+        }
+        if (exec) {
+            GFR_HIP(hipGraphLaunch(exec, s));
+            c.stats.v["graph_launches"] += 1.0;
+        } else {
+            for (int32_t i = 0; i < batch; ++i) launch();
+        }
         GFR_LAUNCH_CHECK();
         launched += batch;
         GFR_HIP(hipMemcpyAsync(c.pinned, flag_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s));

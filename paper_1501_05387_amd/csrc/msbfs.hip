@@ -350,6 +350,7 @@ void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t 
                     al256(16ull * cg.blocks) + al256(sizeof(MsCtl)) + 2 * al256(4 * 64) + al256(8ull * G) +
                     al256(8ull * n * MS_LVL_CAP));
     MsArgs a;
+    memset(&a, 0, sizeof a);   // padding too: the bytes key the captured steps
     a.R = g.R.as<int32_t>();
     a.C = g.C.as<int32_t>();
     a.n = n;
@@ -401,7 +402,9 @@ void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t 
                                    cg.wpt, MsMarks{a}, a.q, chunk, status, &a.ctl->parity, &a.ctl->err);
             });
         };
-        run_until_done(c, &a.ctl->dir, MS_DONE, g.levels_hint() + 2, (int64_t)n + 8, s, launch);
+        StepKey key("msbfs");
+        key.add(a).add(G).add(cg).add(chunk).add(status);
+        run_until_done(c, &a.ctl->dir, MS_DONE, g.levels_hint() + 2, (int64_t)n + 8, s, launch, &key);
         MsCtl h;
         GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, s));
         GFR_HIP(hipStreamSynchronize(s));

@@ -10,13 +10,14 @@
 // single-source SSSP; the queries share the near/far bucket bound of the
 // priority queue (Sec. 4.5), which only changes the schedule, not the result.
 //
-// Narrow rows: a batch first runs with 16-bit distances (128-byte rows, half
-// the bytes of every random row access), unreached = 0xFFFF.  A relaxation
-// that would store a distance of 0xFFFF or more sets the overflow flag, the
-// traversal stops, and the batch is solved again with 32-bit rows; so a
-// finished narrow batch stored exactly the distances the wide one would.
-// Queries 2k and 2k+1 share a 32-bit word of a narrow row, which is lowered
-// with compare-and-swap (there is no 16-bit atomic minimum).
+// Narrow rows: a batch first runs with 8-bit distances (64-byte rows, a
+// quarter of the bytes of every random row access), unreached = 0xFF.  A
+// relaxation that would store 0xFF or more sets the overflow flag, the
+// traversal stops, and the batch is solved again with 16-bit rows (128
+// bytes, unreached 0xFFFF), and past those with 32-bit rows; so a finished
+// narrow batch stored exactly the distances the wide one would.  The 2 or 4
+// queries that share a 32-bit word of a narrow row lower it together with
+// compare-and-swap (there is no 8- or 16-bit atomic minimum).
 //
 // Marks: per vertex a 64-bit mask of the queries improved in an iteration
 // (one atomicOr of the wave's ballot per improved edge, not one byte store
@@ -35,6 +36,7 @@
 //                 or, when the near queue has run dry, the far split with
 //                 the next bucket (compact.h), plus the control.
 #include <algorithm>
+#include <type_traits>
 
 #include "compact.h"
 #include "device.h"
@@ -60,6 +62,8 @@ struct BsCtl {
     unsigned long long m;
     uint32_t pull_iters, pad2;
     unsigned long long lane_relaxed;   // (edge, query) relaxations: edges visited x queries active at the source
+    uint32_t unfit;              // 32-bit rows: a relaxation's sum did not fit below 0xFFFFFFFF (checked after the batch)
+    uint32_t pad3;
 };
 
 struct BsArgs {
@@ -68,8 +72,9 @@ struct BsArgs {
     const uint32_t *W;
     int32_t n;
     uint32_t nwords;
-    uint32_t *D;                 // [n][64] wide rows
-    uint16_t *D16;               // [n][64] narrow rows (the same memory)
+    uint32_t *D;                 // [n][64] 32-bit rows
+    uint16_t *D16;               // [n][64] 16-bit rows (the same memory)
+    uint8_t *D8;                 // [n][64] 8-bit rows (the same memory)
     unsigned long long *qm;      // query mask of every queued vertex
     unsigned long long *nq, *fq; // [n] queries improved into the near / far set
     uint8_t *nany, *fany;        // [n] (padded)
@@ -86,47 +91,71 @@ constexpr int BS_UNROLL = 8;   // edges relaxed together (two distance rows each
 constexpr uint32_t BS_INF = 0xFFFFFFFFu;
 constexpr uint32_t BS_INF16 = 0xFFFFu;
 
+// unreached value of a row of BITS-bit distances
+template <int BITS> __device__ __forceinline__ constexpr uint32_t row_inf()
+{
+    return BITS == 8 ? 0xFFu : BITS == 16 ? 0xFFFFu : 0xFFFFFFFFu;
+}
+
 // distance of query q at vertex v in 32-bit form (unreached: BS_INF)
-template <bool NARROW>
+template <int BITS>
 __device__ __forceinline__ uint32_t bs_load(const BsArgs &a, size_t v, int q)
 {
-    if (NARROW) {
+    if (BITS == 8) {
+        const uint32_t x = a.D8[v * 64 + q];
+        return x == 0xFFu ? BS_INF : x;
+    }
+    if (BITS == 16) {
         const uint32_t x = a.D16[v * 64 + q];
         return x == BS_INF16 ? BS_INF : x;
     }
     return a.D[v * 64 + q];
 }
 
-template <bool NARROW>
+template <int BITS>
 __device__ __forceinline__ void bs_store(const BsArgs &a, size_t v, int q, uint32_t d)
 {
-    if (NARROW) a.D16[v * 64 + q] = (uint16_t)(d == BS_INF ? BS_INF16 : d);
+    if (BITS == 8) a.D8[v * 64 + q] = (uint8_t)(d == BS_INF ? 0xFFu : d);
+    else if (BITS == 16) a.D16[v * 64 + q] = (uint16_t)(d == BS_INF ? BS_INF16 : d);
     else a.D[v * 64 + q] = d;
 }
 
 // Lower the distance of the calling lane's query at vertex v to nd where
 // `imp` is set; `cur` is the value the lane loaded.  Called by the whole
-// wave.  Wide rows: one non-returning atomicMin per improving lane.  Narrow
-// rows: the even lane of each pair writes the pair's word by compare-and-swap
-// (a failed swap returns a word another update lowered; the minima are taken
-// again against it until the swap succeeds or nothing is left to lower).
-template <bool NARROW>
+// wave.  32-bit rows: one non-returning atomicMin per improving lane.
+// Narrow rows: the first lane of each group of 32 / BITS lanes writes the
+// group's word by compare-and-swap (a failed swap returns a word another
+// update lowered; the minima are taken again against it until the swap
+// succeeds or nothing is left to lower).
+template <int BITS>
 __device__ __forceinline__ void bs_lower(const BsArgs &a, size_t v, int lane, uint32_t nd, bool imp, uint32_t cur)
 {
-    if (!NARROW) {
+    if (BITS == 32) {
         if (imp) atomicMin(a.D + v * 64 + lane, nd);
         return;
     }
-    const uint32_t want = imp ? nd : BS_INF16;   // nd < 0xFFFF wherever imp holds
-    const uint32_t raw = cur == BS_INF ? BS_INF16 : cur;
-    const uint32_t want_p = (uint32_t)__shfl_xor((int)want, 1, 64);
-    const uint32_t raw_p = (uint32_t)__shfl_xor((int)raw, 1, 64);
-    if ((lane & 1) == 0 && (want < raw || want_p < raw_p)) {
-        uint32_t *w = (uint32_t *)(a.D16 + v * 64 + lane);
-        uint32_t expect = raw | (raw_p << 16);
+    constexpr int PER = 32 / BITS;   // lanes per 32-bit word
+    constexpr uint32_t INF = row_inf<BITS>();
+    const uint32_t want = imp ? nd : INF;   // nd < INF wherever imp holds
+    const uint32_t raw = cur == BS_INF ? INF : cur;
+    const int base = lane & ~(PER - 1);
+    uint32_t wv[PER], rv[PER];
+    bool lower = false;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        wv[j] = (uint32_t)__shfl((int)want, base + j, 64);
+        rv[j] = (uint32_t)__shfl((int)raw, base + j, 64);
+        lower |= wv[j] < rv[j];
+    }
+    if (lane == base && lower) {
+        uint32_t *w = (uint32_t *)(a.D8 + (v * 64 + lane) * (BITS / 8));
+        uint32_t expect = 0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) expect |= rv[j] << (BITS * j);
         for (;;) {
-            const uint32_t lo = min(expect & 0xFFFFu, want), hi = min(expect >> 16, want_p);
-            const uint32_t desired = lo | (hi << 16);
+            uint32_t desired = 0;
+#pragma unroll
+            for (int j = 0; j < PER; ++j) desired |= min((expect >> (BITS * j)) & INF, wv[j]) << (BITS * j);
             if (desired == expect) break;
             const uint32_t old = atomicCAS(w, expect, desired);
             if (old == expect) break;
@@ -137,7 +166,7 @@ __device__ __forceinline__ void bs_lower(const BsArgs &a, size_t v, int lane, ui
 
 __device__ __forceinline__ int32_t lane_bcast(int32_t x, int j) { return __builtin_amdgcn_readlane(x, j); }
 
-template <int CH, bool NARROW>
+template <int CH, int BITS>
 __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
 {
     BsCtl *ctl = a.ctl;
@@ -151,7 +180,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
     constexpr uint32_t QW = CH / GFR_WAVES;
     const uint32_t nchunks = (mf + CH - 1) / CH;
     uint32_t nimp = 0, nfar = 0, nlr = 0;
-    bool ovf = false;
+    bool ovf = false, unf = false;
     for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
         const uint32_t e0 = c * CH;
         const uint32_t e1 = min(e0 + (uint32_t)CH, mf);
@@ -201,23 +230,23 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
                 const bool fits = nd64 < 0xFFFFFFFFull;
                 const uint32_t nd = (uint32_t)nd64;
                 bool imp;
-                if (NARROW) {
+                if (BITS < 32) {
                     // an improvement that does not fit a narrow row stops the
-                    // batch (it is solved again with wide rows), and so does
-                    // a sum the wide rows would reject
+                    // batch (it is solved again with wider rows), and so does
+                    // a sum the 32-bit rows would reject
                     const bool cand = act & (nd64 < (unsigned long long)dv);
-                    imp = cand & (nd64 < (unsigned long long)BS_INF16);
+                    imp = cand & (nd64 < (unsigned long long)row_inf<BITS>());
                     ovf |= (cand & !imp) | (act & !fits);
                 } else {
                     imp = act & fits & (nd < dv);
-                    ovf |= act & !fits;
+                    unf |= act & !fits;
                 }
                 nlr += act ? 1u : 0u;
                 // the update does not return a value: the mark follows the
                 // pre-check, a superset of the true improvements (a marked
                 // vertex is simply relaxed again with its current distance)
                 const bool near_imp = imp & (nd < hi), far_imp = imp & (nd >= hi);
-                if (ballot(imp)) bs_lower<NARROW>(a, (size_t)v, lane, nd, imp, dv);
+                if (ballot(imp)) bs_lower<BITS>(a, (size_t)v, lane, nd, imp, dv);
                 nimp += imp ? 1u : 0u;
                 const uint64_t bn = ballot(near_imp), bf = ballot(far_imp);
                 if (lane == 0) {
@@ -236,7 +265,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
             if (u_first == lane_bcast(ul, nb - 1)) {
                 // the whole group leaves one vertex (edges are in source
                 // order): its distance row and query bit are loaded once
-                const uint32_t du = bs_load<NARROW>(a, (size_t)u_first, lane);
+                const uint32_t du = bs_load<BITS>(a, (size_t)u_first, lane);
                 const uint32_t q0 = (uint32_t)lane_bcast(qlo, 0), q1 = (uint32_t)lane_bcast(qhi, 0);
                 const bool act_u = (((lane < 32 ? q0 : q1) >> (lane & 31)) & 1u) != 0;
                 for (int j0 = 0; j0 < nb; j0 += 16) {
@@ -247,7 +276,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
                         const int src = min(j0 + j, nb - 1);   // a padded edge repeats the last one
                         vv[j] = lane_bcast(vl, src);
                         ww[j] = (uint32_t)lane_bcast(wl, src);
-                        dv[j] = bs_load<NARROW>(a, (size_t)vv[j], lane);
+                        dv[j] = bs_load<BITS>(a, (size_t)vv[j], lane);
                     }
 #pragma unroll
                     for (int j = 0; j < 16; ++j) relax(vv[j], ww[j], du, dv[j], act_u & (j0 + j < nb));
@@ -264,8 +293,8 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
                         ww[j] = (uint32_t)lane_bcast(wl, src);
                         const uint32_t q0 = (uint32_t)lane_bcast(qlo, src), q1 = (uint32_t)lane_bcast(qhi, src);
                         qw[j] = lane < 32 ? q0 : q1;
-                        du[j] = bs_load<NARROW>(a, (size_t)u, lane);
-                        dv[j] = bs_load<NARROW>(a, (size_t)vv[j], lane);
+                        du[j] = bs_load<BITS>(a, (size_t)u, lane);
+                        dv[j] = bs_load<BITS>(a, (size_t)vv[j], lane);
                     }
 #pragma unroll
                     for (int j = 0; j < BS_UNROLL; ++j)
@@ -275,6 +304,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
         }
     }
     if (ovf) ctl->overflow = 1u;
+    if (unf) ctl->unfit = 1u;
     __shared__ uint32_t s_a[GFR_WAVES], s_b[GFR_WAVES], s_c[GFR_WAVES];
     nimp = wave_sum_u32(nimp);
     nlr = wave_sum_u32(nlr);
@@ -297,6 +327,203 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
     }
 }
 
+// bit i of x moved to bit 2i (a 32-bit value spread over 64 bits)
+__device__ __forceinline__ unsigned long long spread2(uint32_t x32)
+{
+    unsigned long long x = x32;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
+// The relaxation of bsssp_relax with 32-bit rows, two edges per distance-row
+// instruction: lanes 0-31 take edge A and lanes 32-63 edge B, lane k of a half
+// holding queries 2k and 2k+1 of the row as one 8-byte word.  A random row
+// costs about the same per instruction whatever its width, so this halves the
+// row instructions of every edge visit.  Improving queries are lowered with
+// non-returning atomicMin, as in bsssp_relax.
+constexpr int BP2_U = 4;    // edge pairs relaxed together (source and target rows of each)
+constexpr int BP2_UH = 8;   // edge pairs relaxed together when the group leaves one vertex
+
+template <int CH>
+__global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax2(BsArgs a)
+{
+    BsCtl *ctl = a.ctl;
+    if (ctl->mode != BS_RELAX || ctl->dir != BS_PUSH) return;
+    const uint32_t hi = ctl->hi, nf = ctl->nf, mf = ctl->mf;
+    const FrontierQ q = a.q;
+    const uint2 *D2 = (const uint2 *)a.D;
+    __shared__ uint32_t s_off[CH + 1];
+    __shared__ int32_t s_row[CH + 1];
+    __shared__ int32_t s_v[CH + 1];
+    const int lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int half = lane >> 5, k = lane & 31;
+    const int qshift = (2 * k) & 31;
+    constexpr uint32_t QW = CH / GFR_WAVES;
+    const uint32_t nchunks = (mf + CH - 1) / CH;
+    uint32_t nimp = 0, nfar = 0, nlr = 0;
+    bool unf = false;
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const uint32_t e0 = c * CH;
+        const uint32_t e1 = min(e0 + (uint32_t)CH, mf);
+        const int s = q.part[c];
+        const int t = (c + 1 < nchunks) ? q.part[c + 1] : (int)nf - 1;
+        const int cnt = t - s + 1;
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += GFR_BLOCK) {
+            s_off[i] = q.off[s + i];
+            s_row[i] = q.row[s + i];
+            s_v[i] = q.v[s + i];
+        }
+        __syncthreads();
+        const uint32_t eb = e0 + wave * QW, ee = min(eb + QW, e1);
+        if (eb >= ee) continue;
+        int ilo = upper_index(s_off, 0, cnt - 1, eb);
+        auto fetch = [&](uint32_t e, int nbx, int32_t &vx, int32_t &wx, int32_t &ux, unsigned long long &qx) {
+            const uint32_t el = e + (uint32_t)min(lane, nbx - 1);
+            const int il = upper_index(s_off, ilo, min(cnt - 1, ilo + lane + 1), el);
+            const int32_t idx = s_row[il] + (int32_t)(el - s_off[il]);
+            vx = a.C[idx];
+            wx = (int32_t)a.W[idx];
+            ux = s_v[il];
+            qx = a.qm[ux];
+            ilo = lane_bcast(il, nbx - 1);
+        };
+        int nbn = (int)min(64u, ee - eb);
+        int32_t vn, wn, un;
+        unsigned long long qn;
+        fetch(eb, nbn, vn, wn, un, qn);
+        for (uint32_t e = eb; e < ee; e += 64) {
+            const int nb = nbn;
+            const int32_t vl = vn, wl = wn, ul = un;
+            const unsigned long long ql = qn;
+            if (e + 64 < ee) {
+                nbn = (int)min(64u, ee - (e + 64));
+                fetch(e + 64, nbn, vn, wn, un, qn);
+            }
+            const int32_t qlo = (int32_t)(uint32_t)ql, qhi = (int32_t)(uint32_t)(ql >> 32);
+            // this lane's two query bits of the source of group edge j
+            auto qbits = [&](int j) -> uint32_t {
+                const uint32_t w = (uint32_t)(k < 16 ? lane_bcast(qlo, j) : lane_bcast(qhi, j));
+                return (w >> qshift) & 3u;
+            };
+            // relax one edge pair: this lane's half holds edge j (targets vA / vB of the pair)
+            auto relax2 = [&](int32_t vA, int32_t vB, int32_t v, uint32_t w, uint2 du, uint2 dv, uint32_t act) {
+                const unsigned long long s0 = (unsigned long long)du.x + w, s1 = (unsigned long long)du.y + w;
+                const bool a0 = act & 1u, a1 = (act >> 1) & 1u;
+                const bool f0 = s0 < 0xFFFFFFFFull, f1 = s1 < 0xFFFFFFFFull;
+                const uint32_t n0 = (uint32_t)s0, n1 = (uint32_t)s1;
+                const bool i0 = a0 & f0 & (n0 < dv.x), i1 = a1 & f1 & (n1 < dv.y);
+                unf |= (a0 & !f0) | (a1 & !f1);
+                nlr += (a0 ? 1u : 0u) + (a1 ? 1u : 0u);
+                nimp += (i0 ? 1u : 0u) + (i1 ? 1u : 0u);
+                if (ballot(i0 | i1)) {
+                    // non-returning updates; the marks follow the pre-check
+                    uint32_t *row = a.D + (size_t)v * 64 + 2 * k;
+                    if (i0) atomicMin(row, n0);
+                    if (i1) atomicMin(row + 1, n1);
+                    const uint64_t bn0 = ballot(i0 & (n0 < hi)), bn1 = ballot(i1 & (n1 < hi));
+                    const uint64_t bf0 = ballot(i0 & (n0 >= hi)), bf1 = ballot(i1 & (n1 >= hi));
+                    if (lane == 0) {
+                        const unsigned long long nA = spread2((uint32_t)bn0) | (spread2((uint32_t)bn1) << 1);
+                        const unsigned long long nB = spread2((uint32_t)(bn0 >> 32)) | (spread2((uint32_t)(bn1 >> 32)) << 1);
+                        const unsigned long long fA = spread2((uint32_t)bf0) | (spread2((uint32_t)bf1) << 1);
+                        const unsigned long long fB = spread2((uint32_t)(bf0 >> 32)) | (spread2((uint32_t)(bf1 >> 32)) << 1);
+                        if (nA) {
+                            atomicOr(a.nq + vA, nA);
+                            a.nany[vA] = 1;
+                        }
+                        if (nB) {
+                            atomicOr(a.nq + vB, nB);
+                            a.nany[vB] = 1;
+                        }
+                        if (fA) {
+                            atomicOr(a.fq + vA, fA);
+                            a.fany[vA] = 1;
+                            ++nfar;
+                        }
+                        if (fB) {
+                            atomicOr(a.fq + vB, fB);
+                            a.fany[vB] = 1;
+                            ++nfar;
+                        }
+                    }
+                }
+            };
+            const int32_t u_first = lane_bcast(ul, 0);
+            if (u_first == lane_bcast(ul, nb - 1)) {
+                // the whole group leaves one vertex: its row and query bits are loaded once
+                const uint2 du = D2[(size_t)u_first * 32 + k];
+                const uint32_t qb = qbits(0);
+                for (int j0 = 0; j0 < nb; j0 += 2 * BP2_UH) {
+                    uint2 dv[BP2_UH];
+                    int32_t vv[BP2_UH], vA[BP2_UH], vB[BP2_UH];
+                    uint32_t ww[BP2_UH];
+#pragma unroll
+                    for (int t2 = 0; t2 < BP2_UH; ++t2) {
+                        const int jA = min(j0 + 2 * t2, nb - 1), jB = min(j0 + 2 * t2 + 1, nb - 1);
+                        vA[t2] = lane_bcast(vl, jA);
+                        vB[t2] = lane_bcast(vl, jB);
+                        vv[t2] = half ? vB[t2] : vA[t2];
+                        ww[t2] = (uint32_t)(half ? lane_bcast(wl, jB) : lane_bcast(wl, jA));
+                        dv[t2] = D2[(size_t)vv[t2] * 32 + k];
+                    }
+#pragma unroll
+                    for (int t2 = 0; t2 < BP2_UH; ++t2)
+                        relax2(vA[t2], vB[t2], vv[t2], ww[t2], du, dv[t2], (j0 + 2 * t2 + half < nb) ? qb : 0u);
+                }
+            } else {
+                for (int j0 = 0; j0 < nb; j0 += 2 * BP2_U) {
+                    uint2 du[BP2_U], dv[BP2_U];
+                    int32_t vv[BP2_U], vA[BP2_U], vB[BP2_U];
+                    uint32_t ww[BP2_U], qb[BP2_U];
+#pragma unroll
+                    for (int t2 = 0; t2 < BP2_U; ++t2) {
+                        const int jA = min(j0 + 2 * t2, nb - 1), jB = min(j0 + 2 * t2 + 1, nb - 1);
+                        const int j = half ? jB : jA;
+                        const int32_t uA = lane_bcast(ul, jA), uB = lane_bcast(ul, jB);
+                        vA[t2] = lane_bcast(vl, jA);
+                        vB[t2] = lane_bcast(vl, jB);
+                        vv[t2] = half ? vB[t2] : vA[t2];
+                        ww[t2] = (uint32_t)(half ? lane_bcast(wl, jB) : lane_bcast(wl, jA));
+                        const uint32_t bA = qbits(jA), bB = qbits(jB);
+                        qb[t2] = (j0 + 2 * t2 + half < nb) ? (half ? bB : bA) : 0u;
+                        (void)j;
+                        du[t2] = D2[(size_t)(half ? uB : uA) * 32 + k];
+                        dv[t2] = D2[(size_t)vv[t2] * 32 + k];
+                    }
+#pragma unroll
+                    for (int t2 = 0; t2 < BP2_U; ++t2) relax2(vA[t2], vB[t2], vv[t2], ww[t2], du[t2], dv[t2], qb[t2]);
+                }
+            }
+        }
+    }
+    if (unf) ctl->unfit = 1u;
+    __shared__ uint32_t s_a[GFR_WAVES], s_b[GFR_WAVES], s_c[GFR_WAVES];
+    nimp = wave_sum_u32(nimp);
+    nlr = wave_sum_u32(nlr);
+    if (lane == 0) {
+        s_a[wave] = nimp;
+        s_b[wave] = nfar;
+        s_c[wave] = nlr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t x = 0, y = 0, z = 0;
+        for (int i = 0; i < GFR_WAVES; ++i) {
+            x += s_a[i];
+            y += s_b[i];
+            z += s_c[i];
+        }
+        a.part[4 * blockIdx.x] = x;
+        a.part[4 * blockIdx.x + 1] = y;
+        a.part[4 * blockIdx.x + 2] = z;
+    }
+}
+
 // Pull relaxation for frontiers that carry most of the edges: a
 // load-balanced sweep over every vertex's list (the whole-graph queue).  An
 // edge u->v with u in the frontier contributes dist[u][q] + w to a running
@@ -305,7 +532,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
 // per improving edge.  Sources outside the frontier cost one bitmap probe.
 constexpr int BP_UNROLL = 8;
 
-template <int CH, bool NARROW>
+template <int CH, int BITS>
 __global__ __launch_bounds__(GFR_BLOCK) void bsssp_pull(BsArgs a)
 {
     BsCtl *ctl = a.ctl;
@@ -320,19 +547,19 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_pull(BsArgs a)
     constexpr uint32_t QW = CH / GFR_WAVES;
     const uint32_t nchunks = (mf + CH - 1) / CH;
     uint32_t nimp = 0, nfar = 0, nlr = 0;
-    bool ovf = false;
+    bool ovf = false, unf = false;
     int32_t cur = -1;                 // owner whose minimum is being formed (wave-uniform)
     uint32_t acc = 0xFFFFFFFFu;       // its minimum for this lane's query
     uint32_t old = 0;                 // the owner's distance, loaded when the owner starts
     auto flush = [&]() {
         if (cur >= 0) {
             bool imp = acc < old;
-            if (NARROW && imp && acc >= BS_INF16) {
-                ovf = true;   // does not fit a narrow row: the batch is solved again with wide rows
+            if (BITS < 32 && imp && acc >= row_inf<BITS>()) {
+                ovf = true;   // does not fit a narrow row: the batch is solved again with wider rows
                 imp = false;
             }
             const bool near_imp = imp & (acc < hi), far_imp = imp & (acc >= hi);
-            if (ballot(imp)) bs_lower<NARROW>(a, (size_t)cur, lane, acc, imp, old);
+            if (ballot(imp)) bs_lower<BITS>(a, (size_t)cur, lane, acc, imp, old);
             nimp += imp ? 1u : 0u;
             const uint64_t bn = ballot(near_imp), bf = ballot(far_imp);
             if (lane == 0) {
@@ -403,7 +630,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_pull(BsArgs a)
                     ww[k] = (uint32_t)lane_bcast(wl, j);
                     const uint32_t q0 = (uint32_t)lane_bcast(qlo, j), q1 = (uint32_t)lane_bcast(qhi, j);
                     qw[k] = lane < 32 ? q0 : q1;
-                    du[k] = bs_load<NARROW>(a, (size_t)u, lane);
+                    du[k] = bs_load<BITS>(a, (size_t)u, lane);
                 }
 #pragma unroll
                 for (int k = 0; k < BP_UNROLL; ++k) {
@@ -411,13 +638,15 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_pull(BsArgs a)
                     if (vv[k] != cur) {
                         flush();
                         cur = vv[k];
-                        old = bs_load<NARROW>(a, (size_t)cur, lane);   // read by the owner's flush
+                        old = bs_load<BITS>(a, (size_t)cur, lane);   // read by the owner's flush
                     }
                     const bool on = ((qw[k] >> (lane & 31)) & 1u) != 0;
                     nlr += on ? 1u : 0u;
                     const unsigned long long nd64 = (unsigned long long)du[k] + ww[k];
                     const bool fits = nd64 < 0xFFFFFFFFull;
-                    ovf |= on & !fits;
+                    // a narrow batch is solved again with wider rows; 32-bit rows note it for the final check
+                    if (BITS < 32) ovf |= on & !fits;
+                    else unf |= on & !fits;
                     const uint32_t nd = (uint32_t)nd64;
                     acc = (on & fits & (nd < acc)) ? nd : acc;
                 }
@@ -427,6 +656,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_pull(BsArgs a)
         cur = -1;
     }
     if (ovf) ctl->overflow = 1u;
+    if (unf) ctl->unfit = 1u;
     __shared__ uint32_t s_a[GFR_WAVES], s_b[GFR_WAVES], s_c[GFR_WAVES];
     nimp = wave_sum_u32(nimp);
     nlr = wave_sum_u32(nlr);
@@ -450,7 +680,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_pull(BsArgs a)
 }
 
 // 64 mark bytes (0/1) of one vertex -> query mask; clears them when `clear`
-template <bool NARROW>
+template <int BITS>
 struct BsMarks {
     BsArgs a;
     uint32_t nparts;
@@ -514,7 +744,7 @@ struct BsMarks {
             while (fm) {
                 const int qq = __ffsll(fm) - 1;
                 fm &= fm - 1;
-                const uint32_t d = bs_load<NARROW>(a, (size_t)v, qq);
+                const uint32_t d = bs_load<BITS>(a, (size_t)v, qq);
                 if (d < hi) {
                     if (d >= lo) nm |= 1ull << qq;
                 } else {
@@ -678,13 +908,13 @@ struct BsMarks {
     }
 };
 
-template <bool NARROW>
+template <int BITS>
 __global__ void bsssp_init(BsArgs a, const int32_t *src, int32_t k, uint32_t delta, float pull_alpha)
 {
     if (threadIdx.x == 0) {
         for (int32_t q = 0; q < k; ++q) {
             const int32_t v = src[q];
-            bs_store<NARROW>(a, (size_t)v, q, 0u);
+            bs_store<BITS>(a, (size_t)v, q, 0u);
             a.nq[v] |= 1ull << q;
             a.nany[v] = 1;
         }
@@ -699,6 +929,7 @@ __global__ void bsssp_init(BsArgs a, const int32_t *src, int32_t k, uint32_t del
         ctl->split_kept = 0;
         ctl->split_min = 0xFFFFFFFFu;
         ctl->overflow = ctl->parity = ctl->err = ctl->splits = 0;
+        ctl->unfit = 0;
         ctl->relaxed = ctl->improvements = ctl->pair_entries = ctl->lane_relaxed = 0ull;
         ctl->active = 0ull;
         ctl->dir = BS_PUSH;
@@ -709,8 +940,8 @@ __global__ void bsssp_init(BsArgs a, const int32_t *src, int32_t k, uint32_t del
 }
 
 // out[q][v] = D[v][q] for the queries q in `lanes`: 64 vertices x 64 queries
-// per tile through LDS (narrow rows widened, 0xFFFF -> 0xFFFFFFFF)
-template <bool NARROW>
+// per tile through LDS (narrow rows widened, unreached -> 0xFFFFFFFF)
+template <int BITS>
 __global__ __launch_bounds__(GFR_BLOCK) void bsssp_transpose(BsArgs a, int32_t n, unsigned long long lanes,
                                                              uint32_t *out)
 {
@@ -721,13 +952,33 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_transpose(BsArgs a, int32_t n
         __syncthreads();
         for (int i = threadIdx.x; i < 64 * 64; i += GFR_BLOCK) {
             const int r = i / 64, q = i % 64;
-            tile[r][q] = (v0 + r < n) ? bs_load<NARROW>(a, (size_t)(v0 + r), q) : 0u;
+            tile[r][q] = (v0 + r < n) ? bs_load<BITS>(a, (size_t)(v0 + r), q) : 0u;
         }
         __syncthreads();
         for (int i = threadIdx.x; i < 64 * 64; i += GFR_BLOCK) {
             const int q = i / 64, r = i % 64;
             if (((lanes >> q) & 1ull) && v0 + r < n) out[(size_t)q * n + v0 + r] = tile[r][q];
         }
+    }
+}
+
+// A relaxation whose sum does not fit below 0xFFFFFFFF is not applied; the
+// batch fails only if such a sum was a shortest distance: for some query in
+// `lanes`, a vertex left unreached next to a reached one.  Wave per vertex,
+// lane = query.
+__global__ __launch_bounds__(GFR_BLOCK) void bsssp_unfit_check(const int32_t *R, const int32_t *C, const uint32_t *D,
+                                                                int32_t n, unsigned long long lanes, uint32_t *flag)
+{
+    const int lane = lane_id();
+    const bool mine = (lanes >> lane) & 1ull;
+    const uint32_t waves = gridDim.x * GFR_WAVES;
+    for (uint32_t v = blockIdx.x * GFR_WAVES + threadIdx.x / 64; v < (uint32_t)n; v += waves) {
+        if (!mine || D[(size_t)v * 64 + lane] != BS_INF) continue;
+        for (int32_t e = R[v]; e < R[v + 1]; ++e)
+            if (D[(size_t)C[e] * 64 + lane] != BS_INF) {
+                *flag = 1u;
+                break;
+            }
     }
 }
 
@@ -742,7 +993,21 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     const uint32_t chunk = 1024;
     const uint32_t nwords = (uint32_t)(((int64_t)n + 63) / 64) * 2u;
     const size_t nparts = (size_t)(g.m / chunk) + 2;
-    const int G = grid_blocks(c, 7);   // the relax kernel fits seven work-groups per CU
+    // relax / pull grid per row width: the option's work-groups per CU (or as
+    // many as are resident at once), at most one per 1024-edge chunk of the
+    // whole graph.  Many more work-groups than fit at once let the hardware
+    // hand chunks of uneven cost to whichever CU frees first (R-MAT s22, 64
+    // queries: 35.5 ms per batch at 8 per CU, 32.9 at 16, 30.3 at 64).  G
+    // sizes the per-work-group partials.
+    const int bpc = c.opt.batch_blocks_per_cu;
+    const int gcap = (int)std::min<int64_t>(64ll * c.num_cu, std::max<int64_t>(c.num_cu, g.m / 1024 + 1));
+    auto grid_of = [&](const void *relax, const void *pull) {
+        return std::min(gcap, std::max(resident_grid(c, relax, bpc), resident_grid(c, pull, bpc)));
+    };
+    const int Gw[3] = {grid_of((const void *)bsssp_relax<1024, 8>, (const void *)bsssp_pull<1024, 8>),
+                       grid_of((const void *)bsssp_relax<1024, 16>, (const void *)bsssp_pull<1024, 16>),
+                       grid_of((const void *)bsssp_relax<1024, 32>, (const void *)bsssp_pull<1024, 32>)};
+    const int G = std::max(Gw[0], std::max(Gw[1], Gw[2]));
     const CompactGeom cg = compact_geom(nwords, c.num_cu);
     // one shared bucket serves all queries; a narrow bucket desynchronises the
     // queries' frontiers and multiplies edge visits, so the default is a
@@ -755,6 +1020,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
                     3 * al256(4ull * n) + al256(4 * nparts) + al256(16ull * G) + al256(16ull * cg.blocks) +
                     al256(sizeof(BsCtl)) + al256(4 * 64) + al256(8ull * cg.blocks) + al256(4ull * nwords));
     BsArgs a;
+    memset(&a, 0, sizeof a);   // padding too: the bytes key the captured steps
     a.R = g.R.as<int32_t>();
     a.C = g.C.as<int32_t>();
     a.W = g.W.as<uint32_t>();
@@ -762,6 +1028,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     a.nwords = nwords;
     a.D = c.arena.take<uint32_t>(64ull * n);
     a.D16 = (uint16_t *)a.D;
+    a.D8 = (uint8_t *)a.D;
     a.qm = c.arena.take<unsigned long long>(n);
     a.nq = c.arena.take<unsigned long long>(n);
     a.fq = c.arena.take<unsigned long long>(n);
@@ -780,17 +1047,24 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     a.full = g.full;
     a.full_nf = (uint32_t)g.full_nf;
     a.full_mf = (uint32_t)g.m;
-    double iters = 0, relaxed = 0, imps = 0, pulls = 0, lanes = 0, pairs = 0, fallbacks = 0, narrow_batches = 0;
+    double iters = 0, relaxed = 0, imps = 0, pulls = 0, lanes = 0, pairs = 0, fallbacks = 0;
+    double batches8 = 0, batches16 = 0;
     // narrow rows first (option batch.narrow: 0 never, 1 auto, 2 always
-    // tried first); auto skips them on mesh-class graphs, whose long paths
-    // outgrow 16 bits, and on graphs where a batch has overflowed them before
+    // tried first from 16 bits, 3 always tried first from 8 bits); auto skips
+    // them on mesh-class graphs, whose long paths outgrow them, and starts a
+    // graph at the narrowest width no batch on it has outgrown
     const int nopt = c.opt.batch_narrow;
-    bool narrow = nopt == 2 || (nopt == 1 && g.cls == GRAPH_SCALEFREE && !g.narrow_overflowed.load());
+    int bits = 32;
+    if (nopt == 3) bits = 8;
+    else if (nopt == 2) bits = 16;
+    else if (nopt == 1 && g.cls == GRAPH_SCALEFREE) bits = std::max(8, g.row_bits_min.load());
+    const float pull_alpha = (float)c.opt.batch_pull_alpha;
+    const bool pair = c.opt.batch_pair != 0;   // 32-bit rows: two edges per row instruction
     for (int32_t g0 = 0; g0 < k; g0 += 64) {
         const int32_t kk = std::min<int32_t>(64, k - g0);
         BsCtl h;
         for (;;) {
-            fill_u32(a.D, 0xFFFFFFFFu, (narrow ? 32ull : 64ull) * n, s);
+            fill_u32(a.D, 0xFFFFFFFFu, 2ull * bits * n, s);   // 8 * bits bytes per vertex
             fill_u32(a.nq, 0u, 2ull * n, s);
             fill_u32(a.fq, 0u, 2ull * n, s);
             fill_u32(a.nany, 0u, 8ull * nwords, s);
@@ -798,60 +1072,88 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
             fill_u32(a.part, 0u, 4ull * G, s);
             fill_u32(status, 0u, 4ull * cg.blocks, s);
             GFR_HIP(hipMemcpyAsync(dsrc, sources + g0, 4ull * kk, hipMemcpyHostToDevice, s));
-            if (narrow)
-                hipLaunchKernelGGL(bsssp_init<true>, dim3(1), dim3(64), 0, s, a, dsrc, kk, delta,
-                                   (float)c.opt.batch_pull_alpha);
-            else
-                hipLaunchKernelGGL(bsssp_init<false>, dim3(1), dim3(64), 0, s, a, dsrc, kk, delta,
-                                   (float)c.opt.batch_pull_alpha);
+            auto by_width = [&](auto f) {
+                if (bits == 8) f(std::integral_constant<int, 8>());
+                else if (bits == 16) f(std::integral_constant<int, 16>());
+                else f(std::integral_constant<int, 32>());
+            };
+            by_width([&](auto B) {
+                hipLaunchKernelGGL(bsssp_init<decltype(B)::value>, dim3(1), dim3(64), 0, s, a, dsrc, kk, delta,
+                                   pull_alpha);
+            });
             auto compact = [&]() {
                 c.ktimer.run("bsssp_compact", s, [&]() {
-                    if (narrow)
-                        hipLaunchKernelGGL(compact_kernel<BsMarks<true>>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R,
-                                           n, nwords, cg.wpt, BsMarks<true>{a, (uint32_t)G, cg.blocks}, a.q, chunk,
+                    by_width([&](auto B) {
+                        constexpr int W = decltype(B)::value;
+                        hipLaunchKernelGGL(compact_kernel<BsMarks<W>>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R,
+                                           n, nwords, cg.wpt, BsMarks<W>{a, (uint32_t)G, cg.blocks}, a.q, chunk,
                                            status, &a.ctl->parity, &a.ctl->err);
-                    else
-                        hipLaunchKernelGGL(compact_kernel<BsMarks<false>>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s,
-                                           a.R, n, nwords, cg.wpt, BsMarks<false>{a, (uint32_t)G, cg.blocks}, a.q,
-                                           chunk, status, &a.ctl->parity, &a.ctl->err);
+                    });
                 });
             };
             compact();   // queue of the sources
             GFR_LAUNCH_CHECK();
             auto launch = [&]() {
+                const int Gb = Gw[bits == 8 ? 0 : bits == 16 ? 1 : 2];
                 c.ktimer.run("bsssp_relax", s, [&]() {
-                    if (narrow) hipLaunchKernelGGL((bsssp_relax<1024, true>), dim3(G), dim3(GFR_BLOCK), 0, s, a);
-                    else hipLaunchKernelGGL((bsssp_relax<1024, false>), dim3(G), dim3(GFR_BLOCK), 0, s, a);
+                    if (bits == 32 && pair)
+                        hipLaunchKernelGGL(bsssp_relax2<1024>, dim3(Gb), dim3(GFR_BLOCK), 0, s, a);
+                    else
+                        by_width([&](auto B) {
+                            hipLaunchKernelGGL((bsssp_relax<1024, decltype(B)::value>), dim3(Gb), dim3(GFR_BLOCK), 0,
+                                               s, a);
+                        });
                 });
                 c.ktimer.run("bsssp_pull", s, [&]() {
-                    if (narrow) hipLaunchKernelGGL((bsssp_pull<1024, true>), dim3(G), dim3(GFR_BLOCK), 0, s, a);
-                    else hipLaunchKernelGGL((bsssp_pull<1024, false>), dim3(G), dim3(GFR_BLOCK), 0, s, a);
+                    by_width([&](auto B) {
+                        hipLaunchKernelGGL((bsssp_pull<1024, decltype(B)::value>), dim3(Gb), dim3(GFR_BLOCK), 0, s,
+                                           a);
+                    });
                 });
                 compact();
             };
-            run_until_done(c, &a.ctl->mode, BS_DONE, g.iter_hint() + 1, 64ll * n + 1024, s, launch);
+            StepKey key("bsssp");
+            key.add(a).add(G).add(Gw).add(cg).add(chunk).add(status).add(bits).add(pair);
+            run_until_done(c, &a.ctl->mode, BS_DONE, g.iter_hint() + 1, 64ll * n + 1024, s, launch, &key);
             GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(BsCtl), hipMemcpyDeviceToHost, s));
             GFR_HIP(hipStreamSynchronize(s));
             memcpy(&h, c.pinned, sizeof(BsCtl));
             if (h.err) fail(GFR_E_DEVICE, "sssp_batch: frontier compaction look-back timed out");
-            if (narrow && h.overflow) {
-                // a distance outgrew the narrow rows: this batch again, wide
-                narrow = false;
-                g.narrow_overflowed.store(true);
+            if (bits < 32 && h.overflow) {
+                // a distance outgrew the narrow rows: this batch again, twice as wide
+                bits *= 2;
+                int cur = g.row_bits_min.load();
+                while (cur < bits && !g.row_bits_min.compare_exchange_weak(cur, bits)) {
+                }
                 fallbacks += 1;
                 continue;
             }
             break;
         }
-        if (h.overflow) fail(GFR_E_INVALID, "sssp_batch: a path weight does not fit below 0xFFFFFFFF");
-        if (narrow)
-            hipLaunchKernelGGL(bsssp_transpose<true>, dim3(G), dim3(GFR_BLOCK), 0, s, a, n,
-                               kk == 64 ? ~0ull : ((1ull << kk) - 1ull), dist + (size_t)g0 * n);
+        const unsigned long long lanes_mask = kk == 64 ? ~0ull : ((1ull << kk) - 1ull);
+        if (h.unfit) {
+            // 32-bit rows (narrow batches fall back instead): was an unfit sum a distance?
+            fill_u32(a.part, 0u, 1, s);
+            hipLaunchKernelGGL(bsssp_unfit_check, dim3(G), dim3(GFR_BLOCK), 0, s, a.R, a.C, a.D, n, lanes_mask,
+                               a.part);
+            GFR_LAUNCH_CHECK();
+            GFR_HIP(hipMemcpyAsync(c.pinned, a.part, 4, hipMemcpyDeviceToHost, s));
+            GFR_HIP(hipStreamSynchronize(s));
+            if (*(volatile uint32_t *)c.pinned)
+                fail(GFR_E_INVALID, "sssp_batch: a distance does not fit below 0xFFFFFFFF");
+        }
+                if (bits == 8)
+            hipLaunchKernelGGL(bsssp_transpose<8>, dim3(G), dim3(GFR_BLOCK), 0, s, a, n, lanes_mask,
+                               dist + (size_t)g0 * n);
+        else if (bits == 16)
+            hipLaunchKernelGGL(bsssp_transpose<16>, dim3(G), dim3(GFR_BLOCK), 0, s, a, n, lanes_mask,
+                               dist + (size_t)g0 * n);
         else
-            hipLaunchKernelGGL(bsssp_transpose<false>, dim3(G), dim3(GFR_BLOCK), 0, s, a, n,
-                               kk == 64 ? ~0ull : ((1ull << kk) - 1ull), dist + (size_t)g0 * n);
+            hipLaunchKernelGGL(bsssp_transpose<32>, dim3(G), dim3(GFR_BLOCK), 0, s, a, n, lanes_mask,
+                               dist + (size_t)g0 * n);
         GFR_LAUNCH_CHECK();
-        narrow_batches += narrow ? 1 : 0;
+        batches8 += bits == 8 ? 1 : 0;
+        batches16 += bits == 16 ? 1 : 0;
         iters += h.iter;
         relaxed += (double)h.relaxed;
         imps += (double)h.improvements;
@@ -859,8 +1161,10 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
         lanes += (double)h.lane_relaxed;
         pairs += (double)h.pair_entries;
     }
-    c.stats.v["narrow_batches"] += narrow_batches;   // batches solved with 16-bit rows
-    c.stats.v["narrow_fallbacks"] += fallbacks;      // batches solved again with 32-bit rows
+    c.stats.v["narrow_batches"] += batches8 + batches16;   // batches finished with 8- or 16-bit rows
+    c.stats.v["batches_8bit"] += batches8;
+    c.stats.v["batches_16bit"] += batches16;
+    c.stats.v["narrow_fallbacks"] += fallbacks;            // batches solved again with wider rows
     c.stats.v["iterations"] += iters;
     c.stats.v["relaxations"] += relaxed;   // edge visits, each serving up to 64 queries
     c.stats.v["lane_relaxations"] += lanes;   // (edge, query) relaxations
@@ -914,6 +1218,7 @@ __global__ void bs_session_init(BsArgs a, float pull_alpha)
     ctl->split_kept = 0;
     ctl->split_min = 0xFFFFFFFFu;
     ctl->overflow = ctl->parity = ctl->err = ctl->splits = 0;
+    ctl->unfit = 0;
     ctl->relaxed = ctl->improvements = ctl->pair_entries = ctl->lane_relaxed = 0ull;
     ctl->active = 0ull;
     ctl->dir = BS_PUSH;
@@ -984,7 +1289,8 @@ struct BsSession final : LaneSession {
         a.n = g.n;
         a.nwords = nwords;
         a.D = (uint32_t *)take(256 * L.n);
-        a.D16 = nullptr;   // sessions keep wide rows (lanes join at different times; no batch to solve again)
+        a.D16 = nullptr;   // sessions keep 32-bit rows (lanes join at different times; no batch to solve again)
+        a.D8 = nullptr;
         a.qm = (unsigned long long *)take(8 * L.n);
         a.nq = (unsigned long long *)take(8 * L.n);
         a.fq = (unsigned long long *)take(8 * L.n);
@@ -1040,10 +1346,10 @@ struct BsSession final : LaneSession {
     void release(unsigned long long) override {}   // a finished lane has no queued pairs left
     void enqueue_step() override
     {
-        hipLaunchKernelGGL((bsssp_relax<1024, false>), dim3(G), dim3(GFR_BLOCK), 0, stream, a);
-        hipLaunchKernelGGL((bsssp_pull<1024, false>), dim3(G), dim3(GFR_BLOCK), 0, stream, a);
-        hipLaunchKernelGGL(compact_kernel<BsMarks<false>>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, stream, a.R, a.n,
-                           nwords, cg.wpt, BsMarks<false>{a, (uint32_t)G, cg.blocks}, a.q, 1024u, status,
+        hipLaunchKernelGGL((bsssp_relax<1024, 32>), dim3(G), dim3(GFR_BLOCK), 0, stream, a);
+        hipLaunchKernelGGL((bsssp_pull<1024, 32>), dim3(G), dim3(GFR_BLOCK), 0, stream, a);
+        hipLaunchKernelGGL(compact_kernel<BsMarks<32>>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, stream, a.R, a.n,
+                           nwords, cg.wpt, BsMarks<32>{a, (uint32_t)G, cg.blocks}, a.q, 1024u, status,
                            &a.ctl->parity, &a.ctl->err);
         GFR_LAUNCH_CHECK();
         GFR_HIP(hipMemcpyAsync(pin, a.ctl, sizeof(BsCtl), hipMemcpyDeviceToHost, stream));
@@ -1055,7 +1361,8 @@ struct BsSession final : LaneSession {
             msg = "sssp query: frontier compaction look-back timed out";
             return GFR_E_DEVICE;
         }
-        if (pin->overflow) {
+        if (pin->overflow || pin->unfit) {
+            // a session has no per-lane check: a sum past 32 bits fails its queries
             msg = "sssp query: a path weight does not fit below 0xFFFFFFFF";
             return GFR_E_INVALID;
         }
@@ -1064,7 +1371,7 @@ struct BsSession final : LaneSession {
     void extract(unsigned long long lanes) override
     {
         if (!lanes) return;
-        hipLaunchKernelGGL(bsssp_transpose<false>, dim3(G), dim3(GFR_BLOCK), 0, stream, a, a.n, lanes,
+        hipLaunchKernelGGL(bsssp_transpose<32>, dim3(G), dim3(GFR_BLOCK), 0, stream, a, a.n, lanes,
                            (uint32_t *)stage);
         GFR_LAUNCH_CHECK();
     }

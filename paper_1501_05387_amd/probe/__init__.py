@@ -3,7 +3,7 @@
 Measures the rates that bound the engine's kernels: random 4- and 8-byte
 gathers and 4-byte atomics over tables sized like the traversal state
 (0.5 MB: an R-MAT s22 bitmap, L2-resident; 16.8 MB: a distance array, inside
-the 256 MB MALL; 513 MB: a column array, HBM), random distance rows of 128 and
+the 256 MB MALL; 513 MB: a column array, HBM), random distance rows of 64, 128 and
 256 bytes read one wave per row (with and without an atomicMin on every
 word; 128-byte rows also as 64 lanes x 2 bytes and two rows per wave
 instruction), and a stream copy.  ``python -m paper_1501_05387_amd.probe --out F``
@@ -21,7 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgfrprobe.so")
 
 KINDS = {"gather4": 0, "gather8": 1, "atomic4": 2, "row256": 3, "row256_atomic": 4, "row128": 5,
-         "row128_atomic": 6, "copy": 7, "row128_u16": 8, "row128_pair": 9}
+         "row128_atomic": 6, "copy": 7, "row128_u16": 8, "row128_pair": 9, "row64": 10,
+         "row64_u8": 11, "row64_quad": 12, "row64_quad_atomic1": 13, "row256_pair": 14}
 
 MB = 1 << 20
 # (name, kind, table bytes, operations)
@@ -39,6 +40,13 @@ CASES = [
     ("row128_atomic 512MB", "row128_atomic", 512 * MB, 1 << 25),
     ("row128_u16 512MB", "row128_u16", 512 * MB, 1 << 25),
     ("row128_pair 512MB", "row128_pair", 512 * MB, 1 << 25),
+    ("row64 256MB", "row64", 256 * MB, 1 << 25),
+    ("row64_u8 256MB", "row64_u8", 256 * MB, 1 << 25),
+    ("row64_u8 1GB", "row64_u8", 1024 * MB, 1 << 25),
+    ("row64_quad 256MB", "row64_quad", 256 * MB, 1 << 26),
+    ("row64_quad 1GB", "row64_quad", 1024 * MB, 1 << 26),
+    ("row64_quad_atomic1 256MB", "row64_quad_atomic1", 256 * MB, 1 << 26),
+    ("row256_pair 1GB", "row256_pair", 1024 * MB, 1 << 25),
     ("copy 1GB", "copy", 1024 * MB, 0),
 ]
 
@@ -65,7 +73,9 @@ def run(cases=CASES):
         else:
             rate = count / (ms * 1e-3) / 1e9
             per = {"gather4": 4, "gather8": 8, "atomic4": 4, "row256": 256, "row256_atomic": 256,
-                   "row128": 128, "row128_atomic": 128, "row128_u16": 128, "row128_pair": 128}[kind]
+                   "row128": 128, "row128_atomic": 128, "row128_u16": 128, "row128_pair": 128,
+                   "row64": 64, "row64_u8": 64, "row64_quad": 64, "row64_quad_atomic1": 64,
+                   "row256_pair": 256}[kind]
             unit = "G rows/s" if kind.startswith("row") else "G ops/s"
             gbs = rate * per
         rec = {"case": name, "kind": kind, "table_bytes": nbytes, "ops": count, "ms": round(ms, 4),

@@ -1,7 +1,7 @@
 // probe.hip -- memory-rate microbenchmarks that bound the engine's kernels
 // on one MI355X: random 4- and 8-byte gathers and 4-byte atomics over tables
 // sized like the traversal state (L2-, MALL- and HBM-resident), random
-// distance rows of 128 and 256 bytes (one wave per row, as the batched
+// distance rows of 64, 128 and 256 bytes (one wave per row, as the batched
 // relaxation reads them), and a stream copy.  Not part of the engine ABI:
 // a measurement tool driven by the package's probe module.
 //
@@ -89,6 +89,23 @@ __global__ void k_rows16(const uint16_t *t, uint64_t rows, uint64_t count, uint3
     if (acc == 0x9e3779b9u) sink[0] = acc;
 }
 
+// 64-byte rows read as 64 lanes x 1 byte (one row per wave instruction)
+__global__ void k_rows8(const uint8_t *t, uint64_t rows, uint64_t count, uint32_t *sink)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    uint32_t acc = 0;
+    for (uint64_t i0 = wave * 16; i0 < count; i0 += waves * 16) {
+        uint32_t v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = (i0 + j < count) ? t[(uint64_t)(mix32(i0 + j) % rows) * 64 + lane] : 0u;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc += v[j];
+    }
+    if (acc == 0x9e3779b9u) sink[0] = acc;
+}
+
 // 128-byte rows read two per wave instruction: lanes 0-31 take one row as
 // 32 words, lanes 32-63 the next
 __global__ void k_rows_pair(const uint32_t *t, uint64_t rows, uint64_t count, uint32_t *sink)
@@ -108,6 +125,54 @@ __global__ void k_rows_pair(const uint32_t *t, uint64_t rows, uint64_t count, ui
         for (int j = 0; j < 8; ++j) acc += v[j];
     }
     if (acc == 0x9e3779b9u) sink[0] = acc;
+}
+
+// 64-byte rows read four per wave instruction: lanes 16k..16k+15 take row k
+// as 16 words; with `amin`, the first lane of each quarter also lowers one
+// word of its row (one scattered atomic per row)
+__global__ void k_rows_quad(uint32_t *t, uint64_t rows, uint64_t count, int amin, uint32_t *sink)
+{
+    const int lane = threadIdx.x & 63, quarter = lane >> 4, w = lane & 15;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    uint32_t acc = 0;
+    for (uint64_t i0 = wave * 32; i0 < count; i0 += waves * 32) {
+        uint32_t v[8];
+        uint64_t r[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint64_t i = i0 + 4 * j + quarter;
+            r[j] = mix32(i) % rows;
+            v[j] = (i < count) ? t[r[j] * 16 + w] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            acc += v[j];
+            if (amin && w == 0 && i0 + 4 * j + quarter < count) atomicMin(t + r[j] * 16 + (v[j] & 15u), v[j] >> 1);
+        }
+    }
+    if (acc == 0x9e3779b9u) sink[0] = acc;
+}
+
+// 256-byte rows read two per wave instruction: lanes 0-31 take one row as 32
+// 8-byte words, lanes 32-63 the next
+__global__ void k_rows256_pair(const unsigned long long *t, uint64_t rows, uint64_t count, uint32_t *sink)
+{
+    const int lane = threadIdx.x & 63, half = lane >> 5, w = lane & 31;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    unsigned long long acc = 0;
+    for (uint64_t i0 = wave * 16; i0 < count; i0 += waves * 16) {
+        unsigned long long v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint64_t i = i0 + 2 * j + half;
+            v[j] = (i < count) ? t[(uint64_t)(mix32(i) % rows) * 32 + w] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc += v[j];
+    }
+    if (acc == 0x9e3779b97f4a7c15ull) sink[0] = (uint32_t)acc;
 }
 
 __global__ void k_copy(const uint4 *a, uint4 *b, uint64_t n16)
@@ -171,10 +236,15 @@ float probe_run(int kind, uint64_t bytes, uint64_t count)
         case 7: hipLaunchKernelGGL(k_copy, dim3(G), dim3(256), 0, 0, (const uint4 *)t, (uint4 *)u, bytes / 16); break;
         case 8: hipLaunchKernelGGL(k_rows16, dim3(G), dim3(256), 0, 0, (const uint16_t *)t, bytes / 128, count, sink); break;
         case 9: hipLaunchKernelGGL(k_rows_pair, dim3(G), dim3(256), 0, 0, (const uint32_t *)t, bytes / 128, count, sink); break;
+        case 10: hipLaunchKernelGGL(k_rows<16>, dim3(G), dim3(256), 0, 0, (uint32_t *)t, bytes / 64, count, 0, sink); break;
+        case 11: hipLaunchKernelGGL(k_rows8, dim3(G), dim3(256), 0, 0, (const uint8_t *)t, bytes / 64, count, sink); break;
+        case 12: hipLaunchKernelGGL(k_rows_quad, dim3(G), dim3(256), 0, 0, (uint32_t *)t, bytes / 64, count, 0, sink); break;
+        case 13: hipLaunchKernelGGL(k_rows_quad, dim3(G), dim3(256), 0, 0, (uint32_t *)t, bytes / 64, count, 1, sink); break;
+        case 14: hipLaunchKernelGGL(k_rows256_pair, dim3(G), dim3(256), 0, 0, (const unsigned long long *)t, bytes / 256, count, sink); break;
         default: break;
         }
     };
-    if (kind >= 0 && kind <= 9) {
+    if (kind >= 0 && kind <= 14) {
         launch();   // warm-up (and first touch of the tables)
         (void)hipEventRecord(e0, 0);
         launch();

@@ -153,18 +153,24 @@ def test_bfs_host_output_and_stats(ctx):
 # ------------------------------------------------------------------- SSSP
 @pytest.mark.parametrize("name", list(GRAPHS))
 @pytest.mark.parametrize("delta", [0, 1, 7, 100000])
-def test_sssp_matches_oracle(ctx, name, delta):
+@pytest.mark.parametrize("frontier", [1, 2])
+def test_sssp_matches_oracle(ctx, name, delta, frontier):
+    """Queue iterations (advance + compaction) and mark-byte iterations (one
+    launch each, near/far sets as bytes) give the oracle's distances on every
+    graph, for bucket widths from 1 (many splits) to one bucket."""
     row, col, w = graph(name)
     g = _load(ctx, row, col, w)
     ctx.set_option("sssp.delta", delta)
+    ctx.set_option("sssp.frontier", frontier)
     try:
         for s in _sources(row, col, 4):
-            _say("sssp", name, "delta", delta, "src", s)
+            _say("sssp", name, "delta", delta, "frontier", frontier, "src", s)
             got = _host(ctx.sssp(g, s)).view(np.uint32)
             want = oracle.sssp(row, col, w, s)
-            assert np.array_equal(got, want), (name, delta, s, int(np.sum(got != want)))
+            assert np.array_equal(got, want), (name, delta, frontier, s, int(np.sum(got != want)))
     finally:
         ctx.set_option("sssp.delta", 0)
+        ctx.set_option("sssp.frontier", 0)
         g.free()
 
 
@@ -182,7 +188,8 @@ def test_sssp_chunks(ctx):
         g.free()
 
 
-def test_sssp_rejects_unweighted_and_overflow(ctx):
+@pytest.mark.parametrize("frontier", [1, 2])
+def test_sssp_rejects_unweighted_and_overflow(ctx, frontier):
     import paper_1501_05387_amd as gfr
     row, col = _path(10)
     g = _load(ctx, row, col)
@@ -191,10 +198,35 @@ def test_sssp_rejects_unweighted_and_overflow(ctx):
     g.free()
     w = np.full(col.size, 0x7FFFFFFF, np.uint32)
     g = _load(ctx, row, col, w)
-    with pytest.raises(gfr.GfrError) as ei:
-        ctx.sssp(g, 0)
-    assert ei.value.status == gfr.GFR_E_INVALID
-    g.free()
+    ctx.set_option("sssp.frontier", frontier)
+    try:
+        with pytest.raises(gfr.GfrError) as ei:
+            ctx.sssp(g, 0)
+        assert ei.value.status == gfr.GFR_E_INVALID
+        # the largest distance that fits: 0x7FFFFFFF + 0x7FFFFFFF = 0xFFFFFFFE on a 3-vertex path (the
+        # relaxation back from the far end sums past 32 bits and is not an improvement)
+        row3, col3 = _path(3)
+        w3 = np.full(col3.size, 0x7FFFFFFF, np.uint32)
+        g3 = _load(ctx, row3, col3, w3)
+        got = _host(ctx.sssp(g3, 0)).view(np.uint32)
+        assert got.tolist() == [0, 0x7FFFFFFF, 0xFFFFFFFE] == oracle.sssp(row3, col3, w3, 0).tolist()
+        # batched, with 32-bit rows and with narrow rows tried first
+        ctx.set_option("batch.min_sssp", 1)
+        for narrow in (0, 3):
+            ctx.set_option("batch.narrow", narrow)
+            src = np.array([0, 2, 1], np.int32)
+            b = _host(ctx.sssp_batch(g3, src)).view(np.uint32).reshape(3, 3)
+            for i in range(3):
+                assert np.array_equal(b[i], oracle.sssp(row3, col3, w3, int(src[i]))), (narrow, i)
+            with pytest.raises(gfr.GfrError) as ei:
+                ctx.sssp_batch(g, np.array([0, 9], np.int32))
+            assert ei.value.status == gfr.GFR_E_INVALID
+        g3.free()
+    finally:
+        ctx.set_option("sssp.frontier", 0)
+        ctx.set_option("batch.min_sssp", 24)
+        ctx.set_option("batch.narrow", 0)
+        g.free()
 
 
 # ----------------------------------------------------------- predecessors
@@ -440,6 +472,82 @@ def test_sssp_batch_buckets(ctx, delta):
         g.free()
 
 
+@pytest.mark.parametrize("name", ["rmat16", "grid96", "star5000", "path3000", "forest"])
+@pytest.mark.parametrize("delta", [0, 50])
+def test_sssp_batch_pair_kernel(ctx, name, delta):
+    """32-bit rows relaxed two edges per row load (batch.pair 1: each half-wave
+    one edge, two queries per lane) and one edge per load (batch.pair 0) give
+    the oracle's distances on every row, with one bucket and with narrow
+    buckets (far marks); 70 queries make a full and a ragged batch, and a hub
+    (the star's centre) exercises groups that leave one vertex."""
+    row, col, w = graph(name)
+    n = row.size - 1
+    rng = np.random.default_rng(11)
+    src = rng.integers(0, n, size=70).astype(np.int32)
+    src[0] = 0
+    src[5] = src[6]
+    g = _load(ctx, row, col, w)
+    ctx.set_option("batch.min_sssp", 1)
+    ctx.set_option("batch.delta", delta)
+    try:
+        ref = [oracle.sssp(row, col, w, int(x)) for x in src]
+        outs = []
+        for pair in (1, 0):
+            ctx.set_option("batch.pair", pair)
+            _say("sssp_batch pair", pair, name, "delta", delta)
+            got = _host(ctx.sssp_batch(g, src)).view(np.uint32).reshape(src.size, n)
+            for i in range(src.size):
+                assert np.array_equal(got[i], ref[i]), (name, pair, delta, i)
+            outs.append(got)
+        assert np.array_equal(outs[0], outs[1])
+    finally:
+        ctx.set_option("batch.pair", 0)
+        ctx.set_option("batch.delta", 0)
+        ctx.set_option("batch.min_sssp", 24)
+        g.free()
+
+
+def test_step_graph_replays(ctx):
+    """graph.steps 1: the level loops replay captured hipGraphs of their level
+    launches.  Each solver runs four times into the same buffers (one capture,
+    then replays), with eager work and synchronisations between the calls;
+    every replay equals the plain launches and the oracle."""
+    import torch
+    row, col, w = graph("rmat16")
+    n = row.size - 1
+    srcs = graphgen.sample_sources(row, col, 64)
+    g = _load(ctx, row, col, w)
+    dev = "cuda:0"
+    outs = {"bfs": torch.empty(n, dtype=torch.int32, device=dev), "sssp": torch.empty(n, dtype=torch.int32, device=dev),
+            "bfs_batch": torch.empty(64 * n, dtype=torch.int32, device=dev),
+            "sssp_batch": torch.empty(64 * n, dtype=torch.int32, device=dev)}
+    calls = {"bfs": lambda o: ctx.bfs(g, int(srcs[0]), out=o), "sssp": lambda o: ctx.sssp(g, int(srcs[0]), out=o),
+             "bfs_batch": lambda o: ctx.bfs_batch(g, srcs, out=o), "sssp_batch": lambda o: ctx.sssp_batch(g, srcs, out=o)}
+    try:
+        ctx.set_option("graph.steps", 0)
+        plain = {}
+        for k, f in calls.items():
+            f(outs[k])
+            plain[k] = outs[k].clone()
+        assert np.array_equal(plain["bfs"].cpu().numpy(), oracle.bfs(row, col, int(srcs[0])))
+        assert np.array_equal(plain["sssp"].cpu().numpy().view(np.uint32), oracle.sssp(row, col, w, int(srcs[0])))
+        ctx.set_option("graph.steps", 1)
+        junk = torch.zeros(1 << 20, device=dev)
+        for rep in range(4):
+            for k, f in calls.items():
+                outs[k].fill_(-7)
+                junk.add_(1.0)   # eager work of the program between the replays
+                torch.cuda.synchronize()
+                f(outs[k])
+                replays = ctx.stat("graph_launches")
+                _say("step graphs", k, "call", rep, "graph launches", replays)
+                assert replays >= 1, k
+                assert torch.equal(outs[k], plain[k]), (k, rep)
+    finally:
+        ctx.set_option("graph.steps", 0)
+        g.free()
+
+
 @pytest.mark.parametrize("alpha", [1e-6, 24, 1e9])
 def test_bfs_batch_directions(ctx, alpha):
     row, col, _ = graph("rmat16")
@@ -568,12 +676,15 @@ def test_sssp_batch_pull_sweeps(ctx, name, alpha):
 
 
 @pytest.mark.parametrize("name", ["rmat16", "grid96", "path3000", "star5000"])
-@pytest.mark.parametrize("narrow", [0, 2])
+@pytest.mark.parametrize("narrow", [0, 2, 3])
 def test_sssp_batch_row_width(ctx, name, narrow):
-    """Batched SSSP with 32-bit distance rows (narrow 0) and with 16-bit rows
-    tried first (narrow 2) equals the oracle.  On the lattice (weights up to
-    1000) and the long path, distances outgrow 16 bits, the narrow attempt
-    overflows and the batch is solved again with wide rows."""
+    """Batched SSSP with 32-bit distance rows (narrow 0), with 16-bit rows
+    tried first (narrow 2) and with 8-bit rows tried first (narrow 3) equals
+    the oracle.  Where distances outgrow a width (the lattice's weights go up
+    to 1000, the long path), the attempt overflows and the batch is solved
+    again with rows twice as wide.  A tentative distance may outgrow a width
+    that the final ones fit, so a fallback is allowed there, never a narrower
+    finish than the final distances fit."""
     row, col, w = graph(name)
     n = row.size - 1
     rng = np.random.default_rng(5)
@@ -586,19 +697,55 @@ def test_sssp_batch_row_width(ctx, name, narrow):
     try:
         _say("sssp_batch row width", name, narrow)
         s = _host(ctx.sssp_batch(g, src)).view(np.uint32).reshape(src.size, n)
-        nb, fb = ctx.stat("narrow_batches"), ctx.stat("narrow_fallbacks")
+        b8, b16, fb = ctx.stat("batches_8bit"), ctx.stat("batches_16bit"), ctx.stat("narrow_fallbacks")
         ref = [oracle.sssp(row, col, w, int(x)) for x in src]
         for i in range(src.size):
             assert np.array_equal(s[i], ref[i]), (name, narrow, i)
         maxd = max(int(r[r != 0xFFFFFFFF].max()) for r in ref)
+        _say("max distance", maxd, "8-bit batches", b8, "16-bit batches", b16, "fallbacks", fb)
         if narrow == 0:
-            assert nb == 0 and fb == 0
-        elif maxd < 0xFFFF:
-            assert nb == 2 and fb == 0, (maxd, nb, fb)
+            assert b8 == 0 and b16 == 0 and fb == 0
+        elif narrow == 2:
+            assert b8 == 0
+            if maxd >= 0xFFFF:
+                assert b16 == 0 and fb >= 1
         else:
-            assert fb >= 1 and nb + fb >= 1, (maxd, nb, fb)
+            if maxd >= 0xFF:
+                assert b8 == 0 and fb >= 1
+            if maxd >= 0xFFFF:
+                assert b16 == 0 and fb >= 2
+        if narrow and maxd < 0xFF and name == "star5000":
+            # one path per vertex: tentative distances are final ones
+            assert fb == 0 and (b8 if narrow == 3 else b16) == 2
     finally:
-        ctx.set_option("batch.narrow", 1)
+        ctx.set_option("batch.narrow", 0)
+        ctx.set_option("batch.min_sssp", 24)
+        g.free()
+
+
+@pytest.mark.parametrize("second", [0x7F, 0x80, 0xFE])
+def test_sssp_batch_8bit_boundary(ctx, second):
+    """Path 0 - 1 - 2 with weights 0x7F and `second`: the far end sits at 0xFE
+    (the largest 8-bit distance), at 0xFF (does not fit: solved again with
+    16-bit rows) or at 0x17D; four queries share each 32-bit word of a row,
+    and every result equals the oracle."""
+    row = np.array([0, 1, 3, 4], np.int32)
+    col = np.array([1, 0, 2, 1], np.int32)
+    w = np.array([0x7F, 0x7F, second, second], np.uint32)
+    g = _load(ctx, row, col, w)
+    src = np.array([0, 2, 1, 0, 2, 2, 1, 0], np.int32)
+    ctx.set_option("batch.narrow", 3)
+    ctx.set_option("batch.min_sssp", 1)
+    try:
+        s = _host(ctx.sssp_batch(g, src)).view(np.uint32).reshape(src.size, 3)
+        for i in range(src.size):
+            assert np.array_equal(s[i], oracle.sssp(row, col, w, int(src[i]))), (second, i)
+        fits = 0x7F + second < 0xFF
+        assert ctx.stat("batches_8bit") == (1 if fits else 0)
+        assert ctx.stat("batches_16bit") == (0 if fits else 1)
+        assert ctx.stat("narrow_fallbacks") == (0 if fits else 1)
+    finally:
+        ctx.set_option("batch.narrow", 0)
         ctx.set_option("batch.min_sssp", 24)
         g.free()
 
@@ -623,6 +770,6 @@ def test_sssp_batch_narrow_boundary(ctx, second):
         assert ctx.stat("narrow_batches") == (1 if fits else 0)
         assert ctx.stat("narrow_fallbacks") == (0 if fits else 1)
     finally:
-        ctx.set_option("batch.narrow", 1)
+        ctx.set_option("batch.narrow", 0)
         ctx.set_option("batch.min_sssp", 24)
         g.free()
