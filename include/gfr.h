@@ -95,6 +95,10 @@ const char *gfr_last_error(const gfr_ctx *ctx);
  *   "bfs.frontier"    0 auto, 1 queue levels (advance + compaction), 2 mark-byte levels:
  *                     the frontier is a byte per vertex, one launch per level, push
  *                     only (auto: mark bytes on mesh-class graphs unless pull is forced)
+ *   "sssp.pull_alpha" single-source SSSP direction (the pull advance of Sec. 4.5 applied to
+ *                     SSSP): an iteration whose near queue carries more than m / alpha edges
+ *                     relaxes by a pull sweep over every list (one pre-checked atomicMin per
+ *                     vertex instead of per edge); 0 (default) = always push
  *   "sssp.frontier"   0 auto (= 1), 1 queue iterations (advance + compaction), 2 mark-byte
  *                     iterations: the near and far sets are bytes per vertex, one launch
  *                     per iteration
@@ -102,6 +106,11 @@ const char *gfr_last_error(const gfr_ctx *ctx);
  *                     0 = "sssp.delta_factor" (default 2) times the mean edge weight
  *   "advance.chunk"   edges per work-group chunk of the load-balanced advance (Sec. 4.4),
  *                     one of 256, 512, 1024, 2048, 4096
+ *   "advance.mapping" BFS push work mapping (Sec. 4.4): 1 (default) equal edge chunks
+ *                     (load-balanced partitioning); 2 per-vertex groups (lists of a work-group's
+ *                     size or more by the whole work-group, of 64 or more by a wave, the rest
+ *                     by one thread each); 0 the paper's hybrid: per-vertex groups while the
+ *                     frontier has fewer than "advance.twc_threshold" vertices (default 4096)
  *   "msbfs.alpha"     batched BFS: pull when the frontier's edges exceed m / alpha
  *   "batch.delta"     batched SSSP bucket width; 0 = "batch.delta_factor" times the
  *                     mean edge weight, where factor 0 (default) = a single bucket

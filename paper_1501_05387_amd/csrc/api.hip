@@ -347,6 +347,8 @@ static const OptKey kOptKeys[] = {
     {"batch.pull_alpha", 0, 1e6, true},  {"batch.narrow", 0, 3, true},
     {"batch.blocks_per_cu", 0, 64, true}, {"graph.steps", 0, 1, false},
     {"batch.pair", 0, 1, true},
+    {"advance.mapping", 0, 2, true},     {"advance.twc_threshold", 0, 2147483647.0, true},
+    {"sssp.pull_alpha", 0, 1e6, true},
     {"bc.direction", 0, 2, true},
     {"bc.alpha", 1e-6, 1e9, true},       {"bc.beta", 1e-6, 1e9, true},
     {"twohop.direction", 0, 2, true},    {"twohop.alpha", 1e-6, 1e9, true},
@@ -382,6 +384,9 @@ void option_set(Options &o, const std::string &key, double v)
     else if (key == "batch.blocks_per_cu") o.batch_blocks_per_cu = (int)v;
     else if (key == "graph.steps") o.step_graphs = (int)v;
     else if (key == "batch.pair") o.batch_pair = (int)v;
+    else if (key == "advance.mapping") o.advance_mapping = (int)v;
+    else if (key == "advance.twc_threshold") o.twc_threshold = (int)v;
+    else if (key == "sssp.pull_alpha") o.sssp_pull_alpha = v;
     else if (key == "batch.narrow") o.batch_narrow = (int)v;
     else if (key == "bc.direction") o.bc_direction = (int)v;
     else if (key == "bc.alpha") o.bc_alpha = v;
@@ -421,6 +426,9 @@ static double option_get(const Options &o, const std::string &key)
     if (key == "batch.blocks_per_cu") return o.batch_blocks_per_cu;
     if (key == "graph.steps") return o.step_graphs;
     if (key == "batch.pair") return o.batch_pair;
+    if (key == "advance.mapping") return o.advance_mapping;
+    if (key == "advance.twc_threshold") return o.twc_threshold;
+    if (key == "sssp.pull_alpha") return o.sssp_pull_alpha;
     if (key == "batch.narrow") return o.batch_narrow;
     if (key == "bc.direction") return o.bc_direction;
     if (key == "bc.alpha") return o.bc_alpha;

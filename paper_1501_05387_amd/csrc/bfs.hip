@@ -72,7 +72,92 @@ struct BfsArgs {
     FrontierQ q;
     uint32_t *part_insp;   // per work-group edges inspected by a pull level
     BfsCtl *ctl;
+    uint32_t mapping;        // push work mapping: 0 by frontier size, 1 edge chunks, 2 per-vertex groups
+    uint32_t twc_threshold;  // mapping 0: per-vertex groups below this many frontier vertices
 };
+
+// One push edge of BFS level L: test the visited bit, claim (or, idempotent,
+// just write) an unvisited target's depth and next-frontier mark.
+__device__ __forceinline__ void bfs_push_edge(const BfsArgs &a, int32_t v, int32_t L, bool idem)
+{
+    const uint32_t bit = 1u << (v & 31);
+    uint32_t *w = a.vis + (v >> 5);
+    if (!(*w & bit) && !a.mark[v]) {
+        if (idem || !(atomicOr(w, bit) & bit)) {
+            a.depth[v] = L + 1;
+            a.mark[v] = 1;
+        }
+    }
+}
+
+// The per-vertex mapping of Sec. 4.4 (per-CTA / per-warp coarse-grained,
+// then the fine-grained strategy for the rest): each work-group takes
+// GFR_BLOCK frontier vertices, one per thread.  Lists of at least GFR_BLOCK
+// edges are taken one at a time by the whole work-group (their owners compete
+// for it through an LDS word), then lists of at least 64 edges one at a time
+// by the owner's wave.  The remaining short lists are processed by the whole
+// work-group together: their sizes are scanned, the list offsets sit in LDS,
+// and each thread takes every GFR_BLOCK-th of their edges, finding its list
+// by binary search (the cooperative fine-grained form of Sec. 4.4).
+__device__ void bfs_push_twc(const BfsArgs &a, const FrontierQ &q, uint32_t nf, uint32_t mf, int32_t L, bool idem)
+{
+    __shared__ int32_t s_owner, s_row, s_deg;
+    __shared__ uint32_t s_soff[GFR_BLOCK + 1];
+    __shared__ int32_t s_srow[GFR_BLOCK];
+    __shared__ uint32_t s_wsum[GFR_WAVES];
+    const int lane = lane_id(), wave = threadIdx.x / 64;
+    for (uint32_t base = blockIdx.x * GFR_BLOCK; base < nf; base += gridDim.x * GFR_BLOCK) {
+        const uint32_t i = base + threadIdx.x;
+        int32_t row = 0, deg = 0;
+        if (i < nf) {
+            row = q.row[i];
+            deg = (int32_t)((i + 1 < nf ? q.off[i + 1] : mf) - q.off[i]);
+        }
+        for (;;) {   // work-group lists
+            if (threadIdx.x == 0) s_owner = -1;
+            __syncthreads();
+            if (deg >= GFR_BLOCK) s_owner = (int32_t)threadIdx.x;   // one of the writers wins
+            __syncthreads();
+            const int32_t owner = s_owner;
+            if (owner < 0) break;
+            if ((int32_t)threadIdx.x == owner) {
+                s_row = row;
+                s_deg = deg;
+                deg = 0;
+            }
+            __syncthreads();
+            const int32_t r0 = s_row, d0 = s_deg;
+            for (int32_t k = (int32_t)threadIdx.x; k < d0; k += GFR_BLOCK) bfs_push_edge(a, a.C[r0 + k], L, idem);
+            __syncthreads();   // s_row / s_deg are rewritten by the next owner
+        }
+        for (;;) {   // wave lists
+            const uint64_t want = ballot(deg >= 64);
+            if (!want) break;
+            const int src = __ffsll((unsigned long long)want) - 1;
+            const int32_t r0 = __builtin_amdgcn_readlane(row, src), d0 = __builtin_amdgcn_readlane(deg, src);
+            if (lane == src) deg = 0;
+            for (int32_t k = lane; k < d0; k += 64) bfs_push_edge(a, a.C[r0 + k], L, idem);
+        }
+        // short lists, the whole work-group over their concatenated edges
+        const uint32_t incl = wave_incl_scan((uint32_t)deg);
+        if (lane == 63) s_wsum[wave] = incl;
+        __syncthreads();
+        uint32_t wbase = 0, total = 0;
+        for (int k = 0; k < GFR_WAVES; ++k) {
+            if (k < wave) wbase += s_wsum[k];
+            total += s_wsum[k];
+        }
+        s_soff[threadIdx.x] = wbase + incl - (uint32_t)deg;
+        s_srow[threadIdx.x] = row;
+        if (threadIdx.x == 0) s_soff[GFR_BLOCK] = total;
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < total; e += GFR_BLOCK) {
+            const int j = upper_index(s_soff, 0, GFR_BLOCK - 1, e);   // lists of size 0 share offsets: the last wins
+            bfs_push_edge(a, a.C[s_srow[j] + (int32_t)(e - s_soff[j])], L, idem);
+        }
+        __syncthreads();   // LDS is reused by the next slice
+    }
+}
 
 template <int CH>
 __global__ __launch_bounds__(GFR_BLOCK) void bfs_level(BfsArgs a)
@@ -88,6 +173,12 @@ __global__ __launch_bounds__(GFR_BLOCK) void bfs_level(BfsArgs a)
         const uint32_t mf = ctl->mf, nf = ctl->nf;
         const bool idem = ctl->dedup != 0;
         const FrontierQ q = a.q;
+        // Sec. 4.4's hybrid: per-vertex groups for frontiers below the
+        // threshold, equal edge chunks (load-balanced partitioning) above it
+        if (a.mapping == 2 || (a.mapping == 0 && nf < a.twc_threshold)) {
+            bfs_push_twc(a, q, nf, mf, L, idem);
+            return;
+        }
         const uint32_t nchunks = (mf + CH - 1) / CH;
         for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
             const uint32_t e0 = c * CH;
@@ -101,19 +192,32 @@ __global__ __launch_bounds__(GFR_BLOCK) void bfs_level(BfsArgs a)
                 s_row[i] = q.row[s + i];
             }
             __syncthreads();
-#pragma unroll 2
-            for (uint32_t k = 0; k < (uint32_t)CH; k += GFR_BLOCK) {
-                const uint32_t e = e0 + k + threadIdx.x;
-                if (e < e1) {
-                    const int i = upper_index(s_off, 0, cnt - 1, e);
-                    const int32_t v = a.C[s_row[i] + (int32_t)(e - s_off[i])];
-                    const uint32_t bit = 1u << (v & 31);
-                    uint32_t *w = a.vis + (v >> 5);
-                    if (!(*w & bit) && !a.mark[v]) {
-                        if (idem || !(atomicOr(w, bit) & bit)) {
-                            a.depth[v] = L + 1;
-                            a.mark[v] = 1;
-                        }
+            // each thread takes every GFR_BLOCK-th edge of the chunk: all its
+            // column loads are issued first, then all visited-word probes,
+            // then the tests (an edge past the chunk end repeats the chunk's
+            // first edge and is masked)
+            constexpr int PER = CH / GFR_BLOCK;
+            int32_t vv[PER];
+            uint32_t vw[PER];
+            bool ok[PER];
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const uint32_t e = e0 + p * GFR_BLOCK + threadIdx.x;
+                ok[p] = e < e1;
+                const uint32_t ec = ok[p] ? e : e0;
+                const int i = upper_index(s_off, 0, cnt - 1, ec);
+                vv[p] = a.C[s_row[i] + (int32_t)(ec - s_off[i])];
+            }
+#pragma unroll
+            for (int p = 0; p < PER; ++p) vw[p] = a.vis[vv[p] >> 5];
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const int32_t v = vv[p];
+                const uint32_t bit = 1u << (v & 31);
+                if (ok[p] && !(vw[p] & bit) && !a.mark[v]) {
+                    if (idem || !(atomicOr(a.vis + (v >> 5), bit) & bit)) {
+                        a.depth[v] = L + 1;
+                        a.mark[v] = 1;
                     }
                 }
             }
@@ -431,6 +535,8 @@ void run_bfs(Ctx &c, Graph &g, int32_t src, int32_t *depth, hipStream_t s, Arena
     a.q.row = ar.take<int32_t>(n);
     a.q.part = ar.take<int32_t>(nparts);
     a.part_insp = ar.take<uint32_t>(G);
+    a.mapping = (uint32_t)c.opt.advance_mapping;
+    a.twc_threshold = (uint32_t)c.opt.twc_threshold;
     unsigned long long *status = ar.take<unsigned long long>(2ull * cg.blocks);
     a.ctl = ar.take<BfsCtl>(1);
 

@@ -141,9 +141,12 @@ struct Options {
     int bfs_dedup = 0;          // 0 atomic, 1 idempotent
     int bfs_frontier = 0;       // 0 auto (mark bytes on mesh-class graphs), 1 queue, 2 mark bytes
     int sssp_frontier = 0;      // 0 auto (queue iterations), 1 queue, 2 mark bytes
+    double sssp_pull_alpha = 0.0;   // single-source SSSP: pull sweep when the near queue's edges exceed m / alpha (0: never)
     double sssp_delta = 0.0;    // 0 -> sssp_delta_factor x mean edge weight
     double sssp_delta_factor = 2.0;
     int advance_chunk = 1024;
+    int advance_mapping = 1;    // push work mapping (Sec. 4.4): 0 by frontier size, 1 edge chunks, 2 per-vertex groups
+    int twc_threshold = 4096;   // mapping 0: per-vertex groups below this many frontier vertices
     double serve_budget = 32.0e9;
     int profile_kernels = 0;
     double msbfs_alpha = 4.0;   // batched BFS: pull when frontier edges > m / alpha

@@ -157,13 +157,28 @@ __global__ __launch_bounds__(GFR_BLOCK) void msbfs_level(MsArgs a)
                 s_acc[i] = 0ull;
             }
             __syncthreads();
-            for (uint32_t k = threadIdx.x; k < e1 - e0; k += GFR_BLOCK) {
-                const uint32_t e = e0 + k;
-                const int i = upper_index(s_off, 0, cnt - 1, e);
-                if (s_need[i]) {
-                    const unsigned long long f = a.fr[a.C[s_row[i] + (int32_t)(e - s_off[i])]] & s_need[i];
-                    if (f) atomicOr(s_acc + i, f);
-                }
+            // each thread takes every GFR_BLOCK-th edge of the chunk: the
+            // column loads of the edges whose vertex still needs a source are
+            // issued first, then their neighbours' mask loads, then the ORs
+            constexpr int PER = CH / GFR_BLOCK;
+            int ii[PER];
+            int32_t uu[PER];
+            unsigned long long ff[PER];
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const uint32_t k = p * GFR_BLOCK + threadIdx.x;
+                const bool ok = k < e1 - e0;
+                const uint32_t e = e0 + (ok ? k : 0u);
+                ii[p] = upper_index(s_off, 0, cnt - 1, e);
+                uu[p] = -1;
+                if (ok && s_need[ii[p]]) uu[p] = a.C[s_row[ii[p]] + (int32_t)(e - s_off[ii[p]])];
+            }
+#pragma unroll
+            for (int p = 0; p < PER; ++p) ff[p] = uu[p] >= 0 ? a.fr[uu[p]] : 0ull;
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const unsigned long long f = ff[p] & s_need[ii[p]];
+                if (f) atomicOr(s_acc + ii[p], f);
             }
             __syncthreads();
             for (int i = threadIdx.x; i < cnt; i += GFR_BLOCK)

@@ -41,7 +41,13 @@ struct SsspCtl {
     uint32_t splits;
     // traffic model counters
     unsigned long long near_entries, relaxed, improvements, far_entries;
+    uint32_t dir;                // SS_PUSH / SS_PULL for the next relaxation
+    float pull_alpha;            // pull when the near queue's edges exceed m / pull_alpha (0: never)
+    unsigned long long m;
+    uint32_t pull_iters, pad;
 };
+
+enum : uint32_t { SS_PUSH = 0, SS_PULL = 1 };
 
 struct SsspArgs {
     const int32_t *R;
@@ -55,13 +61,16 @@ struct SsspArgs {
     FrontierQ q;
     uint32_t *part;        // per work-group [improvements, far marks written]
     SsspCtl *ctl;
+    uint32_t *fbits;       // [nwords] bitmap of the near queue (written by the compaction)
+    FrontierQ full;        // every vertex with edges (pull sweeps)
+    uint32_t full_nf, full_mf;
 };
 
 template <int CH>
 __global__ __launch_bounds__(GFR_BLOCK) void sssp_relax(SsspArgs a)
 {
     SsspCtl *ctl = a.ctl;
-    if (ctl->mode != SS_RELAX) return;
+    if (ctl->mode != SS_RELAX || ctl->dir != SS_PUSH) return;
     const uint32_t hi = ctl->hi, nf = ctl->nf, mf = ctl->mf;
     const FrontierQ q = a.q;
     __shared__ uint32_t s_off[CH + 1];
@@ -144,6 +153,104 @@ __global__ __launch_bounds__(GFR_BLOCK) void sssp_relax(SsspArgs a)
     }
 }
 
+// Pull relaxation (Sec. 4.5's pull advance applied to SSSP, which the paper
+// leaves to future work): for near queues that carry most of the edges, a
+// load-balanced sweep over every vertex's list.  An edge (v, u) whose u is
+// in the near queue (bitmap) offers dist[u] + w to v; each wave forms the
+// minimum offer per owner v over its 64 edges with a segmented scan, and the
+// last lane of each owner's run lowers dist[v] once (pre-checked atomicMin)
+// and marks it near or far.  Sources outside the queue cost one bitmap probe.
+template <int CH>
+__global__ __launch_bounds__(GFR_BLOCK) void sssp_pull(SsspArgs a)
+{
+    SsspCtl *ctl = a.ctl;
+    if (ctl->mode != SS_RELAX || ctl->dir != SS_PULL) return;
+    const uint32_t hi = ctl->hi;
+    const FrontierQ q = a.full;
+    const uint32_t nf = a.full_nf, mf = a.full_mf;
+    __shared__ uint32_t s_off[CH + 1];
+    __shared__ int32_t s_row[CH + 1];
+    __shared__ int32_t s_v[CH + 1];
+    const int lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    constexpr uint32_t QW = CH / GFR_WAVES;
+    const uint32_t nchunks = (mf + CH - 1) / CH;
+    bool unf = false;
+    uint32_t nimp = 0, nfar = 0;
+    for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const uint32_t e0 = c * CH;
+        const uint32_t e1 = min(e0 + (uint32_t)CH, mf);
+        const int s = q.part[c];
+        const int t = (c + 1 < nchunks) ? q.part[c + 1] : (int)nf - 1;
+        const int cnt = t - s + 1;
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += GFR_BLOCK) {
+            s_off[i] = q.off[s + i];
+            s_row[i] = q.row[s + i];
+            s_v[i] = q.v[s + i];
+        }
+        __syncthreads();
+        const uint32_t eb = e0 + wave * QW, ee = min(eb + QW, e1);
+        if (eb >= ee) continue;
+        int ilo = upper_index(s_off, 0, cnt - 1, eb);
+        for (uint32_t e = eb; e < ee; e += 64) {
+            const int nb = (int)min(64u, ee - e);
+            int32_t v = -1;
+            uint32_t offer = 0xFFFFFFFFu;
+            int il = ilo;
+            if (lane < nb) {
+                const uint32_t el = e + lane;
+                il = upper_index(s_off, ilo, min(cnt - 1, ilo + lane + 1), el);
+                const int32_t idx = s_row[il] + (int32_t)(el - s_off[il]);
+                const int32_t u = a.C[idx];
+                v = s_v[il];
+                if ((a.fbits[u >> 5] >> (u & 31)) & 1u) {
+                    const unsigned long long s64 = (unsigned long long)a.dist[u] + a.W[idx];
+                    if (s64 < 0xFFFFFFFFull) offer = (uint32_t)s64;
+                    else unf = true;
+                }
+            }
+            ilo = __builtin_amdgcn_readlane(il, nb - 1);
+            // segmented minimum over runs of equal owners (lanes are in edge order)
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t o = (uint32_t)__shfl_up((int)offer, d, 64);
+                const int32_t ov = __shfl_up(v, d, 64);
+                if (lane >= d && ov == v) offer = min(offer, o);
+            }
+            const int32_t vnext = __shfl_down(v, 1, 64);
+            const bool last = lane < nb && (lane == nb - 1 || vnext != v);
+            if (last && offer != 0xFFFFFFFFu && offer < a.dist[v]) {
+                atomicMin(a.dist + v, offer);
+                ++nimp;
+                if (offer < hi) {
+                    a.near[v] = 1;
+                } else {
+                    a.far[v] = 1;
+                    ++nfar;
+                }
+            }
+        }
+    }
+    if (unf) ctl->unfit = 1u;
+    __shared__ uint32_t s_a[GFR_WAVES], s_b[GFR_WAVES];
+    nimp = wave_sum_u32(nimp);
+    nfar = wave_sum_u32(nfar);
+    if (lane == 0) {
+        s_a[wave] = nimp;
+        s_b[wave] = nfar;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t x = 0, y = 0;
+        for (int i = 0; i < GFR_WAVES; ++i) {
+            x += s_a[i];
+            y += s_b[i];
+        }
+        a.part[2 * blockIdx.x] = x;
+        a.part[2 * blockIdx.x + 1] = y;
+    }
+}
+
 struct SsspMarks {
     SsspArgs a;
     uint32_t nparts;   // work-groups of sssp_relax
@@ -159,12 +266,16 @@ struct SsspMarks {
         SsspCtl *ctl = a.ctl;
         if (ctl->mode == SS_RELAX) {   // consume the near marks
             const uint32_t m = marks_to_mask(a.near + 32ull * w);
+            a.fbits[w] = m;
             if (m) clear_marks(a.near + 32ull * w);
             return m;
         }
         // split the far marks with the new bucket [lo, hi)
         const uint32_t f = marks_to_mask(a.far + 32ull * w);
-        if (!f) return 0u;
+        if (!f) {
+            a.fbits[w] = 0u;
+            return 0u;
+        }
         const uint32_t lo = ctl->lo, hi = ctl->hi;
         uint32_t out = 0, bits = f;
         seen += __popc(f);
@@ -181,6 +292,7 @@ struct SsspMarks {
                 kmin = min(kmin, d);
             }
         }
+        a.fbits[w] = out;
         return out;
     }
 
@@ -240,7 +352,8 @@ struct SsspMarks {
         uint32_t split_min = 0xFFFFFFFFu;
         if (mode == SS_RELAX) {
             ctl->near_entries += ctl->nf;
-            ctl->relaxed += ctl->mf;
+            ctl->relaxed += ctl->dir == SS_PULL ? ctl->m : ctl->mf;
+            ctl->pull_iters += ctl->dir == SS_PULL ? 1u : 0u;
             ctl->improvements += imp;
             if (far) ctl->far_any = 1u;
         } else {
@@ -273,10 +386,12 @@ struct SsspMarks {
         ctl->iter += 1u;
         ctl->parity ^= 1u;
         ctl->mode = nm;
+        // a near queue carrying most of the edges is relaxed by a pull sweep
+        ctl->dir = (ctl->pull_alpha > 0.f && (double)mf2 * ctl->pull_alpha > (double)ctl->m) ? SS_PULL : SS_PUSH;
     }
 };
 
-__global__ void sssp_init(SsspArgs a, int32_t src, uint32_t chunk, uint32_t delta)
+__global__ void sssp_init(SsspArgs a, int32_t src, uint32_t chunk, uint32_t delta, float pull_alpha)
 {
     const int32_t rs = a.R[src], deg = a.R[src + 1] - rs;
     if (threadIdx.x == 0) {
@@ -300,8 +415,13 @@ __global__ void sssp_init(SsspArgs a, int32_t src, uint32_t chunk, uint32_t delt
         ctl->err = 0;
         ctl->splits = 0;
         ctl->near_entries = ctl->relaxed = ctl->improvements = ctl->far_entries = 0ull;
+        ctl->dir = SS_PUSH;
+        ctl->pull_alpha = pull_alpha;
+        ctl->m = (unsigned long long)a.R[a.n];
+        ctl->pull_iters = 0;
         ctl->mode = deg == 0 ? SS_DONE : SS_RELAX;
     }
+    // (the first iteration pushes; every compaction writes the near-queue bitmap a pull reads)
     for (uint32_t c = threadIdx.x; (uint64_t)c * chunk < (uint64_t)deg; c += blockDim.x) a.q.part[c] = 0;
 }
 
@@ -668,7 +788,7 @@ void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s)
     const int G = grid_blocks(c, 8);   // eight work-groups per CU fit at the default chunk
     const CompactGeom cg = compact_geom(nwords, c.num_cu);
     size_t need = 2 * al256(nwords * 32ull) + 3 * al256(4ull * n) + al256(4 * nparts) + al256(8ull * G) +
-                  al256(16ull * cg.blocks) + al256(sizeof(SsspCtl)) + al256(4);
+                  al256(16ull * cg.blocks) + al256(sizeof(SsspCtl)) + al256(4) + al256(4ull * nwords);
     c.arena.reserve(need);
     SsspArgs a;
     memset(&a, 0, sizeof a);   // padding too: the bytes key the captured steps
@@ -685,6 +805,10 @@ void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s)
     a.q.row = c.arena.take<int32_t>(n);
     a.q.part = c.arena.take<int32_t>(nparts);
     a.part = c.arena.take<uint32_t>(2ull * G);
+    a.fbits = c.arena.take<uint32_t>(nwords);
+    a.full = g.full;
+    a.full_nf = (uint32_t)g.full_nf;
+    a.full_mf = (uint32_t)g.m;
     unsigned long long *status = c.arena.take<unsigned long long>(2ull * cg.blocks);
     a.ctl = c.arena.take<SsspCtl>(1);
     uint32_t *unfit_flag = c.arena.take<uint32_t>(1);
@@ -693,10 +817,11 @@ void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s)
     fill_u32(a.near, 0u, 8ull * nwords, s);
     fill_u32(a.far, 0u, 8ull * nwords, s);
     fill_u32(status, 0u, 4ull * cg.blocks, s);
-    hipLaunchKernelGGL(sssp_init, dim3(1), dim3(GFR_BLOCK), 0, s, a, src, chunk, delta);
+    hipLaunchKernelGGL(sssp_init, dim3(1), dim3(GFR_BLOCK), 0, s, a, src, chunk, delta, (float)c.opt.sssp_pull_alpha);
     GFR_LAUNCH_CHECK();
 
     SsspMarks marks{a, (uint32_t)G};
+    const bool pull = c.opt.sssp_pull_alpha > 0;   // direction-optimizing iterations
     auto launch = [&]() {
         c.ktimer.run("sssp_relax", s, [&]() {
             switch (chunk) {
@@ -707,6 +832,10 @@ void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s)
             default: hipLaunchKernelGGL(sssp_relax<4096>, dim3(G), dim3(GFR_BLOCK), 0, s, a); break;
             }
         });
+        if (pull)
+            c.ktimer.run("sssp_pull", s, [&]() {
+                hipLaunchKernelGGL(sssp_pull<GATHER_CH>, dim3(G), dim3(GFR_BLOCK), 0, s, a);
+            });
         c.ktimer.run("sssp_compact", s, [&]() {
             hipLaunchKernelGGL(compact_kernel<SsspMarks>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R, n, nwords,
                                cg.wpt, marks, a.q, chunk, status, &a.ctl->parity, &a.ctl->err);
@@ -715,7 +844,7 @@ void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s)
     // every iteration relaxes or splits; the loop is bounded well below this cap
     const int64_t cap = 64ll * n + 1024;
     StepKey key("sssp");
-    key.add(a).add(G).add(cg).add(chunk).add(status);
+    key.add(a).add(G).add(cg).add(chunk).add(status).add(pull);
     const int32_t launched = run_until_done(c, &a.ctl->mode, SS_DONE, g.iter_hint() + 1, cap, s, launch, &key);
     SsspCtl h;
     GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(SsspCtl), hipMemcpyDeviceToHost, s));
@@ -730,6 +859,7 @@ void run_sssp(Ctx &c, Graph &g, int32_t src, uint32_t *dist, hipStream_t s)
     c.stats.v["near_entries"] += (double)h.near_entries;
     c.stats.v["improvements"] += (double)h.improvements;
     c.stats.v["far_entries"] += (double)h.far_entries;
+    c.stats.v["pull_iterations"] += h.pull_iters;
     c.stats.v["delta"] = delta;
     c.stats.v["launches"] += launched;
     c.stats.v["solves"] += 1.0;

@@ -282,20 +282,32 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
                     for (int j = 0; j < 16; ++j) relax(vv[j], ww[j], du, dv[j], act_u & (j0 + j < nb));
                 }
             } else {
+                // edges are in source order: a source row is loaded once per
+                // run of edges that share it (about 5 sources per such group)
+                int32_t uprev = -1;
+                uint32_t duprev = 0;
                 for (int j0 = 0; j0 < nb; j0 += BS_UNROLL) {
                     uint32_t du[BS_UNROLL], dv[BS_UNROLL], ww[BS_UNROLL], qw[BS_UNROLL];
-                    int32_t vv[BS_UNROLL];
+                    int32_t vv[BS_UNROLL], uu[BS_UNROLL];
+                    bool same[BS_UNROLL];
 #pragma unroll
                     for (int j = 0; j < BS_UNROLL; ++j) {
                         const int src = min(j0 + j, nb - 1);
-                        const int32_t u = lane_bcast(ul, src);
+                        uu[j] = lane_bcast(ul, src);
+                        same[j] = uu[j] == (j == 0 ? uprev : uu[j - 1]);   // wave-uniform
                         vv[j] = lane_bcast(vl, src);
                         ww[j] = (uint32_t)lane_bcast(wl, src);
                         const uint32_t q0 = (uint32_t)lane_bcast(qlo, src), q1 = (uint32_t)lane_bcast(qhi, src);
                         qw[j] = lane < 32 ? q0 : q1;
-                        du[j] = bs_load<BITS>(a, (size_t)u, lane);
+                        du[j] = 0u;
+                        if (!same[j]) du[j] = bs_load<BITS>(a, (size_t)uu[j], lane);
                         dv[j] = bs_load<BITS>(a, (size_t)vv[j], lane);
                     }
+#pragma unroll
+                    for (int j = 0; j < BS_UNROLL; ++j)
+                        if (same[j]) du[j] = j == 0 ? duprev : du[j - 1];
+                    uprev = uu[BS_UNROLL - 1];
+                    duprev = du[BS_UNROLL - 1];
 #pragma unroll
                     for (int j = 0; j < BS_UNROLL; ++j)
                         relax(vv[j], ww[j], du[j], dv[j], (j0 + j < nb) & (((qw[j] >> (lane & 31)) & 1u) != 0));

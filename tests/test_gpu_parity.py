@@ -125,6 +125,34 @@ def test_bfs_frontier_representations(ctx, name, frontier):
         g.free()
 
 
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("mapping,threshold", [(2, 4096), (0, 4096), (0, 64)])
+def test_bfs_push_work_mappings(ctx, name, mapping, threshold):
+    """Push levels with the per-vertex mapping of Sec. 4.4 (lists of a
+    work-group's size or more by the whole work-group, of 64 or more by a wave,
+    the rest per thread) alone, and the hybrid that uses it below a frontier
+    size and equal edge chunks above it, give the oracle's depths.  The star's
+    centre (5000 edges) takes the work-group path, R-MAT hubs the wave path."""
+    row, col, w = graph(name)
+    g = _load(ctx, row, col)
+    ctx.set_option("bfs.direction", 1)
+    ctx.set_option("bfs.frontier", 1)
+    ctx.set_option("advance.mapping", mapping)
+    ctx.set_option("advance.twc_threshold", threshold)
+    try:
+        for s in _sources(row, col, 4):
+            _say("bfs push mapping", mapping, "threshold", threshold, name, "src", s)
+            got = _host(ctx.bfs(g, s))
+            want = oracle.bfs(row, col, s)
+            assert np.array_equal(got, want), (name, mapping, threshold, s, int(np.sum(got != want)))
+    finally:
+        ctx.set_option("bfs.direction", 0)
+        ctx.set_option("bfs.frontier", 0)
+        ctx.set_option("advance.mapping", 1)
+        ctx.set_option("advance.twc_threshold", 4096)
+        g.free()
+
+
 def test_bfs_rmat16_from_vertex0_all_chunks(ctx):
     row, col, _ = graph("rmat16")
     g = _load(ctx, row, col)
@@ -171,6 +199,34 @@ def test_sssp_matches_oracle(ctx, name, delta, frontier):
     finally:
         ctx.set_option("sssp.delta", 0)
         ctx.set_option("sssp.frontier", 0)
+        g.free()
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("alpha", [24, 1e6])
+@pytest.mark.parametrize("delta", [0, 1])
+def test_sssp_pull_directions(ctx, name, alpha, delta):
+    """Direction-optimizing single-source SSSP: iterations whose near queue
+    carries more than m / alpha edges relax by a pull sweep (alpha 1e6: nearly
+    every iteration after the first pulls).  Distances equal the oracle's with
+    one bucket and with many (delta 1)."""
+    row, col, w = graph(name)
+    g = _load(ctx, row, col, w)
+    ctx.set_option("sssp.pull_alpha", alpha)
+    ctx.set_option("sssp.delta", delta)
+    try:
+        pulls = 0
+        for s in _sources(row, col, 4):
+            _say("sssp pull", name, "alpha", alpha, "delta", delta, "src", s)
+            got = _host(ctx.sssp(g, s)).view(np.uint32)
+            want = oracle.sssp(row, col, w, s)
+            assert np.array_equal(got, want), (name, alpha, delta, s, int(np.sum(got != want)))
+            pulls += ctx.stat("pull_iterations")
+        if alpha == 1e6 and name in ("rmat16", "grid96"):
+            assert pulls >= 1
+    finally:
+        ctx.set_option("sssp.pull_alpha", 0)
+        ctx.set_option("sssp.delta", 0)
         g.free()
 
 
