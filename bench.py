@@ -118,7 +118,7 @@ SERVE_SCALES = (18, 19, 20, 21, 22, 23)
 SERVE_RATES = (500.0, 2000.0, 8000.0, 1e9)
 
 
-def serve_leg(ctx, resident, nq, log, rates=SERVE_RATES):
+def serve_leg(ctx, resident, nq, log, rates=SERVE_RATES, modes=("batched", "one_at_a_time")):
     """The serving workload: six resident R-MAT graphs (scales 18-23, edge
     factor 16, weights in [1,64]); a Poisson stream of queries, 70 % BFS and
     30 % SSSP, each on a graph drawn Zipf(s = 1.2) over the scales in
@@ -149,6 +149,8 @@ def serve_leg(ctx, resident, nq, log, rates=SERVE_RATES):
             ref[key] = (ctx.bfs(g, srcs[i]) if kinds[i] == gfr.GFR_Q_BFS else ctx.sssp(g, srcs[i])).clone()
     res = {}
     for mode, mb in (("batched", 64), ("one_at_a_time", 1)):
+        if mode not in modes:
+            continue
         ctx.set_option("serve.max_batch", mb)
         pts = []
         for rate in rates:
@@ -221,6 +223,9 @@ def main():
     ap.add_argument("--cpu-sources", type=int, default=5, help="oracle sample size (sources, about 12 s of CPU work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-queries", type=int, default=10000, help="queries per serving point (0: skip)")
+    ap.add_argument("--serve-rates", default="500,2000,8000,burst",
+                    help="offered rates of the serving points, queries/s ('burst': all at once)")
+    ap.add_argument("--serve-modes", default="batched,one_at_a_time", help="serving modes to run")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="finish with one device copy of this many MiB (a known-size kernel that "
                          "calibrates the HBM byte counters of a profiler run)")
@@ -409,7 +414,9 @@ def main():
             w2 = graphgen.weights(r2, c2, 64)
             resident[sc] = (r2, c2, w2, ctx.graph_load_csr(r2, c2, w2))
             log("serving graph scale %d loaded (n=%d m=%d)" % (sc, r2.size - 1, c2.size))
-        serving = serve_leg(ctx, resident, args.serve_queries, log)
+        rates = tuple(1e9 if r.strip() == "burst" else float(r) for r in args.serve_rates.split(","))
+        serving = serve_leg(ctx, resident, args.serve_queries, log, rates=rates,
+                            modes=tuple(m.strip() for m in args.serve_modes.split(",")))
         log("serving:", json.dumps(serving))
         for sc, (_, _, _, g2) in resident.items():
             if g2 is not g:

@@ -11,7 +11,8 @@ The options it sweeps change only how a result is reached:
   (Sec. 4.5), as a multiple of the mean edge weight so that it carries over
   between graphs of one class;
 * ``msbfs.alpha`` and ``batch.delta_factor``: the same two choices for the
-  batched (64 sources at once) traversals;
+  batched (64 sources at once) traversals, and ``batch.blocks_per_cu``, the
+  work-groups per CU of the batched relaxation's grid;
 * ``batch.min_bfs`` / ``batch.min_sssp``: the batch size from which one
   shared traversal beats sequential single-source solves.
 
@@ -50,6 +51,7 @@ SWEEP = {
     "sssp.delta_factor": [0.5, 1, 2, 4, 8, 16, 64],
     "msbfs.alpha": [1, 2, 4, 8, 16, 64],
     "batch.delta_factor": [0, 2, 8, 32],
+    "batch.blocks_per_cu": [8, 16, 32, 64],
 }
 QUICK = {
     "advance.chunk": [512, 2048],
@@ -58,6 +60,7 @@ QUICK = {
     "sssp.delta_factor": [1, 8],
     "msbfs.alpha": [2, 16],
     "batch.delta_factor": [0, 8],
+    "batch.blocks_per_cu": [16, 64],
 }
 CROSSOVER_K = [2, 4, 8, 16, 32, 48]
 SINGLE_SOURCES = 4          # sources timed per graph for the single-source solvers
@@ -65,6 +68,7 @@ SINGLE_SOURCES = 4          # sources timed per graph for the single-source solv
 DEFAULTS = {
     "advance.chunk": 1024, "bfs.alpha": 15, "bfs.beta": 18, "sssp.delta_factor": 2,
     "msbfs.alpha": 4, "batch.delta_factor": 0, "batch.min_bfs": 8, "batch.min_sssp": 24,
+    "batch.blocks_per_cu": 64,
 }
 
 
@@ -207,7 +211,7 @@ class Tuner:
         opts = self._descend(cases, ["bfs_batch"], ["msbfs.alpha"], sweep, dict(opts, **{"batch.min_bfs": 1}),
                              k=kmax, rounds=1)
         if weighted:
-            opts = self._descend(cases, ["sssp_batch"], ["batch.delta_factor"], sweep,
+            opts = self._descend(cases, ["sssp_batch"], ["batch.delta_factor", "batch.blocks_per_cu"], sweep,
                                  dict(opts, **{"batch.min_sssp": 1}), k=kmax, rounds=1)
         opts["batch.min_bfs"] = self._crossover(cases, "bfs_batch")
         if weighted:
@@ -260,7 +264,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--out", default="tuning.json")
     ap.add_argument("--scales", default="16,20,22", help="R-MAT scales of the scale-free class")
-    ap.add_argument("--grid", type=int, default=2048, help="side of the grid graph of the mesh class")
+    ap.add_argument("--grid", type=int, default=4096, help="side of the grid graph of the mesh class")
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--repeats", type=int, default=3)
     a = ap.parse_args(argv)

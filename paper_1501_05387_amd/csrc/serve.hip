@@ -77,6 +77,14 @@ struct Server {
     gfr_ticket next = 1;
     std::mutex sess_mu;            // sessions (and their device memory)
     std::vector<std::unique_ptr<SessionEntry>> sessions;
+    // results copied to device outputs, completed when their event has fired
+    // (worker only, under sess_mu)
+    struct PendingDone {
+        hipEvent_t ev;
+        std::vector<gfr_ticket> tickets;
+    };
+    std::vector<PendingDone> pending;
+    std::vector<hipEvent_t> ev_pool;
     Bounce bounce;                 // host copies of the worker
     // statistics
     std::vector<double> latency_ms;
@@ -137,6 +145,11 @@ static gfr_query query_of(Server *sv, gfr_ticket t)
 }
 
 // Copy finished lanes' results out, complete their tickets, free the lanes.
+// When every output is device memory the copies are only queued: the lanes
+// are free at once (anything later on the session's stream runs after the
+// copies) and the tickets complete when the copies' event has fired, so the
+// worker never waits for a session here.  Host outputs are copied through
+// the bounce buffers and waited for.
 static void retire(Server *sv, SessionEntry &e, unsigned long long lanes, gfr_status st)
 {
     if (!lanes) return;
@@ -144,6 +157,9 @@ static void retire(Server *sv, SessionEntry &e, unsigned long long lanes, gfr_st
     const size_t row = 4ull * (size_t)s.n;
     if (st == GFR_OK) {
         try {
+            bool all_dev = true;
+            for (unsigned long long m = lanes; m; m &= m - 1)
+                all_dev &= query_of(sv, e.lane[__builtin_ctzll(m)]).out_on_device != 0;
             s.extract(lanes);
             for (unsigned long long m = lanes; m; m &= m - 1) {
                 const int q = __builtin_ctzll(m);
@@ -152,6 +168,26 @@ static void retire(Server *sv, SessionEntry &e, unsigned long long lanes, gfr_st
                     GFR_HIP(hipMemcpyAsync(qq.out, s.row(q), row, hipMemcpyDeviceToDevice, s.stream));
                 else
                     copy_to_host(sv->bounce, qq.out, s.row(q), row, s.stream);
+            }
+            if (all_dev) {
+                hipEvent_t ev = nullptr;
+                if (!sv->ev_pool.empty()) {
+                    ev = sv->ev_pool.back();
+                    sv->ev_pool.pop_back();
+                } else {
+                    GFR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+                }
+                GFR_HIP(hipEventRecord(ev, s.stream));
+                Server::PendingDone p{ev, {}};
+                for (unsigned long long m = lanes; m; m &= m - 1) {
+                    const int q = __builtin_ctzll(m);
+                    p.tickets.push_back(e.lane[q]);
+                    e.lane[q] = 0;
+                }
+                sv->pending.push_back(std::move(p));
+                e.busy &= ~lanes;
+                s.release(lanes);
+                return;
             }
             GFR_HIP(hipStreamSynchronize(s.stream));
         } catch (const Error &err) {
@@ -169,6 +205,34 @@ static void retire(Server *sv, SessionEntry &e, unsigned long long lanes, gfr_st
     e.busy &= ~lanes;
     s.release(lanes);
     sv->cv_done.notify_all();
+}
+
+// Complete the tickets whose result copies have finished (under sess_mu).
+static bool complete_pending(Server *sv)
+{
+    bool any = false;
+    for (size_t i = 0; i < sv->pending.size();) {
+        Server::PendingDone &p = sv->pending[i];
+        const hipError_t r = hipEventQuery(p.ev);
+        if (r == hipErrorNotReady) {
+            ++i;
+            continue;
+        }
+        gfr_status st = GFR_OK;
+        if (r != hipSuccess) {
+            (void)hipGetLastError();
+            st = GFR_E_DEVICE;
+        }
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            for (gfr_ticket t : p.tickets) complete_locked(sv, t, st);
+        }
+        sv->ev_pool.push_back(p.ev);
+        sv->pending.erase(sv->pending.begin() + (long)i);
+        any = true;
+    }
+    if (any) sv->cv_done.notify_all();
+    return any;
 }
 
 // Private device state of a single-source thread: its own stream, scratch
@@ -324,6 +388,7 @@ static void worker_loop(Server *sv)
         bool in_flight = false, progress = false;
         {
             std::unique_lock<std::mutex> ls(sv->sess_mu);
+            progress |= complete_pending(sv);
             // 1. steps that ended: retire the lanes that finished
             for (auto &ep : sv->sessions) {
                 SessionEntry &e = *ep;
@@ -523,6 +588,7 @@ static void worker_loop(Server *sv)
                 if (e.s && e.in_flight) in_flight = true;
             }
             drop_dead_sessions(sv);
+            if (!sv->pending.empty()) in_flight = true;
         }
         sv->cv_done.notify_all();
         if (in_flight) {
@@ -548,6 +614,11 @@ void serve_shutdown(Ctx &c)
     if (sv->worker.joinable()) sv->worker.join();
     for (auto &th : sv->single_workers)
         if (th.joinable()) th.join();
+    for (auto &p : sv->pending) {
+        (void)hipEventSynchronize(p.ev);
+        (void)hipEventDestroy(p.ev);
+    }
+    for (hipEvent_t ev : sv->ev_pool) (void)hipEventDestroy(ev);
     delete sv;   // session destructors wait for their streams
     c.server = nullptr;
 }

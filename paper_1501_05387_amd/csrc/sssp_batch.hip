@@ -1255,7 +1255,8 @@ BsLayout bs_layout(int64_t n, int64_t m, int num_cu)
     L.n = (size_t)n;
     L.nwords = (size_t)((n + 63) / 64) * 2;
     L.nparts = (size_t)(m / 1024) + 2;
-    L.G = (size_t)num_cu * 7;
+    // relax grid as for direct batches: 64 work-groups per CU, at most one per 1024-edge chunk
+    L.G = (size_t)std::min<int64_t>(64ll * num_cu, std::max<int64_t>(num_cu, m / 1024 + 1));
     L.blocks = compact_geom((uint32_t)L.nwords, num_cu).blocks;
     return L;
 }
