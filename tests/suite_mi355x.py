@@ -197,7 +197,7 @@ def suite(args, log):
                       "alg_frac_of_peak_p50": float(np.median(gbs)) / HBM_PEAK_GBS, "rerelaxation_r": _dist(rr)}
         log("d2 sssp", d2["sssp"]["gteps"])
         for mode, fn, bytes_of in (("msbfs_64", lambda: ctx.bfs_batch(g, srcs), lambda st: msbfs_bytes(dict(st, m=g.m), n)),
-                                   ("batched_sssp_64", lambda: ctx.sssp_batch(g, srcs), lambda st: bsssp_bytes(st, n))):
+                                   ("batched_sssp_64", lambda: ctx.sssp_batch(g, srcs), lambda st: bsssp_bytes(st))):
             ts = _timed(ctx, fn, 10)
             st = read_stats(ctx, STAT_KEYS)
             t = float(np.median(ts)) * 1e-3
