@@ -317,12 +317,128 @@ def suite(args, log):
     return rep
 
 
+def render_md(rep) -> str:
+    """The suite's report as markdown tables (the figures of `rep`, nothing else)."""
+    L = ["# Measurement suite on one MI355X", "",
+         "Command (repository root): `python -m tests.suite_mi355x --out profiles/suite_mi355x.json --md "
+         "profiles/suite_mi355x.md` (about 3 minutes). Device times of whole calls; median of 10 after warm-up unless "
+         "stated; GTEPS = sum of degrees of reached vertices / time (Graph500 count = half). Algorithmic GB/s from the "
+         "kernels' own counters (byte models in the design notes), against 8 TB/s.",
+         "Kernel sources digest `%s`; device %s." % (rep.get("source_digest"), rep.get("device"))]
+    d1 = rep.get("d1_rmat16_bfs0")
+    if d1:
+        L += ["", "## R-MAT s16, BFS from vertex 0", "", "| bit-exact | ms | levels | µs per level | GTEPS |",
+              "|---|---|---|---|---|",
+              "| %s | %.3f | %d | %.1f | %.1f |" % (d1["bit_exact"], d1["ms_median"], d1["levels"], d1["us_per_level"],
+                                                d1["gteps"])]
+    d2 = rep.get("d2_rmat22")
+    if d2:
+        L += ["", "## R-MAT s22, 64 sources (parity sample ok: %s)" % d2["parity_sample_ok"], "",
+              "| mode | GTEPS hmean | p25 / p50 / p75 | alg GB/s (p50) | of peak |", "|---|---|---|---|---|"]
+        for mode in ("push_bfs", "do_bfs", "queue_push_bfs", "queue_do_bfs", "sssp"):
+            r = d2[mode]
+            L.append("| %s (per source) | %.1f | %.1f / %.1f / %.1f | %.0f | %.3f |" % (
+                mode, r["gteps"]["hmean"], r["gteps"]["p25"], r["gteps"]["p50"], r["gteps"]["p75"],
+                r["alg_GBs"]["p50"], r["alg_frac_of_peak_p50"]))
+        for mode in ("msbfs_64", "batched_sssp_64"):
+            r = d2[mode]
+            L.append("| %s (one call, %.2f ms) | %.1f (aggregate) | — | %.0f | %.3f |" % (
+                mode, r["ms_median"], r["gteps"], r["alg_GBs"], r["alg_frac_of_peak"]))
+        L += ["", "Single-source SSSP re-relaxation factor r (edges relaxed / edges of reached vertices): p50 %.2f."
+              % d2["sssp"]["rerelaxation_r"]["p50"]]
+    d3 = rep.get("d3_grid4096")
+    if d3:
+        L += ["", "## 4096² lattice with long edges, 16 sources (parity sample ok: %s)" % d3["parity_sample_ok"], "",
+              "| mode | GTEPS hmean | µs per level (p50) | levels / push / pull (first sources) |", "|---|---|---|---|"]
+        names = {"push_bfs": "push_bfs (mark-byte levels, the mesh default)", "do_bfs": "do_bfs (auto: mark-byte levels)",
+                 "queue_push_bfs": "push_bfs, queue levels", "queue_do_bfs": "do_bfs, queue levels"}
+        for mode, label in names.items():
+            r = d3[mode]
+            L.append("| %s | %.2f | %.1f | %s |" % (label, r["gteps"]["hmean"], r["us_per_level"]["p50"],
+                                                  r["levels_push_pull"]))
+        L.append("| sssp | %.2f | — | r p50 %.2f |" % (d3["sssp"]["gteps"]["hmean"], d3["sssp"]["rerelaxation_r"]["p50"]))
+        L += ["", "CC: %.2f ms, %d components, bit-exact %s." % (d3["cc"]["ms_median"], d3["cc"]["components"],
+                                                                 d3["cc"]["bit_exact"])]
+    d4 = rep.get("d4_rmat23")
+    if d4:
+        pr = d4["pagerank"]
+        L += ["", "## R-MAT s23", "",
+              "PageRank (d = 0.85, L1 < 1e-6): %.1f ms, %d iterations, %.2f ms per iteration, final L1 %.2e, L1 against "
+              "the FP64 oracle at the same iteration count %.2e." % (pr["ms_median"], pr["iterations"],
+                                                                     pr["ms_per_iteration"], pr["final_l1"],
+                                                                     pr["l1_vs_fp64_oracle"]), "",
+              "PageRank with per-vertex convergence filtering (FP64), per tolerance in units of 1/N:", "",
+              "| vertex_tol | ms | iterations | vertex updates / (iterations × N) | edges gathered / (iterations × m) |",
+              "|---|---|---|---|---|"]
+        for k, r in d4["pagerank_filtered"].items():
+            L.append("| %s | %.1f | %d | %.3f | %.3f |" % (k, r["ms_median"], r["iterations"], r["vertex_update_share"],
+                                                          r["edge_share"]))
+        b = d4["bc_32"]
+        L += ["", "BC from 32 sources: %.1f ms, %.1f GTEPS (2× convention); against the oracle on 4 sources largest "
+              "relative error %.2e, mean %.2e, zero wherever the oracle is zero: %s; path-length identity over all 32 "
+              "sources (sum of BC = sum of d(s,t) - 1) holds to a relative residual of %.1e." % (
+                  b["ms_median"], b["gteps_2x"], b["max_rel_err_4_sources"], b["mean_rel_err_4_sources"],
+                  b["zero_where_oracle_zero"], b["identity_rel_residual_32"])]
+    pe = rep.get("d4_rmat20_pagerank_filtered_error")
+    if pe:
+        L += ["", "## Filtered PageRank error report, R-MAT s20", "",
+              "Against the FP64 fixed point (oracle until its L1 change is below 1e-11, %d iterations):"
+              % pe["fixed_point_iterations"], "",
+              "| run | iterations | L1 error | vertex updates / (iterations × N) |", "|---|---|---|---|",
+              "| plain FP32, L1 < 1e-6 | %d | %.2e | 1 |" % (pe["plain_fp32_tol1e-6"]["iterations"],
+                                                          pe["plain_fp32_tol1e-6"]["l1_error"])]
+        for k, r in pe.items():
+            if k.endswith("/N"):
+                L.append("| filtered, vertex_tol %s | %d | %.2e | %.3f |" % (k, r["iterations"], r["l1_error"],
+                                                                           r["vertex_update_share"]))
+    d6 = rep.get("d6_two_hop_and_ranking")
+    if d6:
+        L += ["", "## 2-hop walk counts and node rankings", "",
+              "R-MAT s22. 2-hop from 1 and 64 seeds, each direction of the second advance (bit-exact against the "
+              "oracle: %s, %s):" % (d6["two_hop_1_bit_exact"], d6["two_hop_64_bit_exact"]), "",
+              "| seeds | direction | ms | edges inspected | G edges/s |", "|---|---|---|---|---|"]
+        for seeds in (1, 64):
+            for dr in ("push", "pull", "auto"):
+                r = d6["two_hop_%d_%s" % (seeds, dr)]
+                L.append("| %d | %s | %.3f | %.3g | %.1f |" % (seeds, dr, r["ms_median"], r["edges_inspected"], r["gteps"]))
+        L += ["", "Personalized PageRank (FP64, L1 < 1e-9): 1 seed %.1f ms (%d iterations, %.2f ms each), 64 seeds "
+              "%.1f ms; L1 against the oracle %.1e." % (d6["ppr_1"]["ms_median"], d6["ppr_1"]["iterations"],
+                                                        d6["ppr_1"]["ms_per_iteration"], d6["ppr_64"]["ms_median"],
+                                                        d6["ppr_1_l1_vs_oracle"]), "",
+              "Bipartite R-MAT, 2^21 vertices per side (n = %d, m = %d directed entries), 20 iterations:"
+              % (d6["bipartite_graph"]["n"], d6["bipartite_graph"]["m"]), "",
+              "| method | ms | ms per iteration | G edges/s | max abs error vs oracle (5 iterations) |",
+              "|---|---|---|---|---|"]
+        for name, key in (("SALSA", "salsa"), ("HITS", "hits")):
+            r = d6["%s_20_iterations" % key]
+            L.append("| %s | %.2f | %.3f | %.1f | %.1e |" % (name, r["ms_median"], r["ms_per_iteration"],
+                                                           r["edges_per_s"] / 1e9, d6["%s_5_max_abs_err" % key]))
+    d5 = rep.get("d5_serving")
+    if d5:
+        L += ["", "## Serving: six R-MAT graphs s18-s23, %d queries per point" % d5["queries_per_point"], "",
+              d5["mix"] + ".", "",
+              "| offered q/s | batched q/s | p50 / p99 ms | lanes per step | joined running | equal | one at a time q/s "
+              "| p50 / p99 ms |", "|---|---|---|---|---|---|---|---|"]
+        for b, o in zip(d5["batched"], d5["one_at_a_time"]):
+            L.append("| %s | %.0f | %.1f / %.1f | %.1f | %d | %s | %.0f | %.1f / %.1f |" % (
+                "burst" if b["offered_qps"] is None else "%.0f" % b["offered_qps"], b["qps"], b["p50_ms"], b["p99_ms"],
+                b["mean_batch"], b["joined_running"], b["results_equal"] and o["results_equal"], o["qps"], o["p50_ms"],
+                o["p99_ms"]))
+    return "\n".join(L) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--out", required=True, help="write the suite's JSON here")
     ap.add_argument("--suite-queries", type=int, default=10000, help="serving queries per point")
     ap.add_argument("--suite-parts", default="123456", help="rows to run (digits of d.1 .. d.6)")
+    ap.add_argument("--md", help="also write the report as markdown here")
+    ap.add_argument("--render", action="store_true", help="only render the JSON at --out as markdown (--md)")
     args = ap.parse_args()
+    if args.render:
+        with open(args.md, "w") as f:
+            f.write(render_md(json.load(open(args.out))))
+        return
 
     def log(*a):
         print("[suite]", *a, file=sys.stderr, flush=True)
@@ -330,6 +446,9 @@ def main():
     rep = suite(args, log)
     with open(args.out, "w") as f:
         json.dump(rep, f, indent=1)
+    if args.md:
+        with open(args.md, "w") as f:
+            f.write(render_md(rep))
     log("suite written to", args.out)
 
 
