@@ -140,7 +140,10 @@ const char *gfr_last_error(const gfr_ctx *ctx);
  *   "batch.min_bfs", "batch.min_sssp"  batches smaller than this run as sequential
  *                     single-source solves (same results, lower cost for few sources)
  *   "profile.kernels" 1: time every launch of the level kernels with HIP events
- *                     (statistics "t.<kernel>.ms" and "t.<kernel>.n")
+ *                     (statistics "t.<kernel>.ms" and "t.<kernel>.n"); 2: only the advance
+ *                     kernels (bfs_level, sssp_relax, msbfs_level, bsssp_relax and their pull
+ *                     and mark-byte forms), two event records per timed launch instead of per
+ *                     launch; 0 (default): none
  *   "serve.budget_bytes"  device bytes the serving runtime's batching sessions may hold;
  *                     lowering it releases idle sessions beyond it (busy ones when they
  *                     finish).  The single-source workers' scratch is not counted.

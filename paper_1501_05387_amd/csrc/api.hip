@@ -317,6 +317,7 @@ static void timed_begin(Ctx &c, hipStream_t s)
     c.stats.clear();
     c.ktimer.reset();
     c.ktimer.on = c.opt.profile_kernels != 0;
+    c.ktimer.advance_only = c.opt.profile_kernels == 2;
     GFR_HIP(hipEventRecord(c.ev0, s));
 }
 
@@ -353,7 +354,7 @@ static const OptKey kOptKeys[] = {
     {"bc.alpha", 1e-6, 1e9, true},       {"bc.beta", 1e-6, 1e9, true},
     {"twohop.direction", 0, 2, true},    {"twohop.alpha", 1e-6, 1e9, true},
     {"serve.budget_bytes", 0, 1e15, false}, {"serve.max_batch", 1, 64, false},
-    {"profile.kernels", 0, 1, false}, {"serve.hipgraph", 0, 1, false},
+    {"profile.kernels", 0, 2, false}, {"serve.hipgraph", 0, 1, false},
 };
 
 static const OptKey &opt_key(const std::string &key)

@@ -208,8 +208,11 @@ void copy_to_host(Bounce &b, void *dst, const void *src, size_t bytes, hipStream
 // Optional per-launch timing of named kernels with HIP events on the launch
 // stream ("profile.kernels" option).  Results land in the context statistics
 // as "t.<kernel>.ms" (summed device time) and "t.<kernel>.n" (launches).
+// With advance_only, only the advance kernels (names holding "level",
+// "relax" or "pull") are timed: each timed launch costs two event records.
 struct KernelTimer {
     bool on = false;
+    bool advance_only = false;
     std::vector<hipEvent_t> pool;
     std::vector<std::pair<const char *, std::pair<hipEvent_t, hipEvent_t>>> marks;
     size_t used = 0;
@@ -227,9 +230,13 @@ struct KernelTimer {
         used = 0;
         marks.clear();
     }
+    static bool is_advance(const char *name)
+    {
+        return strstr(name, "level") || strstr(name, "relax") || strstr(name, "pull");
+    }
     template <class F> void run(const char *name, hipStream_t s, F launch)
     {
-        if (!on) {
+        if (!on || (advance_only && !is_advance(name))) {
             launch();
             return;
         }

@@ -10,14 +10,15 @@
 // single-source SSSP; the queries share the near/far bucket bound of the
 // priority queue (Sec. 4.5), which only changes the schedule, not the result.
 //
-// Narrow rows: a batch first runs with 8-bit distances (64-byte rows, a
-// quarter of the bytes of every random row access), unreached = 0xFF.  A
-// relaxation that would store 0xFF or more sets the overflow flag, the
-// traversal stops, and the batch is solved again with 16-bit rows (128
-// bytes, unreached 0xFFFF), and past those with 32-bit rows; so a finished
-// narrow batch stored exactly the distances the wide one would.  The 2 or 4
-// queries that share a 32-bit word of a narrow row lower it together with
-// compare-and-swap (there is no 8- or 16-bit atomic minimum).
+// Narrow rows (an option; 32-bit rows are the default): a batch first runs
+// with 8-bit distances (64-byte rows, a quarter of the bytes of every random
+// row access), unreached = 0xFF.  A relaxation that would store 0xFF or more
+// sets the overflow flag, the traversal stops, and the batch is solved again
+// with 16-bit rows (128 bytes, unreached 0xFFFF), and past those with 32-bit
+// rows; so a finished narrow batch stored exactly the distances the wide one
+// would.  The 2 or 4 queries that share a 32-bit word of a narrow row lower
+// it together with compare-and-swap (there is no 8- or 16-bit atomic
+// minimum), which is why the narrow forms are slower on this GPU.
 //
 // Marks: per vertex a 64-bit mask of the queries improved in an iteration
 // (one atomicOr of the wave's ballot per improved edge, not one byte store
@@ -1154,7 +1155,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
             if (*(volatile uint32_t *)c.pinned)
                 fail(GFR_E_INVALID, "sssp_batch: a distance does not fit below 0xFFFFFFFF");
         }
-                if (bits == 8)
+        if (bits == 8)
             hipLaunchKernelGGL(bsssp_transpose<8>, dim3(G), dim3(GFR_BLOCK), 0, s, a, n, lanes_mask,
                                dist + (size_t)g0 * n);
         else if (bits == 16)

@@ -563,6 +563,38 @@ def test_sssp_batch_pair_kernel(ctx, name, delta):
         g.free()
 
 
+def test_kernel_timing_modes(ctx):
+    """profile.kernels 1 times every level launch, 2 only the advance kernels
+    (the compactions run untimed); the results do not change."""
+    row, col, w = graph("rmat16")
+    srcs = graphgen.sample_sources(row, col, 64)
+    g = _load(ctx, row, col, w)
+    try:
+        got = {}
+        for mode in (0, 1, 2):
+            ctx.set_option("profile.kernels", mode)
+            _say("kernel timing mode", mode)
+            got[mode] = _host(ctx.sssp_batch(g, srcs)).view(np.uint32)
+            def st(key):
+                try:
+                    return ctx.stat(key)
+                except Exception:   # a statistic the call did not produce
+                    return 0.0
+            relax, compact = st("t.bsssp_relax.n"), st("t.bsssp_compact.n")
+            if mode == 0:
+                assert relax == 0 and compact == 0
+            elif mode == 1:
+                assert relax > 0 and compact > 0
+            else:
+                assert relax > 0 and compact == 0 and st("t.bsssp_relax.ms") > 0
+        assert np.array_equal(got[0], got[1]) and np.array_equal(got[0], got[2])
+        n = row.size - 1
+        assert np.array_equal(got[2].reshape(64, n)[5], oracle.sssp(row, col, w, int(srcs[5])))
+    finally:
+        ctx.set_option("profile.kernels", 0)
+        g.free()
+
+
 def test_step_graph_replays(ctx):
     """graph.steps 1: the level loops replay captured hipGraphs of their level
     launches.  Each solver runs four times into the same buffers (one capture,
