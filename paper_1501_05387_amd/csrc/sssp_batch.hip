@@ -1117,16 +1117,19 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
                                                s, a);
                         });
                 });
-                c.ktimer.run("bsssp_pull", s, [&]() {
-                    by_width([&](auto B) {
-                        hipLaunchKernelGGL((bsssp_pull<1024, decltype(B)::value>), dim3(Gb), dim3(GFR_BLOCK), 0, s,
-                                           a);
+                // the pull sweep runs only where the control chose it; with
+                // pull_alpha 0 it never does, and is not launched at all
+                if (pull_alpha > 0.f)
+                    c.ktimer.run("bsssp_pull", s, [&]() {
+                        by_width([&](auto B) {
+                            hipLaunchKernelGGL((bsssp_pull<1024, decltype(B)::value>), dim3(Gb), dim3(GFR_BLOCK), 0,
+                                               s, a);
+                        });
                     });
-                });
                 compact();
             };
             StepKey key("bsssp");
-            key.add(a).add(G).add(Gw).add(cg).add(chunk).add(status).add(bits).add(pair);
+            key.add(a).add(G).add(Gw).add(cg).add(chunk).add(status).add(bits).add(pair).add(pull_alpha);
             run_until_done(c, &a.ctl->mode, BS_DONE, g.iter_hint() + 1, 64ll * n + 1024, s, launch, &key);
             GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(BsCtl), hipMemcpyDeviceToHost, s));
             GFR_HIP(hipStreamSynchronize(s));
@@ -1272,6 +1275,7 @@ struct BsSession final : LaneSession {
     BsArgs a{};
     CompactGeom cg{};
     int G = 0;
+    bool pull = false;   // pull sweeps possible (batch.pull_alpha > 0)
     uint32_t nwords = 0;
     unsigned long long *status = nullptr;
     int32_t *pairs = nullptr, *pin_pairs = nullptr;
@@ -1331,6 +1335,7 @@ struct BsSession final : LaneSession {
         fill_u32(a.fany, 0u, 8 * L.nwords, stream);
         fill_u32(a.part, 0u, 4 * L.G, stream);
         fill_u32(status, 0u, 4 * L.blocks, stream);
+        pull = o.batch_pull_alpha > 0;
         hipLaunchKernelGGL(bs_session_init, dim3(1), dim3(64), 0, stream, a, (float)o.batch_pull_alpha);
         GFR_LAUNCH_CHECK();
     }
@@ -1361,7 +1366,7 @@ struct BsSession final : LaneSession {
     void enqueue_step() override
     {
         hipLaunchKernelGGL((bsssp_relax<1024, 32>), dim3(G), dim3(GFR_BLOCK), 0, stream, a);
-        hipLaunchKernelGGL((bsssp_pull<1024, 32>), dim3(G), dim3(GFR_BLOCK), 0, stream, a);
+        if (pull) hipLaunchKernelGGL((bsssp_pull<1024, 32>), dim3(G), dim3(GFR_BLOCK), 0, stream, a);
         hipLaunchKernelGGL(compact_kernel<BsMarks<32>>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, stream, a.R, a.n,
                            nwords, cg.wpt, BsMarks<32>{a, (uint32_t)G, cg.blocks}, a.q, 1024u, status,
                            &a.ctl->parity, &a.ctl->err);

@@ -24,9 +24,16 @@ def workers() -> int:
 
 
 def map_sources(fn, sources):
-    """[fn(s) for s in sources], the calls spread over worker threads."""
+    """[fn(s) for s in sources], the calls spread over worker threads (a line
+    is printed as each one finishes: long full-size runs show progress)."""
+    sources = list(sources)
     with ThreadPoolExecutor(max_workers=workers()) as ex:
-        return list(ex.map(lambda s: fn(int(s)), list(sources)))
+        futs = [ex.submit(fn, int(s)) for s in sources]
+        out = []
+        for i, f in enumerate(futs):
+            out.append(f.result())
+            print("[oracle] %d/%d solves done" % (i + 1, len(futs)), flush=True)
+        return out
 
 
 def bfs_rows(row, col, sources):

@@ -61,10 +61,14 @@ def test_rmat22_bench_step(ctx):
     bad_s = [i for i in range(64) if not np.array_equal(dist_h[i], ref_s[i])]
     _say("rmat22 rows differing from the oracle: bfs %s sssp %s" % (bad_b, bad_s))
     assert not bad_b and not bad_s
-    # the rules any correct result obeys, on every row and every directed edge
-    for i in range(64):
+    # every row equals the oracle's; the rules any correct result obeys (on
+    # every directed edge) pin the oracle itself, on a spread of rows (each
+    # check is a pass over the 128 M edges)
+    for i in (0, 21, 42, 63):
+        _say("rmat22 invariants on row", i)
         invariants.check_bfs(row, col, int(srcs[i]), dep_h[i])
         invariants.check_sssp(row, col, w, int(srcs[i]), dist_h[i])
+    for i in range(64):
         assert np.array_equal(dep_h[i] >= 0, dist_h[i] != 0xFFFFFFFF), ("SSSP and BFS reach differ", i)
 
 
