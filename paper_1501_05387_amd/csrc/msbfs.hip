@@ -251,8 +251,10 @@ constexpr int32_t MS_LVL_CAP = 24;   // depths kept as records (5 bit planes cov
 constexpr int32_t MS_DEEP = INT32_MIN;
 static_assert(MS_LVL_CAP <= 32, "five bit planes hold depths below 32");
 
-__global__ __launch_bounds__(GFR_BLOCK) void msbfs_output(MsArgs a, int32_t nlev)
+__global__ __launch_bounds__(GFR_BLOCK) void msbfs_output(MsArgs a)
 {
+    // depths 0 .. level were recorded (the last record is the empty frontier)
+    const int32_t nlev = min(MS_LVL_CAP, a.ctl->level + 1);
     const int32_t kq = a.k;
     const size_t n = (size_t)a.n;
     for (size_t v = (size_t)blockIdx.x * GFR_BLOCK + threadIdx.x; v - threadIdx.x < n;
@@ -420,17 +422,17 @@ void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t 
         StepKey key("msbfs");
         key.add(a).add(G).add(cg).add(chunk).add(status);
         run_until_done(c, &a.ctl->dir, MS_DONE, g.levels_hint() + 2, (int64_t)n + 8, s, launch, &key);
+        // the output pass takes the depth count from the control block, so it
+        // is queued before the block is read back (a failed batch fails the call)
+        c.ktimer.run("msbfs_output", s, [&]() {
+            hipLaunchKernelGGL(msbfs_output, dim3(grid_blocks(c, 8)), dim3(GFR_BLOCK), 0, s, a);
+        });
+        GFR_LAUNCH_CHECK();
         MsCtl h;
         GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, s));
         GFR_HIP(hipStreamSynchronize(s));
         memcpy(&h, c.pinned, sizeof(MsCtl));
         if (h.err) fail(GFR_E_DEVICE, "bfs_batch: frontier compaction look-back timed out");
-        // depths 0 .. h.level were recorded (the last record is the empty frontier)
-        const int32_t nlev = std::min<int32_t>(MS_LVL_CAP, h.level + 1);
-        c.ktimer.run("msbfs_output", s, [&]() {
-            hipLaunchKernelGGL(msbfs_output, dim3(grid_blocks(c, 8)), dim3(GFR_BLOCK), 0, s, a, nlev);
-        });
-        GFR_LAUNCH_CHECK();
         levels += h.level;
         pull_levels += (double)h.pull_levels;
         push_edges += (double)h.push_edges;

@@ -1075,6 +1075,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     const bool pair = c.opt.batch_pair != 0;   // 32-bit rows: two edges per row instruction
     for (int32_t g0 = 0; g0 < k; g0 += 64) {
         const int32_t kk = std::min<int32_t>(64, k - g0);
+        const unsigned long long lanes_mask = kk == 64 ? ~0ull : ((1ull << kk) - 1ull);
         BsCtl h;
         for (;;) {
             fill_u32(a.D, 0xFFFFFFFFu, 2ull * bits * n, s);   // 8 * bits bytes per vertex
@@ -1131,6 +1132,13 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
             StepKey key("bsssp");
             key.add(a).add(G).add(Gw).add(cg).add(chunk).add(status).add(bits).add(pair).add(pull_alpha);
             run_until_done(c, &a.ctl->mode, BS_DONE, g.iter_hint() + 1, 64ll * n + 1024, s, launch, &key);
+            if (bits == 32) {
+                // no fallback can follow: the output is written before the
+                // control block is read back (a failed batch fails the call)
+                hipLaunchKernelGGL(bsssp_transpose<32>, dim3(G), dim3(GFR_BLOCK), 0, s, a, n, lanes_mask,
+                                   dist + (size_t)g0 * n);
+                GFR_LAUNCH_CHECK();
+            }
             GFR_HIP(hipMemcpyAsync(c.pinned, a.ctl, sizeof(BsCtl), hipMemcpyDeviceToHost, s));
             GFR_HIP(hipStreamSynchronize(s));
             memcpy(&h, c.pinned, sizeof(BsCtl));
@@ -1146,7 +1154,6 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
             }
             break;
         }
-        const unsigned long long lanes_mask = kk == 64 ? ~0ull : ((1ull << kk) - 1ull);
         if (h.unfit) {
             // 32-bit rows (narrow batches fall back instead): was an unfit sum a distance?
             fill_u32(a.part, 0u, 1, s);
@@ -1163,9 +1170,6 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
                                dist + (size_t)g0 * n);
         else if (bits == 16)
             hipLaunchKernelGGL(bsssp_transpose<16>, dim3(G), dim3(GFR_BLOCK), 0, s, a, n, lanes_mask,
-                               dist + (size_t)g0 * n);
-        else
-            hipLaunchKernelGGL(bsssp_transpose<32>, dim3(G), dim3(GFR_BLOCK), 0, s, a, n, lanes_mask,
                                dist + (size_t)g0 * n);
         GFR_LAUNCH_CHECK();
         batches8 += bits == 8 ? 1 : 0;
