@@ -247,7 +247,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the engine is single-device); "
+        print("bench.py: the engine runs on one GPU only (it is single-device); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
