@@ -122,11 +122,14 @@ struct Graph {
     int32_t full_nf = 0;
     int32_t n_isolated = 0;
     int32_t bip_checked_nl = -1;   // last side split verified for the bipartite rankings
-    // hints for the speculative level loop (the size of the first batch of
-    // launches); written by every solve on the graph, also from the serving
-    // threads, hence atomic (relaxed: a stale hint only sizes a batch)
+    // hints for the speculative level loops (the size of the first batch of
+    // launches), one per solver (a 64-source traversal takes more levels than
+    // one source's); written by every solve on the graph, also from the
+    // serving threads, hence atomic (relaxed: a stale hint only sizes a batch)
     std::atomic<int32_t> bfs_levels_hint{8};
     std::atomic<int32_t> sssp_iter_hint{16};
+    std::atomic<int32_t> msbfs_levels_hint{8};
+    std::atomic<int32_t> bsssp_iter_hint{16};
     int32_t levels_hint() const { return bfs_levels_hint.load(std::memory_order_relaxed); }
     int32_t iter_hint() const { return sssp_iter_hint.load(std::memory_order_relaxed); }
     // narrowest distance-row width (8, 16 or 32 bits) that no batched SSSP

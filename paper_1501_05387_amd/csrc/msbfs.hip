@@ -421,7 +421,8 @@ void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t 
         };
         StepKey key("msbfs");
         key.add(a).add(G).add(cg).add(chunk).add(status);
-        run_until_done(c, &a.ctl->dir, MS_DONE, g.levels_hint() + 2, (int64_t)n + 8, s, launch, &key);
+        run_until_done(c, &a.ctl->dir, MS_DONE, g.msbfs_levels_hint.load(std::memory_order_relaxed) + 2,
+                       (int64_t)n + 8, s, launch, &key);
         // the output pass takes the depth count from the control block, so it
         // is queued before the block is read back (a failed batch fails the call)
         c.ktimer.run("msbfs_output", s, [&]() {
@@ -433,6 +434,7 @@ void run_bfs_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, int32_t 
         GFR_HIP(hipStreamSynchronize(s));
         memcpy(&h, c.pinned, sizeof(MsCtl));
         if (h.err) fail(GFR_E_DEVICE, "bfs_batch: frontier compaction look-back timed out");
+        g.msbfs_levels_hint.store(h.level, std::memory_order_relaxed);
         levels += h.level;
         pull_levels += (double)h.pull_levels;
         push_edges += (double)h.push_edges;

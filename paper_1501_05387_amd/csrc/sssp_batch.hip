@@ -1131,7 +1131,8 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
             };
             StepKey key("bsssp");
             key.add(a).add(G).add(Gw).add(cg).add(chunk).add(status).add(bits).add(pair).add(pull_alpha);
-            run_until_done(c, &a.ctl->mode, BS_DONE, g.iter_hint() + 1, 64ll * n + 1024, s, launch, &key);
+            run_until_done(c, &a.ctl->mode, BS_DONE, g.bsssp_iter_hint.load(std::memory_order_relaxed) + 1,
+                           64ll * n + 1024, s, launch, &key);
             if (bits == 32) {
                 // no fallback can follow: the output is written before the
                 // control block is read back (a failed batch fails the call)
@@ -1143,6 +1144,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
             GFR_HIP(hipStreamSynchronize(s));
             memcpy(&h, c.pinned, sizeof(BsCtl));
             if (h.err) fail(GFR_E_DEVICE, "sssp_batch: frontier compaction look-back timed out");
+            g.bsssp_iter_hint.store((int32_t)h.iter, std::memory_order_relaxed);
             if (bits < 32 && h.overflow) {
                 // a distance outgrew the narrow rows: this batch again, twice as wide
                 bits *= 2;
