@@ -147,3 +147,23 @@ def test_packaged_tuning_file_is_accepted():
     assert st in (gfr.GFR_OK, gfr.GFR_E_DEVICE), st
     if st == gfr.GFR_OK:
         L.gfr_ctx_destroy(p.value)
+
+
+def test_bench_traffic_digest_covers_existing_sources():
+    """The digest that ties a committed HBM-counter figure to the relaxation
+    kernel names files that exist and includes every header that kernel's
+    source includes, so that an edit to any of them voids the figure."""
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import bench
+    pkg = os.path.join(root, "paper_1501_05387_amd")
+    for f in bench.RELAX_SOURCES:
+        assert os.path.isfile(os.path.join(pkg, f)), f
+    src = open(os.path.join(pkg, "csrc", "sssp_batch.hip")).read()
+    local = set(re.findall(r'#include "([^"]+)"', src))
+    covered = {os.path.basename(f) for f in bench.RELAX_SOURCES}
+    for h in local:
+        assert os.path.basename(h) in covered, h
+    assert len(bench.relax_source_digest()) == 16
+    assert bench.relax_source_digest() != bench.kernel_source_digest()
