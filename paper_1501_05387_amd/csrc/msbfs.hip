@@ -251,23 +251,82 @@ constexpr int32_t MS_LVL_CAP = 24;   // depths kept as records (5 bit planes cov
 constexpr int32_t MS_DEEP = INT32_MIN;
 static_assert(MS_LVL_CAP <= 32, "five bit planes hold depths below 32");
 
+// The depths of vertex v for every source from its level records: bit b of
+// plane[b] is bit b of the depth (a vertex is recorded at one depth per
+// source).  -1 where the source never reached v; MS_DEEP marks a depth past
+// the records, already written by msbfs_finalize.
+__device__ __forceinline__ int32_t ms_depth_of(const unsigned long long *plane, unsigned long long found,
+                                               unsigned long long vis, int q, int32_t base)
+{
+    int32_t d = 0;
+#pragma unroll
+    for (int bit = 0; bit < 5; ++bit) d |= (int32_t)((plane[bit] >> q) & 1ull) << bit;
+    const bool rec_q = (found >> q) & 1ull, seen = (vis >> q) & 1ull;
+    return rec_q ? d - base : (seen ? MS_DEEP : -1);
+}
+
 __global__ __launch_bounds__(GFR_BLOCK) void msbfs_output(MsArgs a)
 {
     // depths 0 .. level were recorded (the last record is the empty frontier)
     const int32_t nlev = min(MS_LVL_CAP, a.ctl->level + 1);
     const int32_t kq = a.k;
     const size_t n = (size_t)a.n;
+    if (n % 4 == 0 && ((uintptr_t)a.depth & 15) == 0) {
+        // four consecutive vertices per thread: 32-byte record loads and one
+        // 16-byte store per source row (every row then starts 16-byte aligned;
+        // the records and masks are arena memory, 256-byte aligned)
+        for (size_t v0 = ((size_t)blockIdx.x * GFR_BLOCK + threadIdx.x) * 4; v0 < n;
+             v0 += (size_t)gridDim.x * GFR_BLOCK * 4) {
+            unsigned long long plane[4][5], found[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                found[j] = 0;
+#pragma unroll
+                for (int bit = 0; bit < 5; ++bit) plane[j][bit] = 0;
+            }
+            for (int d = 0; d < nlev; ++d) {
+                const ulonglong2 *r2 = (const ulonglong2 *)(a.lvl + (size_t)d * n + v0);
+                const ulonglong2 lo = r2[0], hi = r2[1];
+                const unsigned long long r[4] = {lo.x, lo.y, hi.x, hi.y};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    found[j] |= r[j];
+#pragma unroll
+                    for (int bit = 0; bit < 5; ++bit)
+                        if ((d >> bit) & 1) plane[j][bit] |= r[j];
+                }
+            }
+            const ulonglong2 *vis2 = (const ulonglong2 *)(a.vis + v0);
+            const ulonglong2 va = vis2[0], vb = vis2[1];
+            const unsigned long long vis[4] = {va.x, va.y, vb.x, vb.y};
+            for (int q = 0; q < kq; ++q) {
+                const int32_t base = a.base[q];
+                int32_t x[4];
+                bool deep = false;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    x[j] = ms_depth_of(plane[j], found[j], vis[j], q, base);
+                    deep |= x[j] == MS_DEEP;
+                }
+                int32_t *row = a.depth + (size_t)q * n + v0;
+                if (!deep) {
+                    *(int4 *)row = make_int4(x[0], x[1], x[2], x[3]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (x[j] != MS_DEEP) row[j] = x[j];
+                }
+            }
+        }
+        return;
+    }
     for (size_t v = (size_t)blockIdx.x * GFR_BLOCK + threadIdx.x; v - threadIdx.x < n;
          v += (size_t)gridDim.x * GFR_BLOCK) {
         const bool ok = v < n;
         const size_t vc = ok ? v : n - 1;
-        unsigned long long rec[MS_LVL_CAP];
-#pragma unroll
-        for (int d = 0; d < MS_LVL_CAP; ++d) rec[d] = a.lvl[(size_t)min(d, nlev - 1) * n + vc];
         unsigned long long plane[5] = {0, 0, 0, 0, 0}, found = 0;
-#pragma unroll
-        for (int d = 0; d < MS_LVL_CAP; ++d) {
-            const unsigned long long r = d < nlev ? rec[d] : 0ull;
+        for (int d = 0; d < nlev; ++d) {
+            const unsigned long long r = a.lvl[(size_t)d * n + vc];
             found |= r;
 #pragma unroll
             for (int bit = 0; bit < 5; ++bit)
@@ -275,11 +334,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void msbfs_output(MsArgs a)
         }
         const unsigned long long vis = a.vis[vc];
         for (int q = 0; q < kq; ++q) {
-            int32_t d = 0;
-#pragma unroll
-            for (int bit = 0; bit < 5; ++bit) d |= (int32_t)((plane[bit] >> q) & 1ull) << bit;
-            const bool rec_q = (found >> q) & 1ull, seen = (vis >> q) & 1ull;
-            const int32_t x = rec_q ? d - a.base[q] : (seen ? MS_DEEP : -1);
+            const int32_t x = ms_depth_of(plane, found, vis, q, a.base[q]);
             if (ok && x != MS_DEEP) a.depth[(size_t)q * n + v] = x;
         }
     }
