@@ -86,27 +86,17 @@ static bool is_device_ptr_on(const void *p, int device)
     return attr.type == hipMemoryTypeDevice && attr.device == device;
 }
 
-// 16-byte stores over the 16-byte aligned body, 4-byte stores for the words
-// before and after it
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t count)
 {
-    const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    const size_t lead = ((16u - ((uintptr_t)p & 15u)) & 15u) / 4u;   // words before the first 16-byte boundary
-    const size_t head = lead < count ? lead : count;
-    if (tid < head) p[tid] = v;
-    const size_t nvec = (count - head) / 4;
-    uint4 *q = (uint4 *)(p + head);
-    const uint4 vv = make_uint4(v, v, v, v);
-    for (size_t i = tid; i < nvec; i += stride) q[i] = vv;
-    const size_t t0 = head + 4 * nvec;
-    if (tid < count - t0) p[t0 + tid] = v;
+    for (; i < count; i += stride) p[i] = v;
 }
 
 void fill_u32(void *p, uint32_t value, size_t count, hipStream_t s)
 {
     if (count == 0) return;
-    size_t blocks = (count / 4 + 255) / 256 + 1;
+    size_t blocks = (count + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t *)p, value, count);
     GFR_LAUNCH_CHECK();

@@ -960,7 +960,6 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_transpose(BsArgs a, int32_t n
 {
     __shared__ uint32_t tile[64][65];
     const int32_t ntiles = (n + 63) / 64;
-    const bool vec = n % 4 == 0 && ((uintptr_t)out & 15) == 0;   // every output row 16-byte aligned
     for (int32_t tb = blockIdx.x; tb < ntiles; tb += gridDim.x) {
         const int32_t v0 = tb * 64;
         __syncthreads();
@@ -969,19 +968,9 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_transpose(BsArgs a, int32_t n
             tile[r][q] = (v0 + r < n) ? bs_load<BITS>(a, (size_t)(v0 + r), q) : 0u;
         }
         __syncthreads();
-        if (vec && v0 + 64 <= n) {
-            // four consecutive vertices of one query per thread: 16-byte stores
-            for (int i = threadIdx.x; i < 64 * 16; i += GFR_BLOCK) {
-                const int q = i / 16, r = (i % 16) * 4;
-                if ((lanes >> q) & 1ull)
-                    *(uint4 *)(out + (size_t)q * n + v0 + r) =
-                        make_uint4(tile[r][q], tile[r + 1][q], tile[r + 2][q], tile[r + 3][q]);
-            }
-        } else {
-            for (int i = threadIdx.x; i < 64 * 64; i += GFR_BLOCK) {
-                const int q = i / 64, r = i % 64;
-                if (((lanes >> q) & 1ull) && v0 + r < n) out[(size_t)q * n + v0 + r] = tile[r][q];
-            }
+        for (int i = threadIdx.x; i < 64 * 64; i += GFR_BLOCK) {
+            const int q = i / 64, r = i % 64;
+            if (((lanes >> q) & 1ull) && v0 + r < n) out[(size_t)q * n + v0 + r] = tile[r][q];
         }
     }
 }
