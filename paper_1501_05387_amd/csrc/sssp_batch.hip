@@ -698,6 +698,7 @@ struct BsMarks {
     BsArgs a;
     uint32_t nparts;
     uint32_t nactp;   // compaction groups
+    uint32_t wave_run = 0;   // every thread owns one word: a wave's 64 words are consecutive
     uint32_t kept = 0, kmin = 0xFFFFFFFFu;
     unsigned long long actq = 0;
     uint32_t pairs = 0;   // (vertex, query) pairs queued by this thread
@@ -710,6 +711,32 @@ struct BsMarks {
         if (ctl->mode == BS_RELAX) {
             const uint32_t m = marks_to_mask(a.nany + 32ull * w);
             a.fbits[w] = m;
+            if (wave_run && ballot(true) == ~0ull) {
+                // a dense run of 64 words (at least 8 marked vertices a word on
+                // average, all 2048 vertices below n): the wave moves their
+                // masks as one coalesced 16 KB block, lane l taking 16-byte
+                // pieces l, l + 64, ... (a vertex without the mark has a zero
+                // mask, and its qm is never read)
+                const uint32_t wfirst = (uint32_t)__builtin_amdgcn_readfirstlane((int)w);
+                const uint32_t tot = wave_sum_u32(__popc(m));
+                if (tot >= 64u * 8u && (wfirst + 64ull) * 32ull <= (unsigned long long)a.n) {
+                    if (m) clear_marks(a.nany + 32ull * w);
+                    ulonglong2 *pn = (ulonglong2 *)(a.nq + 32ull * wfirst);
+                    ulonglong2 *pq = (ulonglong2 *)(a.qm + 32ull * wfirst);
+                    const int l = lane_id();
+                    ulonglong2 x[16];
+#pragma unroll
+                    for (int it = 0; it < 16; ++it) x[it] = pn[it * 64 + l];
+#pragma unroll
+                    for (int it = 0; it < 16; ++it) {
+                        pn[it * 64 + l] = make_ulonglong2(0ull, 0ull);
+                        pq[it * 64 + l] = x[it];
+                        actq |= x[it].x | x[it].y;
+                        pairs += __popcll(x[it].x) + __popcll(x[it].y);
+                    }
+                    return m;
+                }
+            }
             if (!m) return 0u;
             clear_marks(a.nany + 32ull * w);
             if (__popc(m) >= 8) {
@@ -1100,7 +1127,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
                     by_width([&](auto B) {
                         constexpr int W = decltype(B)::value;
                         hipLaunchKernelGGL(compact_kernel<BsMarks<W>>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, s, a.R,
-                                           n, nwords, cg.wpt, BsMarks<W>{a, (uint32_t)G, cg.blocks}, a.q, chunk,
+                                           n, nwords, cg.wpt, BsMarks<W>{a, (uint32_t)G, cg.blocks, cg.wpt == 1u}, a.q, chunk,
                                            status, &a.ctl->parity, &a.ctl->err);
                     });
                 });
@@ -1374,7 +1401,7 @@ struct BsSession final : LaneSession {
         hipLaunchKernelGGL((bsssp_relax<1024, 32>), dim3(G), dim3(GFR_BLOCK), 0, stream, a);
         if (pull) hipLaunchKernelGGL((bsssp_pull<1024, 32>), dim3(G), dim3(GFR_BLOCK), 0, stream, a);
         hipLaunchKernelGGL(compact_kernel<BsMarks<32>>, dim3(cg.blocks), dim3(GFR_BLOCK), 0, stream, a.R, a.n,
-                           nwords, cg.wpt, BsMarks<32>{a, (uint32_t)G, cg.blocks}, a.q, 1024u, status,
+                           nwords, cg.wpt, BsMarks<32>{a, (uint32_t)G, cg.blocks, cg.wpt == 1u}, a.q, 1024u, status,
                            &a.ctl->parity, &a.ctl->err);
         GFR_LAUNCH_CHECK();
         GFR_HIP(hipMemcpyAsync(pin, a.ctl, sizeof(BsCtl), hipMemcpyDeviceToHost, stream));
