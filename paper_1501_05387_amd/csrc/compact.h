@@ -201,7 +201,8 @@ __device__ __forceinline__ uint32_t word_degrees(const int32_t *R, int32_t n, ui
 // offsets of its run with coalesced 16-byte loads into LDS and takes its
 // 33-entry slices from there (offset j at j + j/32, so that the lanes' slices
 // fall in different banks), instead of 33 offsets a lane 128 bytes apart.
-// Otherwise as word_degrees.  s_r: this wave's 2,113 LDS words.
+// Otherwise as word_degrees.  s_r: this wave's 2,113 LDS words (one run per
+// wave and launch).
 constexpr int COMPACT_RUN_LDS = 2 * 1024 + 64 + 1;
 
 __device__ __forceinline__ uint32_t run_degrees(const int32_t *R, int32_t n, uint32_t w, bool active, uint32_t &bits,
@@ -242,10 +243,6 @@ __device__ __forceinline__ uint32_t run_degrees(const int32_t *R, int32_t n, uin
                 }
                 prev = next;
             }
-            // the slices are read before the next run overwrites them
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             bits = keep;
             return sum;
         }
