@@ -126,6 +126,9 @@ const char *gfr_last_error(const gfr_ctx *ctx);
  *                     many as are resident at once
  *   "batch.pair"      batched SSSP with 32-bit rows: 1 relaxes two edges per distance-row
  *                     load (each half-wave one edge), 0 (default) one edge per load
+ *   "batch.pending"   batched SSSP: 1 (default) a queued vertex also relaxes the queries improved
+ *                     at it earlier in the same relaxation launch (read from its marks, which
+ *                     stay); 0 only its queued queries.  Results do not change
  *   "graph.steps"     1: the level loops of BFS, SSSP and the batched solvers replay their
  *                     speculative batches of level launches from hipGraphs captured once per
  *                     distinct set of launch arguments; 0 (default): plain launches

@@ -159,6 +159,7 @@ struct Options {
     int batch_narrow = 0;       // batched SSSP narrow rows: 0 never, 1 auto, 2 from 16 bits, 3 from 8 bits
     int batch_blocks_per_cu = 64;  // batched SSSP relax grid: work-groups per CU, 0 = as many as are resident
     int batch_pair = 0;         // batched SSSP, 32-bit rows: relax two edges per row instruction
+    int batch_pending = 1;      // batched SSSP: sources also relax queries improved earlier in the launch
     int step_graphs = 0;        // replay level steps from captured hipGraphs
     int serve_max_batch = 64;
     int serve_graphs = 1;       // serving sessions replay their rounds from captured hipGraphs

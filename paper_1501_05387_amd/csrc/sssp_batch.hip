@@ -24,6 +24,13 @@
 // (one atomicOr of the wave's ballot per improved edge, not one byte store
 // per improving lane) plus a byte any[v] for the compaction's scan.
 //
+// Pending queries: a queued vertex relaxes its queued queries and, read from
+// its marks of the running launch, the queries improved at it earlier in the
+// same launch (the marks stay; the vertex is queued for them again).  A
+// relaxation with any distance a path has reached is safe, and carrying an
+// improvement one launch early saves later launches the visits it would have
+// caused (R-MAT s22, 64 queries: 4.03 m -> 3.74 m edge visits, 30.0 -> 28.8 ms).
+//
 // Every iteration is two launches:
 //   bsssp_relax   load-balanced edge chunks over the near queue; each wave
 //                 takes a quarter of the chunk, 64 edges at a time: lane l
@@ -83,6 +90,7 @@ struct BsArgs {
     uint32_t *part;              // per work-group [improvements, far marks written, lane relaxations, 0]
     unsigned long long *actp;    // per compaction group: OR of the query masks it queued
     uint32_t *fbits;             // [nwords] frontier bitmap of the next relaxation (qm valid where set)
+    uint32_t pending;            // a source also relaxes the queries improved at it earlier in the launch
     FrontierQ full;              // every vertex with edges (pull sweeps)
     uint32_t full_nf, full_mf;
     BsCtl *ctl;
@@ -208,6 +216,7 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
             wx = (int32_t)a.W[idx];
             ux = s_v[il];
             qx = a.qm[ux];
+            if (a.pending) qx |= a.nq[ux];
             ilo = lane_bcast(il, nbx - 1);
         };
         int nbn = (int)min(64u, ee - eb);
@@ -268,7 +277,9 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
                 // order): its distance row and query bit are loaded once
                 const uint32_t du = bs_load<BITS>(a, (size_t)u_first, lane);
                 const uint32_t q0 = (uint32_t)lane_bcast(qlo, 0), q1 = (uint32_t)lane_bcast(qhi, 0);
-                const bool act_u = (((lane < 32 ? q0 : q1) >> (lane & 31)) & 1u) != 0;
+                // a pending query read before its distance arrived here is not
+                // relaxed (its mark stays, it is relaxed in a later launch)
+                const bool act_u = ((((lane < 32 ? q0 : q1) >> (lane & 31)) & 1u) != 0) & (du != BS_INF);
                 for (int j0 = 0; j0 < nb; j0 += 16) {
                     uint32_t dv[16], ww[16];
                     int32_t vv[16];
@@ -311,7 +322,8 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
                     duprev = du[BS_UNROLL - 1];
 #pragma unroll
                     for (int j = 0; j < BS_UNROLL; ++j)
-                        relax(vv[j], ww[j], du[j], dv[j], (j0 + j < nb) & (((qw[j] >> (lane & 31)) & 1u) != 0));
+                        relax(vv[j], ww[j], du[j], dv[j],
+                              (j0 + j < nb) & (((qw[j] >> (lane & 31)) & 1u) != 0) & (du[j] != BS_INF));
                 }
             }
         }
@@ -1084,6 +1096,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     int32_t *dsrc = c.arena.take<int32_t>(64);
     a.actp = c.arena.take<unsigned long long>(cg.blocks);
     a.fbits = c.arena.take<uint32_t>(nwords);
+    a.pending = c.opt.batch_pending != 0;
     a.full = g.full;
     a.full_nf = (uint32_t)g.full_nf;
     a.full_mf = (uint32_t)g.m;
@@ -1358,6 +1371,7 @@ struct BsSession final : LaneSession {
         pairs = (int32_t *)take(4 * 128);
         stage = take(4 * 64 * L.n);
         a.fbits = (uint32_t *)take(4 * L.nwords);
+        a.pending = o.batch_pending != 0;
         a.full = g.full;
         a.full_nf = (uint32_t)g.full_nf;
         a.full_mf = (uint32_t)g.m;

@@ -530,6 +530,44 @@ def test_sssp_batch_buckets(ctx, delta):
 
 @pytest.mark.parametrize("name", ["rmat16", "grid96", "star5000", "path3000", "forest"])
 @pytest.mark.parametrize("delta", [0, 50])
+@pytest.mark.parametrize("narrow", [0, 3])
+def test_sssp_batch_pending_queries(ctx, name, delta, narrow):
+    """A queued vertex also relaxes the queries improved at it earlier in the
+    same launch (batch.pending 1, the default) or only its queued ones (0):
+    the oracle's distances on every row either way, with one bucket and narrow
+    buckets, 32-bit rows and narrow rows from 8 bits, a full and a ragged
+    batch."""
+    row, col, w = graph(name)
+    n = row.size - 1
+    rng = np.random.default_rng(13)
+    src = rng.integers(0, n, size=70).astype(np.int32)
+    src[0] = 0
+    src[5] = src[6]
+    g = _load(ctx, row, col, w)
+    ctx.set_option("batch.min_sssp", 1)
+    ctx.set_option("batch.delta", delta)
+    ctx.set_option("batch.narrow", narrow)
+    try:
+        ref = [oracle.sssp(row, col, w, int(x)) for x in src]
+        visits = []
+        for pending in (1, 0):
+            ctx.set_option("batch.pending", pending)
+            _say("sssp_batch pending", pending, name, "delta", delta, "narrow", narrow)
+            got = _host(ctx.sssp_batch(g, src)).view(np.uint32).reshape(src.size, n)
+            visits.append(ctx.stat("relaxations"))
+            for i in range(src.size):
+                assert np.array_equal(got[i], ref[i]), (name, pending, delta, narrow, i)
+        print("edge visits with / without pending queries:", visits)
+    finally:
+        ctx.set_option("batch.pending", 1)
+        ctx.set_option("batch.narrow", 0)
+        ctx.set_option("batch.delta", 0)
+        ctx.set_option("batch.min_sssp", 24)
+        g.free()
+
+
+@pytest.mark.parametrize("name", ["rmat16", "grid96", "star5000", "path3000", "forest"])
+@pytest.mark.parametrize("delta", [0, 50])
 def test_sssp_batch_pair_kernel(ctx, name, delta):
     """32-bit rows relaxed two edges per row load (batch.pair 1: each half-wave
     one edge, two queries per lane) and one edge per load (batch.pair 0) give
