@@ -77,6 +77,16 @@ def bsssp_bytes(st: dict) -> float:
     return 16 * st["pair_entries"] + 12 * st["lane_relaxations"] + 8 * st["improvements"]
 
 
+def bsssp_floor_bytes(pairs: int, edges: int, queries: int) -> float:
+    """The SSSP work model at its floor (re-relaxation factor r = 1): every
+    reached (vertex, query) pair enters the frontier once (16 B), every edge
+    leaving it is relaxed once for that query (12 B) and every reached pair
+    other than a source is improved once (8 B).  Fixed by the solves' results
+    alone, so no schedule, re-relaxation or speculative relaxation is credited
+    with bytes."""
+    return 16 * pairs + 12 * edges + 8 * (pairs - queries)
+
+
 def bsssp_row_bytes(st: dict) -> float:
     """Bytes the batched layout moves per edge visit: column and weight (8 B)
     plus the target's whole 64-query distance row (256 B), plus 4 B per
@@ -291,6 +301,7 @@ def main():
     te_bfs = sum(int(deg[d2[i] >= 0].sum().item()) for i in range(args.sources))
     s2 = dist.view(args.sources, n)
     te_sssp = sum(int(deg[s2[i] != -1].sum().item()) for i in range(args.sources))
+    pairs_sssp = int((s2 != -1).sum().item())   # reached (vertex, query) pairs, sources included
 
     # timed steps; HIP events on the library's launch stream bracket every level
     # kernel inside them (profile.kernels), which gives the roofline figures
@@ -358,7 +369,8 @@ def main():
     ss = ss_acc
     ktimes = {k: tuple(v) for k, v in kacc.items()}
     kernels = {k: {"ms": v[0], "launches": v[1]} for k, v in ktimes.items()}
-    kernels["bsssp_relax"]["bytes"] = bsssp_bytes(ss)
+    kernels["bsssp_relax"]["bytes"] = bsssp_floor_bytes(pairs_sssp, te_sssp, args.sources) * args.steps
+    kernels["bsssp_relax"]["counted_bytes"] = bsssp_bytes(ss)
     kernels["bsssp_relax"]["row_layout_bytes"] = bsssp_row_bytes(ss)
     kernels["msbfs_level"]["bytes"] = msbfs_bytes(sb, n)
     for k in ("bsssp_relax", "msbfs_level"):
@@ -382,10 +394,16 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_source": traffic_src,
                 "bytes_per_launch": kd["bytes"] / kd["launches"],
-                "bytes_model": ("16 B per (vertex, query) frontier entry + 12 B per (edge, query) relaxation "
-                                "+ 8 B per improvement" if dom == "bsssp_relax" else "see msbfs_bytes"),
+                "bytes_model": ("SSSP work model at r = 1: 16 B per reached (vertex, query) pair + 12 B per "
+                                "(edge, query) leaving it + 8 B per improvement, per step over the step's "
+                                "launches" if dom == "bsssp_relax" else "see msbfs_bytes"),
                 "avg_launch_us": kd["ms"] / kd["launches"] * 1e3}
     if dom == "bsssp_relax":
+        # the same model over the entries, relaxations and improvements the
+        # kernel counted (re-relaxations and pending-query relaxations
+        # included; these share the row visit of the frontier's own lanes, so
+        # the figure can exceed the bytes that reach HBM)
+        roofline["counted_bytes_per_launch"] = kd["counted_bytes"] / kd["launches"]
         roofline["row_layout_bytes_per_launch"] = kd["row_layout_bytes"] / kd["launches"]
         # re-relaxation factor: (edge, query) relaxations over the edges the
         # queries reach (sum of reached degrees), the floor of one relaxation each
