@@ -129,6 +129,10 @@ const char *gfr_last_error(const gfr_ctx *ctx);
  *   "batch.pending"   batched SSSP: 1 (default) a queued vertex also relaxes the queries improved
  *                     at it earlier in the same relaxation launch (read from its marks, which
  *                     stay); 0 only its queued queries.  Results do not change
+ *   "batch.sparse"    batched SSSP with 32-bit rows and one edge per row load (batch.pair 0):
+ *                     a group of 64 queued edges each carrying at most this many queries
+ *                     (default 8) is relaxed one lane per edge, loading single distances
+ *                     instead of whole 64-query rows; 0 never.  Results do not change
  *   "graph.steps"     1: the level loops of BFS, SSSP and the batched solvers replay their
  *                     speculative batches of level launches from hipGraphs captured once per
  *                     distinct set of launch arguments; 0 (default): plain launches

@@ -348,6 +348,7 @@ static const OptKey kOptKeys[] = {
     {"batch.pull_alpha", 0, 1e6, true},  {"batch.narrow", 0, 3, true},
     {"batch.blocks_per_cu", 0, 64, true}, {"graph.steps", 0, 1, false},
     {"batch.pair", 0, 1, true},          {"batch.pending", 0, 1, true},
+    {"batch.sparse", 0, 64, true},
     {"advance.mapping", 0, 2, true},     {"advance.twc_threshold", 0, 2147483647.0, true},
     {"sssp.pull_alpha", 0, 1e6, true},
     {"bc.direction", 0, 2, true},
@@ -386,6 +387,7 @@ void option_set(Options &o, const std::string &key, double v)
     else if (key == "graph.steps") o.step_graphs = (int)v;
     else if (key == "batch.pair") o.batch_pair = (int)v;
     else if (key == "batch.pending") o.batch_pending = (int)v;
+    else if (key == "batch.sparse") o.batch_sparse = (int)v;
     else if (key == "advance.mapping") o.advance_mapping = (int)v;
     else if (key == "advance.twc_threshold") o.twc_threshold = (int)v;
     else if (key == "sssp.pull_alpha") o.sssp_pull_alpha = v;
@@ -429,6 +431,7 @@ static double option_get(const Options &o, const std::string &key)
     if (key == "graph.steps") return o.step_graphs;
     if (key == "batch.pair") return o.batch_pair;
     if (key == "batch.pending") return o.batch_pending;
+    if (key == "batch.sparse") return o.batch_sparse;
     if (key == "advance.mapping") return o.advance_mapping;
     if (key == "advance.twc_threshold") return o.twc_threshold;
     if (key == "sssp.pull_alpha") return o.sssp_pull_alpha;

@@ -160,6 +160,7 @@ struct Options {
     int batch_blocks_per_cu = 64;  // batched SSSP relax grid: work-groups per CU, 0 = as many as are resident
     int batch_pair = 0;         // batched SSSP, 32-bit rows: relax two edges per row instruction
     int batch_pending = 1;      // batched SSSP: sources also relax queries improved earlier in the launch
+    int batch_sparse = 8;       // batched SSSP: edge groups with at most this many queries per edge go lane = edge
     int step_graphs = 0;        // replay level steps from captured hipGraphs
     int serve_max_batch = 64;
     int serve_graphs = 1;       // serving sessions replay their rounds from captured hipGraphs

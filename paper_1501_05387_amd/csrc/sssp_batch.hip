@@ -29,7 +29,13 @@
 // same launch (the marks stay; the vertex is queued for them again).  A
 // relaxation with any distance a path has reached is safe, and carrying an
 // improvement one launch early saves later launches the visits it would have
-// caused (R-MAT s22, 64 queries: 4.03 m -> 3.74 m edge visits, 30.0 -> 28.8 ms).
+// caused (R-MAT s22, 64 queries: 4.03 m -> 3.74 m edge visits, 31.1 -> 30.0 ms).
+//
+// Sparse groups: a group of 64 edges whose edges each carry at most a few
+// queries (option, default 8) is relaxed with lane = edge, one query per turn,
+// loading 4-byte distances rather than 256-byte rows.  Such groups are most of
+// the second launch (the sources' neighbours) and of the tail launches (R-MAT
+// s22, 64 queries: 30.0 -> 28.0 ms per batch, the same visits).
 //
 // Every iteration is two launches:
 //   bsssp_relax   load-balanced edge chunks over the near queue; each wave
@@ -91,6 +97,8 @@ struct BsArgs {
     unsigned long long *actp;    // per compaction group: OR of the query masks it queued
     uint32_t *fbits;             // [nwords] frontier bitmap of the next relaxation (qm valid where set)
     uint32_t pending;            // a source also relaxes the queries improved at it earlier in the launch
+    uint32_t sparse;             // a group of 64 edges with at most this many queries per edge is relaxed
+                                 // lane = edge (32-bit rows; 0: never)
     FrontierQ full;              // every vertex with edges (pull sweeps)
     uint32_t full_nf, full_mf;
     BsCtl *ctl;
@@ -230,6 +238,42 @@ __global__ __launch_bounds__(GFR_BLOCK) void bsssp_relax(BsArgs a)
             if (e + 64 < ee) {
                 nbn = (int)min(64u, ee - (e + 64));
                 fetch(e + 64, nbn, vn, wn, un, qn);
+            }
+            if (BITS == 32 && a.sparse != 0u && !ballot(lane < nb && (uint32_t)__popcll(ql) > a.sparse)) {
+                // few queries per edge: lane l relaxes edge l for each of its
+                // queries in turn, loading single 4-byte distances instead
+                // of whole 256-byte rows (the turns that read words of one
+                // row find its lines in cache after the first)
+                unsigned long long rem = lane < nb ? ql : 0ull;
+                while (ballot(rem != 0ull)) {
+                    const bool has = rem != 0ull;
+                    const int qq = has ? __ffsll(rem) - 1 : 0;
+                    rem &= rem - 1ull;
+                    const uint32_t du = has ? a.D[(size_t)ul * 64 + qq] : BS_INF;
+                    const uint32_t dv = has ? a.D[(size_t)vl * 64 + qq] : 0u;
+                    // as in the row form: a pending query whose distance has
+                    // not arrived is skipped and keeps its mark
+                    const bool act = has & (du != BS_INF);
+                    const unsigned long long nd64 = (unsigned long long)du + (uint32_t)wl;
+                    const bool fits = nd64 < 0xFFFFFFFFull;
+                    const uint32_t nd = (uint32_t)nd64;
+                    const bool imp = act & fits & (nd < dv);
+                    unf |= act & !fits;
+                    nlr += act ? 1u : 0u;
+                    nimp += imp ? 1u : 0u;
+                    if (imp) {
+                        atomicMin(a.D + (size_t)vl * 64 + qq, nd);
+                        if (nd < hi) {
+                            atomicOr(a.nq + vl, 1ull << qq);
+                            a.nany[vl] = 1;
+                        } else {
+                            atomicOr(a.fq + vl, 1ull << qq);
+                            a.fany[vl] = 1;
+                        }
+                    }
+                    if (ballot(imp & (nd >= hi)) != 0ull && lane == 0) ++nfar;
+                }
+                continue;
             }
             const int32_t qlo = (int32_t)(uint32_t)ql, qhi = (int32_t)(uint32_t)(ql >> 32);
             // one relaxation of edge (u, v, w) for this lane's query; the test
@@ -1097,6 +1141,7 @@ void run_sssp_batch(Ctx &c, Graph &g, const int32_t *sources, int32_t k, uint32_
     a.actp = c.arena.take<unsigned long long>(cg.blocks);
     a.fbits = c.arena.take<uint32_t>(nwords);
     a.pending = c.opt.batch_pending != 0;
+    a.sparse = (uint32_t)c.opt.batch_sparse;
     a.full = g.full;
     a.full_nf = (uint32_t)g.full_nf;
     a.full_mf = (uint32_t)g.m;
@@ -1372,6 +1417,7 @@ struct BsSession final : LaneSession {
         stage = take(4 * 64 * L.n);
         a.fbits = (uint32_t *)take(4 * L.nwords);
         a.pending = o.batch_pending != 0;
+        a.sparse = (uint32_t)o.batch_sparse;
         a.full = g.full;
         a.full_nf = (uint32_t)g.full_nf;
         a.full_mf = (uint32_t)g.m;

@@ -568,6 +568,41 @@ def test_sssp_batch_pending_queries(ctx, name, delta, narrow):
 
 @pytest.mark.parametrize("name", ["rmat16", "grid96", "star5000", "path3000", "forest"])
 @pytest.mark.parametrize("delta", [0, 50])
+@pytest.mark.parametrize("pending", [1, 0])
+def test_sssp_batch_sparse_groups(ctx, name, delta, pending):
+    """Groups of edges with few queries each are relaxed one lane per edge
+    (batch.sparse): the oracle's distances on every row with every group in
+    that form (64), with a low threshold (2), the default (8) and none (0), with one
+    bucket and narrow buckets (far marks written lane by lane), a full and a
+    ragged batch."""
+    row, col, w = graph(name)
+    n = row.size - 1
+    rng = np.random.default_rng(17)
+    src = rng.integers(0, n, size=70).astype(np.int32)
+    src[0] = 0
+    src[5] = src[6]
+    g = _load(ctx, row, col, w)
+    ctx.set_option("batch.min_sssp", 1)
+    ctx.set_option("batch.delta", delta)
+    ctx.set_option("batch.pending", pending)
+    try:
+        ref = [oracle.sssp(row, col, w, int(x)) for x in src]
+        for sparse in (64, 2, 8, 0):
+            ctx.set_option("batch.sparse", sparse)
+            _say("sssp_batch sparse", sparse, name, "delta", delta, "pending", pending)
+            got = _host(ctx.sssp_batch(g, src)).view(np.uint32).reshape(src.size, n)
+            for i in range(src.size):
+                assert np.array_equal(got[i], ref[i]), (name, sparse, delta, pending, i)
+    finally:
+        ctx.set_option("batch.sparse", 8)
+        ctx.set_option("batch.pending", 1)
+        ctx.set_option("batch.delta", 0)
+        ctx.set_option("batch.min_sssp", 24)
+        g.free()
+
+
+@pytest.mark.parametrize("name", ["rmat16", "grid96", "star5000", "path3000", "forest"])
+@pytest.mark.parametrize("delta", [0, 50])
 def test_sssp_batch_pair_kernel(ctx, name, delta):
     """32-bit rows relaxed two edges per row load (batch.pair 1: each half-wave
     one edge, two queries per lane) and one edge per load (batch.pair 0) give
