@@ -266,19 +266,22 @@ def test_sssp_rejects_unweighted_and_overflow(ctx, frontier):
         g3 = _load(ctx, row3, col3, w3)
         got = _host(ctx.sssp(g3, 0)).view(np.uint32)
         assert got.tolist() == [0, 0x7FFFFFFF, 0xFFFFFFFE] == oracle.sssp(row3, col3, w3, 0).tolist()
-        # batched, with 32-bit rows and with narrow rows tried first
+        # batched, with 32-bit rows (whole rows and lane-per-edge groups) and
+        # with narrow rows tried first
         ctx.set_option("batch.min_sssp", 1)
-        for narrow in (0, 3):
+        for narrow, sparse in ((0, 0), (0, 8), (3, 8)):
             ctx.set_option("batch.narrow", narrow)
+            ctx.set_option("batch.sparse", sparse)
             src = np.array([0, 2, 1], np.int32)
             b = _host(ctx.sssp_batch(g3, src)).view(np.uint32).reshape(3, 3)
             for i in range(3):
-                assert np.array_equal(b[i], oracle.sssp(row3, col3, w3, int(src[i]))), (narrow, i)
+                assert np.array_equal(b[i], oracle.sssp(row3, col3, w3, int(src[i]))), (narrow, sparse, i)
             with pytest.raises(gfr.GfrError) as ei:
                 ctx.sssp_batch(g, np.array([0, 9], np.int32))
             assert ei.value.status == gfr.GFR_E_INVALID
         g3.free()
     finally:
+        ctx.set_option("batch.sparse", 8)
         ctx.set_option("sssp.frontier", 0)
         ctx.set_option("batch.min_sssp", 24)
         ctx.set_option("batch.narrow", 0)
