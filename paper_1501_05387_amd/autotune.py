@@ -11,8 +11,10 @@ The options it sweeps change only how a result is reached:
   (Sec. 4.5), as a multiple of the mean edge weight so that it carries over
   between graphs of one class;
 * ``msbfs.alpha`` and ``batch.delta_factor``: the same two choices for the
-  batched (64 sources at once) traversals, and ``batch.blocks_per_cu``, the
-  work-groups per CU of the batched relaxation's grid;
+  batched (64 sources at once) traversals, ``batch.blocks_per_cu``, the
+  work-groups per CU of the batched relaxation's grid, and ``batch.sparse``,
+  the most queries per edge with which a group of edges is relaxed one lane
+  per edge rather than one distance row per edge;
 * ``batch.min_bfs`` / ``batch.min_sssp``: the batch size from which one
   shared traversal beats sequential single-source solves.
 
@@ -52,6 +54,7 @@ SWEEP = {
     "msbfs.alpha": [1, 2, 4, 8, 16, 64],
     "batch.delta_factor": [0, 2, 8, 32],
     "batch.blocks_per_cu": [8, 16, 32, 64],
+    "batch.sparse": [0, 4, 8, 12],
 }
 QUICK = {
     "advance.chunk": [512, 2048],
@@ -61,6 +64,7 @@ QUICK = {
     "msbfs.alpha": [2, 16],
     "batch.delta_factor": [0, 8],
     "batch.blocks_per_cu": [16, 64],
+    "batch.sparse": [0, 8],
 }
 CROSSOVER_K = [2, 4, 8, 16, 32, 48]
 SINGLE_SOURCES = 4          # sources timed per graph for the single-source solvers
@@ -68,7 +72,7 @@ SINGLE_SOURCES = 4          # sources timed per graph for the single-source solv
 DEFAULTS = {
     "advance.chunk": 1024, "bfs.alpha": 15, "bfs.beta": 18, "sssp.delta_factor": 2,
     "msbfs.alpha": 4, "batch.delta_factor": 0, "batch.min_bfs": 8, "batch.min_sssp": 24,
-    "batch.blocks_per_cu": 64,
+    "batch.blocks_per_cu": 64, "batch.sparse": 8,
 }
 
 
@@ -211,7 +215,7 @@ class Tuner:
         opts = self._descend(cases, ["bfs_batch"], ["msbfs.alpha"], sweep, dict(opts, **{"batch.min_bfs": 1}),
                              k=kmax, rounds=1)
         if weighted:
-            opts = self._descend(cases, ["sssp_batch"], ["batch.delta_factor", "batch.blocks_per_cu"], sweep,
+            opts = self._descend(cases, ["sssp_batch"], ["batch.delta_factor", "batch.blocks_per_cu", "batch.sparse"], sweep,
                                  dict(opts, **{"batch.min_sssp": 1}), k=kmax, rounds=1)
         opts["batch.min_bfs"] = self._crossover(cases, "bfs_batch")
         if weighted:
