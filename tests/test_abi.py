@@ -167,3 +167,36 @@ def test_bench_traffic_digest_covers_existing_sources():
         assert os.path.basename(h) in covered, h
     assert len(bench.relax_source_digest()) == 16
     assert bench.relax_source_digest() != bench.kernel_source_digest()
+
+
+def test_bench_sssp_floor_bytes_counts_each_reached_pair_once():
+    """The batched relaxation's algorithmic bytes (the SSSP work model at
+    r = 1) equal, summed per query and per reached vertex, 16 B for its
+    frontier entry, 12 B per edge leaving it and 8 B for its improvement
+    (none for the query's own source), on oracle distances of a small graph
+    with an unreachable part."""
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import bench
+    import graphgen
+    import oracle
+    r1, c1 = graphgen.rmat(8)
+    n1 = r1.size - 1
+    # a second copy of the graph, never reached from sources in the first
+    row = np.concatenate([r1, r1[1:] + r1[-1]]).astype(r1.dtype)
+    col = np.concatenate([c1, c1 + n1]).astype(c1.dtype)
+    w = graphgen.weights(row, col, 64)
+    deg = np.diff(row)
+    srcs = [0, 3, 3, 17]
+    want, pairs, edges = 0, 0, 0
+    for s in srcs:
+        d = oracle.sssp(row, col, w, s)
+        for v in range(row.size - 1):
+            if d[v] != 0xFFFFFFFF:
+                want += 16 + 12 * int(deg[v]) + (8 if v != s else 0)
+        reached = d != 0xFFFFFFFF
+        pairs += int(reached.sum())
+        edges += int(deg[reached].sum())
+    assert pairs < len(srcs) * (row.size - 1)   # the copy stays unreached
+    assert bench.bsssp_floor_bytes(pairs, edges, len(srcs)) == want
